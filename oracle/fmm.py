@@ -1,0 +1,215 @@
+"""Step-by-step occ-FMM-K far field, complex128 (Theory section, Eqs. 11-18).
+
+Steps, in the paper's order:
+  1. AO multipoles O^{rs,X} of every pair about the centre X of its leaf, Eq. (8).
+  2. MO transforms, Eq. (15a,b):  O^{rj,X} = sum_s O^{rs,X} C_sj,
+     O^{ij,X} = sum_r O^{rj,X} C_ri  (the occupied-pair multipole, "Omega").
+  3. Upward pass, Eq. (17a) / (11):  O^{ij,Xp}_{lm} = sum O_{l-l',m-m'}(Xc-Xp) O^{ij,Xc}_{l'm'}.
+  4. Interaction lists, Eq. (17b) / (12):
+     Mloc^{ij}_{lm}(X) = (-1)^l sum M_{l+l',m+m'}(X-X') O^{ij,X'}_{l'm'}.
+  5. Downward pass, Eq. (17c) / (13):  Mloc_{lm}(Xc) = sum Mloc_{l'm'}(Xp) O_{l'-l,m'-m}(Xc-Xp)
+     (the printed M_{l'm'}(Xp) is read as the parent's local expansion).
+  6. K^ff_ri = 2 sum_X sum_j sum_lm O^{rj,X}_{lm} Mloc^{ij}_{lm}(X), Eq. (18) with the
+     factor 2 of Eq. (5) and the sum over leaf boxes X made explicit.
+
+Truncation: l <= L and l' <= L everywhere (the irregular harmonics are
+therefore needed to 2L).  Optional i and j ranges restrict the output
+columns and the summed occupied index.
+
+``far_K_direct`` evaluates the same truncated quantity without translations:
+for every far leaf pair it expands both pairs about the centres of the
+ancestors whose interaction lists contain each other and applies the M2L
+kernel once.  M2M is exact for multipoles truncated at L and L2L is an exact
+re-centring of a degree-L polynomial, so both must agree to rounding.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import harmonics as H
+from .basis import Functions, ao_multipoles, function_pairs
+from .tree import Tree
+
+
+def m2m_matrix(L: int, d: np.ndarray) -> np.ndarray:
+    """T[lm, l'm'] = O_{l-l', m-m'}(d), d = Xc - Xp (Eq. 11)."""
+    Od = H.regular(L, d)
+    Q = H.ncomp(L)
+    T = np.zeros((Q, Q), dtype=np.complex128)
+    for l in range(L + 1):
+        for m in range(-l, l + 1):
+            for lp in range(l + 1):
+                for mp in range(-lp, lp + 1):
+                    if abs(m - mp) <= l - lp:
+                        T[H.idx(l, m), H.idx(lp, mp)] = Od[H.idx(l - lp, m - mp)]
+    return T
+
+
+def m2l_matrix(L: int, R: np.ndarray) -> np.ndarray:
+    """T[lm, l'm'] = (-1)^l M_{l+l', m+m'}(R), R = X - X' (Eq. 12)."""
+    MR = H.irregular(2 * L, R)
+    Q = H.ncomp(L)
+    T = np.zeros((Q, Q), dtype=np.complex128)
+    for l in range(L + 1):
+        for m in range(-l, l + 1):
+            for lp in range(L + 1):
+                for mp in range(-lp, lp + 1):
+                    T[H.idx(l, m), H.idx(lp, mp)] = (-1) ** l * MR[H.idx(l + lp, m + mp)]
+    return T
+
+
+def l2l_matrix(L: int, d: np.ndarray) -> np.ndarray:
+    """T[lm, l'm'] = O_{l'-l, m'-m}(d), d = Xc - Xp (Eq. 13)."""
+    Od = H.regular(L, d)
+    Q = H.ncomp(L)
+    T = np.zeros((Q, Q), dtype=np.complex128)
+    for l in range(L + 1):
+        for m in range(-l, l + 1):
+            for lp in range(l, L + 1):
+                for mp in range(-lp, lp + 1):
+                    if abs(mp - m) <= lp - l:
+                        T[H.idx(l, m), H.idx(lp, mp)] = Od[H.idx(lp - l, mp - m)]
+    return T
+
+
+class Setup:
+    """Step 1: pairs, tree and the leaf AO multipoles (per geometry)."""
+
+    def __init__(self, system, params, nquad: int | None = None):
+        self.system, self.params = system, params
+        self.L = int(params.lmax)
+        self.fn = Functions(system)
+        self.r, self.s, self.P = function_pairs(system, self.fn, params.pair_log_thresh)
+        self.tree = Tree(self.P, params.split_mask, params.depth, params.ws)
+        t = self.tree
+        self.nleaf = len(t.boxes[t.depth])
+        self.leaf_pairs = [np.nonzero(t.pair_leaf == b)[0] for b in range(self.nleaf)]
+        self.leaf_funcs, self.leaf_O = [], []
+        Q = H.ncomp(self.L)
+        for b in range(self.nleaf):
+            k = self.leaf_pairs[b]
+            f = np.unique(np.concatenate([self.r[k], self.s[k]]))
+            loc = {int(v): n for n, v in enumerate(f)}
+            X = t.centre(t.depth, t.boxes[t.depth][b])
+            om = ao_multipoles(self.fn, self.r[k], self.s[k], X, self.L, nquad)
+            dense = np.zeros((Q, len(f), len(f)), dtype=np.complex128)
+            for n, kk in enumerate(k):
+                dense[:, loc[int(self.r[kk])], loc[int(self.s[kk])]] += om[n]
+            self.leaf_funcs.append(f)
+            self.leaf_O.append(dense)
+
+    @property
+    def nbasis(self) -> int:
+        return self.fn.n
+
+
+def _ranges(nocc, i_range, j_range):
+    i0, i1 = (0, nocc) if i_range is None else i_range
+    j0, j1 = (0, nocc) if j_range is None else j_range
+    return i0, i1, j0, j1
+
+
+def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int = 64,
+          return_imag: bool = False):
+    """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM."""
+    t, L = setup.tree, setup.L
+    nocc = C.shape[1]
+    i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
+    K = np.zeros((setup.nbasis, i1 - i0), dtype=np.complex128)
+    if t.lmin is None or j1 <= j0 or i1 <= i0:
+        return (K.real, 0.0) if return_imag else K.real
+    D = t.depth
+    # translation operators
+    up = {}
+    for lev in range(t.lmin + 1, D + 1):
+        for b, c in enumerate(t.boxes[lev]):
+            p = t.parent(lev, b)
+            up[(lev, b)] = m2m_matrix(L, t.centre(lev, c) - t.centre(lev - 1, t.boxes[lev - 1][p]))
+    down = {k: None for k in up}
+    for (lev, b) in up:
+        c = t.boxes[lev][b]
+        p = t.parent(lev, b)
+        down[(lev, b)] = l2l_matrix(L, t.centre(lev, c) - t.centre(lev - 1, t.boxes[lev - 1][p]))
+    m2l = {}
+    for lev in range(t.lmin, D + 1):
+        for b, c in enumerate(t.boxes[lev]):
+            for b2 in t.il[lev][b]:
+                m2l[(lev, b, b2)] = m2l_matrix(L, t.centre(lev, c) - t.centre(lev, t.boxes[lev][b2]))
+    for jb0 in range(j0, j1, jblock):
+        jb1 = min(j1, jb0 + jblock)
+        # Step 2: MO transforms at the leaves
+        Hb, Om = [], {D: []}
+        for b in range(setup.nleaf):
+            CB = C[setup.leaf_funcs[b]]
+            h = np.einsum("qrs,sj->qrj", setup.leaf_O[b], CB[:, jb0:jb1])        # O^{rj}
+            Hb.append(h)
+            Om[D].append(np.einsum("ri,qrj->qij", CB[:, i0:i1], h))             # O^{ij}
+        # Step 3: upward
+        for lev in range(D - 1, t.lmin - 1, -1):
+            acc = [np.zeros_like(Om[D][0]) for _ in t.boxes[lev]]
+            for b in range(len(t.boxes[lev + 1])):
+                p = t.parent(lev + 1, b)
+                acc[p] += np.tensordot(up[(lev + 1, b)], Om[lev + 1][b], axes=(1, 0))
+            Om[lev] = acc
+        # Steps 4-5: interaction lists and downward
+        Ml = {}
+        for lev in range(t.lmin, D + 1):
+            cur = []
+            for b in range(len(t.boxes[lev])):
+                acc = np.zeros_like(Om[D][0])
+                for b2 in t.il[lev][b]:
+                    acc += np.tensordot(m2l[(lev, b, b2)], Om[lev][b2], axes=(1, 0))
+                if lev > t.lmin:
+                    p = t.parent(lev, b)
+                    acc += np.tensordot(down[(lev, b)], Ml[lev - 1][p], axes=(1, 0))
+                cur.append(acc)
+            Ml[lev] = cur
+        # Step 6: K^ff
+        for b in range(setup.nleaf):
+            K[setup.leaf_funcs[b]] += 2.0 * np.einsum("qrj,qij->ri", Hb[b], Ml[D][b])
+    if return_imag:
+        return K.real, float(np.abs(K.imag).max())
+    return K.real
+
+
+def far_K_direct(setup: Setup, C: np.ndarray, i_range=None, j_range=None, nquad=None):
+    """Same truncated K^ff from ancestor-centred expansions, one M2L per far leaf pair."""
+    t, L = setup.tree, setup.L
+    nocc = C.shape[1]
+    i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
+    K = np.zeros((setup.nbasis, i1 - i0), dtype=np.complex128)
+    if t.lmin is None:
+        return K.real
+    D = t.depth
+    cache = {}
+
+    def mult(leaf, lev):
+        key = (leaf, lev)
+        if key not in cache:
+            a = t.ancestor(lev, leaf)
+            X = t.centre(lev, t.boxes[lev][a])
+            k = setup.leaf_pairs[leaf]
+            f = setup.leaf_funcs[leaf]
+            loc = {int(v): n for n, v in enumerate(f)}
+            om = ao_multipoles(setup.fn, setup.r[k], setup.s[k], X, L, nquad)
+            dense = np.zeros((H.ncomp(L), len(f), len(f)), dtype=np.complex128)
+            for n, kk in enumerate(k):
+                dense[:, loc[int(setup.r[kk])], loc[int(setup.s[kk])]] += om[n]
+            cache[key] = (dense, X)
+        return cache[key]
+
+    for b1 in range(setup.nleaf):
+        for b2 in range(setup.nleaf):
+            lev = t.far_level(b1, b2)
+            if lev is None:
+                continue
+            O1, X1 = mult(b1, lev)
+            O2, X2 = mult(b2, lev)
+            C1, C2 = C[setup.leaf_funcs[b1]], C[setup.leaf_funcs[b2]]
+            h = np.einsum("qrs,sj->qrj", O1, C1[:, j0:j1])
+            om = np.einsum("ui,qtu->qti", C2[:, i0:i1], O2)
+            om = np.einsum("qti,tj->qij", om, C2[:, j0:j1])
+            T = m2l_matrix(L, X1 - X2)
+            Mloc = np.tensordot(T, om, axes=(1, 0))                         # (q, i, j)
+            K[setup.leaf_funcs[b1]] += 2.0 * np.einsum("qrj,qij->ri", h, Mloc)
+    return K.real

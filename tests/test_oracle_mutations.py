@@ -1,0 +1,47 @@
+"""Planted mistakes in the oracle (on the CPU) must be caught by the pins.
+
+Each case patches one oracle routine with a plausible error and checks that the
+corresponding pin (hierarchical == direct, or convergence to the point-charge
+limit) no longer holds.
+"""
+import numpy as np
+import pytest
+
+from oracle import fmm
+from oracle.exact import far_K_exact_s
+
+from conftest import rel
+
+
+def _hier_vs_direct(st, C):
+    return rel(fmm.far_K(st, C), fmm.far_K_direct(st, C))
+
+
+def test_transposed_m2m_is_caught(tiny, monkeypatch):
+    wl, C, st = tiny
+    orig = fmm.m2m_matrix
+    monkeypatch.setattr(fmm, "m2m_matrix", lambda L, d: orig(L, d).T.copy())
+    assert _hier_vs_direct(st, C) > 1e-3
+
+
+def test_l2l_wrong_displacement_sign_is_caught(tiny, monkeypatch):
+    wl, C, st = tiny
+    orig = fmm.l2l_matrix
+    monkeypatch.setattr(fmm, "l2l_matrix", lambda L, d: orig(L, -d))
+    assert _hier_vs_direct(st, C) > 1e-3
+
+
+def test_m2l_missing_parity_is_caught(tiny, monkeypatch):
+    wl, C, st = tiny
+    Kp = far_K_exact_s(st, C, "pc")
+    good = rel(fmm.far_K(st, C), Kp)
+    orig = fmm.m2l_matrix
+
+    def no_parity(L, R):
+        T = orig(L, R)
+        for l in range(L + 1):
+            T[l * l:(l + 1) * (l + 1)] *= (-1) ** l
+        return T
+    monkeypatch.setattr(fmm, "m2l_matrix", no_parity)
+    bad = rel(fmm.far_K(st, C), Kp)
+    assert good < 2e-2 and bad > 10 * good
