@@ -1,0 +1,198 @@
+/*
+ * occk — far-field occupied exchange K^ff_ri of occ-FMM-K on AMD MI355X (gfx950).
+ *
+ * Method: Le & Shiozaki, "Occupied-orbital fast multipole method for efficient
+ * exact exchange evaluation" (arXiv:1708.05353), Theory section:
+ *   K_ri = 2 sum_j (rj|ji)                                   Eq. (5)
+ *   O^{rj,X} = sum_s O^{rs,X} C_sj,  O^{ij,X} = sum_r O^{rj,X} C_ri   Eq. (15a,b)
+ *   upward / interaction-list / downward translations per (i,j)    Eq. (17a-c)
+ *   K^ff_ri = 2 sum_X sum_j sum_lm O^{rj,X}_lm Mloc^{ij}_lm(X)      Eq. (18)
+ * with the scaled solid harmonics of Eq. (4a,b), AO multipoles of Eq. (8)
+ * about the centre of the leaf box that holds each AO pair, and square
+ * truncation l, l' <= L.
+ *
+ * Conventions for every entry point
+ *   - Return value: OCCK_OK (0) or a negative OCCK_E* code; occk_last_error()
+ *     then returns a thread-local message.  No C++ exception crosses the ABI.
+ *   - All argument validation happens on the host before any HIP call.
+ *   - Pointers documented as "device" must be HIP device allocations on the
+ *     current device; "host" pointers are ordinary host memory.
+ *   - A tree handle is used from one host thread / one stream at a time.
+ */
+#ifndef OCCK_H
+#define OCCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCCK_ABI_VERSION 1
+
+enum {
+  OCCK_OK = 0,
+  OCCK_EINVAL = -1,      /* bad argument (null, out of range, inconsistent)   */
+  OCCK_ENOMEM = -2,      /* host or device allocation failed / over the cap   */
+  OCCK_EHIP = -3,        /* a HIP runtime call failed                          */
+  OCCK_EHANDLE = -4,     /* freed, forged or foreign handle                    */
+  OCCK_ENONFINITE = -5,  /* non-finite input where finite values are required  */
+  OCCK_ESTATE = -6       /* operation not valid in the handle's current state  */
+};
+
+/* arithmetic of the contractions (translation operators are always generated
+ * in FP64 and K is always accumulated in FP64) */
+enum { OCCK_PREC_FP64 = 0, OCCK_PREC_FP32 = 1, OCCK_PREC_BF16X3 = 2 };
+enum { OCCK_RANK_FIXED = 0, OCCK_RANK_LEARNED = 1 };
+
+/* Molecular system: atoms and uncontracted normalised Cartesian Gaussian
+ * primitive shells (l = 0 or 1).  Functions are numbered shell by shell; a p
+ * shell contributes x, y, z in that order.  Coordinates in bohr.  All arrays
+ * are host memory owned by the caller and only read during occk_build_tree. */
+typedef struct occk_system {
+  int32_t natoms;
+  const double* xyz;          /* [natoms*3] */
+  int32_t nshell;
+  const int32_t* shell_atom;  /* [nshell], 0 <= atom < natoms */
+  const int32_t* shell_l;     /* [nshell], 0 or 1 */
+  const double* shell_exp;    /* [nshell], > 0 */
+} occk_system;
+
+/* Box-tree parameters (Theory section: hierarchy, near/far split).
+ *   split_mask  bit0 x, bit1 y, bit2 z: dimensions that are subdivided
+ *   depth       number of subdivisions (2^depth boxes per split dimension), 1..12
+ *   ws          two boxes of one level are near iff the Chebyshev distance of
+ *               their integer indices is <= ws (0..4)
+ *   lmax        multipole rank L (0..8); l <= L and l' <= L
+ *   pair_log_thresh  keep an ordered shell pair iff (ab/(a+b))|A-B|^2 <= thresh
+ *               (+inf keeps every pair)
+ * Root box: over the split dimensions E = largest extent of the pair centres,
+ * delta = 0.05 E + 1, lo = min - 0.35 delta, width W = E + delta; a dimension
+ * that is not split is one layer centred on the midpoint of the pair centres.
+ * The interaction list of a box holds the non-near boxes of its level whose
+ * parents are near its parent; empty boxes are pruned. */
+typedef struct occk_tree_params {
+  int32_t split_mask;
+  int32_t depth;
+  int32_t ws;
+  int32_t lmax;
+  double pair_log_thresh;
+} occk_tree_params;
+
+typedef struct occk_tree occk_tree;
+typedef struct occk_selector occk_selector;
+
+#define OCCK_MAX_LEVELS 13
+
+typedef struct occk_tree_info_t {
+  int32_t nbasis;
+  int32_t lmax;
+  int32_t ncomp;               /* (L+1)^2 real components per box            */
+  int32_t depth;
+  int32_t lmin;                /* coarsest level with a non-empty interaction
+                                  list, -1 when there is no far field        */
+  int32_t nleaf;
+  int32_t nbox;                /* boxes on levels lmin..depth                */
+  int32_t boxes_per_level[OCCK_MAX_LEVELS];
+  int32_t il_per_level[OCCK_MAX_LEVELS];
+  int64_t n_il;                /* ordered interaction-list pairs, all levels */
+  int64_t n_edges;             /* parent-child edges between lmin and depth  */
+  int64_t npairs;              /* screened ordered AO function pairs         */
+  int64_t sum_nb;              /* sum over leaves of functions in the leaf   */
+  int64_t sum_nb2;             /* sum over leaves of nB^2                    */
+  int32_t max_nb;
+  int32_t n_ops;               /* translation operators generated per call   */
+  int64_t m2m_nnz;             /* structural nonzeros of one real-form M2M
+                                  (= L2L) operator                           */
+  double lo[3], width, mid[3];
+} occk_tree_info_t;
+
+typedef struct occk_far_opts {
+  int32_t precision;           /* OCCK_PREC_*                                  */
+  int32_t rank_mode;           /* OCCK_RANK_*; LEARNED needs selector         */
+  const occk_selector* selector;
+  int32_t jblock;              /* occupied j columns per batch, 0 = automatic */
+  int32_t accumulate;          /* 0: K[:, i0:i1] = K^ff, 1: K[:, i0:i1] += K^ff */
+} occk_far_opts;
+
+/* Returns OCCK_ABI_VERSION. */
+int32_t occk_abi_version(void);
+
+/* Thread-local message describing the last non-zero status; never NULL. */
+const char* occk_last_error(void);
+
+/* Step 1 of the method (per geometry, host only, no HIP call): screened AO
+ * pairs and their Gaussian-product centres, pair -> leaf assignment, the box
+ * levels, neighbour and interaction lists (Theory section), and the leaf AO
+ * multipole integrals of Eq. (8) in FP64 about each leaf centre.  Everything
+ * needed is copied; *out owns it.  Device memory is allocated lazily by the
+ * first occk_far_K.  Errors: EINVAL (bad system/params, a pair centre within
+ * 1e-8 h of a leaf boundary, a screening value within 1e-9 of the threshold),
+ * ENOMEM. */
+int32_t occk_build_tree(const occk_system* sys, const occk_tree_params* params, occk_tree** out);
+
+/* Frees host and device memory of the handle; NULL is accepted.  EHANDLE for
+ * a handle that is not live. */
+int32_t occk_free_tree(occk_tree* tree);
+
+/* Counts of the built tree (host only). */
+int32_t occk_tree_info(const occk_tree* tree, occk_tree_info_t* info);
+
+/* Host-side export for checking the tree against an independent one.
+ *   leaf_coords  [nleaf*3] int32 integer box indices of the leaves (level depth),
+ *                in the library's leaf order; may be NULL
+ *   il_level, il_target, il_source  [n_il] int32: level and the integer
+ *                box-index triples are not exported; instead target and source
+ *                are leaf-order-independent linear keys x + 4096 (y + 4096 z)
+ *                of the boxes at that level; may be NULL
+ *   pair_leaf    [npairs] int32 leaf index of each screened pair in the order
+ *                (shell a, shell b, function of a, function of b) with a, b
+ *                ascending; may be NULL */
+int32_t occk_tree_export(const occk_tree* tree, int32_t* leaf_coords, int32_t* il_level,
+                         int32_t* il_target, int32_t* il_source, int32_t* pair_leaf);
+
+/* Host copy of one leaf's data: its sorted function list (nb entries) and the
+ * dense real-form AO multipole block O[q][a][b] (q over (L+1)^2 real
+ * components: (l,0), then Re and Im of (l,m) for m = 1..l; a, b local
+ * function indices) about the leaf centre, Eq. (8).  Either output may be NULL.
+ * *nb receives the function count.  Host only. */
+int32_t occk_tree_leaf(const occk_tree* tree, int32_t leaf, int32_t* nb, int32_t* funcs, double* O);
+
+/* Far-field occupied exchange, Eqs. (15)-(18), on the GPU:
+ *   K[r, i] = 2 sum_{j in [j0,j1)} (rj|ji)_ff   for i in [i0, i1), all r
+ * C: device, row-major nbasis x ldc FP64, columns 0..nocc-1 are the occupied
+ *    orbitals (ldc >= nocc).  Only columns in [i0,i1) and [j0,j1) are read.
+ * K: device, row-major nbasis x ldk FP64 (ldk >= i1); columns outside
+ *    [i0,i1) are not touched.  K must not overlap C.
+ * opts: NULL means FP64, fixed rank, automatic j batching, overwrite.
+ * hip_stream: hipStream_t (NULL = default stream).  All work is enqueued
+ *    asynchronously on it; the caller synchronises.  The first call on a
+ *    handle uploads the tree and allocates the workspace (synchronous).
+ * Errors (before any device work): EINVAL for null/ill-formed arguments or
+ *    ranges (0 <= i0 <= i1 <= nocc, 0 <= j0 <= j1 <= nocc), EHANDLE, ESTATE
+ *    (LEARNED without a trained selector), ENOMEM (workspace beyond
+ *    OCCK_MAX_DEVICE_BYTES or hipMalloc failure), EHIP. */
+int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
+                   int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                   const occk_far_opts* opts, double* K, int64_t ldk, void* hip_stream);
+
+/* ---- diagnostics (not needed by callers of the method) ---- */
+
+/* Lane-layout probe of the FP64 MFMA used by the kernels: multiplies a 16x4
+ * one-hot A (1 at row ia, column ka) by a 4x16 one-hot B (1 at row ka, column
+ * jb) on the GPU and writes every lane's four accumulator values to
+ * host_out[64*4].  Synchronous.  EINVAL on out-of-range indices. */
+int32_t occk_debug_mfma_probe(int32_t ia, int32_t ka, int32_t jb, double* host_out);
+
+/* Copies a workspace buffer of the handle's last occk_far_K call to host
+ * memory after a device synchronisation: which = 0 translation operators,
+ * 1 half-transformed multipoles H, 2 box data (Omega then Mloc), 3 per-leaf K
+ * partials.  *count receives the element count; host may be NULL to query it.
+ * ESTATE before the first occk_far_K. */
+int32_t occk_debug_buffer(occk_tree* tree, int32_t which, double* host, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OCCK_H */

@@ -1,0 +1,260 @@
+// extern "C" entry points of libocck: argument validation, error reporting,
+// handle lifetime.  Host only; the GPU work lives in far_k.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <stdexcept>
+#include <unordered_set>
+
+#include "occk_internal.hpp"
+
+namespace occk {
+
+static thread_local std::string g_err = "";
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+static std::mutex g_mu;
+static std::unordered_set<const Tree*> g_live;
+
+static bool live(const Tree* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return t && g_live.count(t) && t->magic == kTreeMagic;
+}
+
+}  // namespace occk
+
+using namespace occk;
+
+#define OCCK_GUARD_BEGIN try {
+#define OCCK_GUARD_END                                             \
+  }                                                                \
+  catch (const std::invalid_argument& e) {                        \
+    set_error(e.what());                                           \
+    return OCCK_EINVAL;                                            \
+  }                                                                \
+  catch (const std::bad_alloc&) {                                  \
+    set_error("host allocation failed");                           \
+    return OCCK_ENOMEM;                                            \
+  }                                                                \
+  catch (const std::exception& e) {                                \
+    set_error(e.what());                                           \
+    return OCCK_EINVAL;                                            \
+  }                                                                \
+  catch (...) {                                                    \
+    set_error("unknown error");                                    \
+    return OCCK_EINVAL;                                            \
+  }
+
+extern "C" {
+
+int32_t occk_abi_version(void) { return OCCK_ABI_VERSION; }
+
+const char* occk_last_error(void) { return g_err.c_str(); }
+
+int32_t occk_build_tree(const occk_system* sys, const occk_tree_params* params, occk_tree** out) {
+  if (!out) {
+    set_error("out is NULL");
+    return OCCK_EINVAL;
+  }
+  *out = nullptr;
+  OCCK_GUARD_BEGIN
+  Tree* t = build_tree(sys, params);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_live.insert(t);
+  }
+  *out = reinterpret_cast<occk_tree*>(t);
+  return OCCK_OK;
+  OCCK_GUARD_END
+}
+
+int32_t occk_free_tree(occk_tree* tree) {
+  if (!tree) return OCCK_OK;
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_live.count(t) || t->magic != kTreeMagic) {
+      set_error("occk_free_tree: handle is not live");
+      return OCCK_EHANDLE;
+    }
+    g_live.erase(t);
+  }
+  device_free(t);
+  t->magic = 0;
+  delete t;
+  return OCCK_OK;
+}
+
+int32_t occk_tree_info(const occk_tree* tree, occk_tree_info_t* info) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_info: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!info) {
+    set_error("info is NULL");
+    return OCCK_EINVAL;
+  }
+  std::memset(info, 0, sizeof(*info));
+  const int D = t->params.depth;
+  info->nbasis = t->nbasis;
+  info->lmax = t->L;
+  info->ncomp = t->Q;
+  info->depth = D;
+  info->lmin = t->lmin;
+  info->nleaf = t->nleaf();
+  for (int lev = 0; lev <= D && lev < OCCK_MAX_LEVELS; ++lev) {
+    info->boxes_per_level[lev] = int32_t(t->boxes[lev].size());
+    info->il_per_level[lev] = int32_t(t->il_idx[lev].size());
+    info->n_il += int64_t(t->il_idx[lev].size());
+    if (t->lmin >= 0 && lev >= t->lmin) info->nbox += int32_t(t->boxes[lev].size());
+    if (t->lmin >= 0 && lev > t->lmin) info->n_edges += int64_t(t->boxes[lev].size());
+  }
+  info->npairs = int64_t(t->pairs.size());
+  for (const auto& f : t->leaf_funcs) {
+    info->sum_nb += int64_t(f.size());
+    info->sum_nb2 += int64_t(f.size()) * int64_t(f.size());
+    info->max_nb = std::max<int32_t>(info->max_nb, int32_t(f.size()));
+  }
+  info->n_ops = int32_t(t->ops.size());
+  info->m2m_nnz = t->m2m_nnz;
+  for (int d = 0; d < 3; ++d) {
+    info->lo[d] = t->lo[d];
+    info->mid[d] = t->mid[d];
+  }
+  info->width = t->W;
+  return OCCK_OK;
+}
+
+int32_t occk_tree_export(const occk_tree* tree, int32_t* leaf_coords, int32_t* il_level,
+                         int32_t* il_target, int32_t* il_source, int32_t* pair_leaf) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_export: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  const int D = t->params.depth;
+  if (leaf_coords)
+    for (size_t b = 0; b < t->boxes[D].size(); ++b)
+      for (int d = 0; d < 3; ++d) leaf_coords[3 * b + d] = t->boxes[D][b][d];
+  int64_t k = 0;
+  for (int lev = 0; lev <= D; ++lev) {
+    const auto& bx = t->boxes[lev];
+    for (size_t b = 0; b < bx.size(); ++b)
+      for (int32_t e = t->il_ptr[lev][b]; e < t->il_ptr[lev][b + 1]; ++e, ++k) {
+        const auto& c2 = bx[t->il_idx[lev][e]];
+        if (il_level) il_level[k] = lev;
+        if (il_target) il_target[k] = int32_t(coord_key(bx[b][0], bx[b][1], bx[b][2]));
+        if (il_source) il_source[k] = int32_t(coord_key(c2[0], c2[1], c2[2]));
+      }
+  }
+  if (pair_leaf)
+    for (size_t p = 0; p < t->pairs.size(); ++p) pair_leaf[p] = t->pairs[p].leaf;
+  return OCCK_OK;
+}
+
+int32_t occk_tree_leaf(const occk_tree* tree, int32_t leaf, int32_t* nb, int32_t* funcs, double* O) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_leaf: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (leaf < 0 || leaf >= t->nleaf()) {
+    set_error("leaf index out of range");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  const auto& f = t->leaf_funcs[leaf];
+  if (nb) *nb = int32_t(f.size());
+  if (funcs) std::copy(f.begin(), f.end(), funcs);
+  if (O) leaf_multipoles(*t, leaf, O);
+  return OCCK_OK;
+  OCCK_GUARD_END
+}
+
+int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
+                   int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
+                   void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_far_K: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!C || !K) {
+    set_error("occk_far_K: C and K must be non-NULL device pointers");
+    return OCCK_EINVAL;
+  }
+  if (nocc <= 0 || ldc < nocc) {
+    set_error("occk_far_K: need nocc > 0 and ldc >= nocc");
+    return OCCK_EINVAL;
+  }
+  if (!(0 <= i0 && i0 <= i1 && i1 <= nocc) || !(0 <= j0 && j0 <= j1 && j1 <= nocc)) {
+    set_error("occk_far_K: need 0 <= i0 <= i1 <= nocc and 0 <= j0 <= j1 <= nocc");
+    return OCCK_EINVAL;
+  }
+  if (ldk < i1 || ldk <= 0) {
+    set_error("occk_far_K: need ldk >= i1");
+    return OCCK_EINVAL;
+  }
+  if ((reinterpret_cast<uintptr_t>(C) | reinterpret_cast<uintptr_t>(K)) & 7) {
+    set_error("occk_far_K: C and K must be 8-byte aligned");
+    return OCCK_EINVAL;
+  }
+  {
+    const uintptr_t c0 = reinterpret_cast<uintptr_t>(C);
+    const uintptr_t c1 = c0 + uintptr_t(t->nbasis) * uintptr_t(ldc) * 8;
+    const uintptr_t k0 = reinterpret_cast<uintptr_t>(K);
+    const uintptr_t k1 = k0 + uintptr_t(t->nbasis) * uintptr_t(ldk) * 8;
+    if (c0 < k1 && k0 < c1) {
+      set_error("occk_far_K: K overlaps C");
+      return OCCK_EINVAL;
+    }
+  }
+  occk_far_opts o{};
+  if (opts) o = *opts;
+  if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X3) {
+    set_error("occk_far_K: unknown precision");
+    return OCCK_EINVAL;
+  }
+  if (o.rank_mode != OCCK_RANK_FIXED && o.rank_mode != OCCK_RANK_LEARNED) {
+    set_error("occk_far_K: unknown rank_mode");
+    return OCCK_EINVAL;
+  }
+  if (o.rank_mode == OCCK_RANK_LEARNED && !o.selector) {
+    set_error("occk_far_K: LEARNED rank mode needs a selector");
+    return OCCK_ESTATE;
+  }
+  if (o.jblock < 0) {
+    set_error("occk_far_K: jblock must be >= 0");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return far_K(t, C, ldc, nocc, i0, i1, j0, j1, &o, K, ldk, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_debug_mfma_probe(int32_t ia, int32_t ka, int32_t jb, double* host_out) {
+  if (!host_out || ia < 0 || ia > 15 || jb < 0 || jb > 15 || ka < 0 || ka > 3) {
+    set_error("occk_debug_mfma_probe: bad arguments");
+    return OCCK_EINVAL;
+  }
+  return debug_mfma_probe(ia, ka, jb, host_out);
+}
+
+int32_t occk_debug_buffer(occk_tree* tree, int32_t which, double* host, int64_t* count) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_debug_buffer: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (which < 0 || which > 3) {
+    set_error("occk_debug_buffer: which must be 0..3");
+    return OCCK_EINVAL;
+  }
+  return debug_buffer(t, which, host, count);
+}
+
+}  // extern "C"

@@ -1,0 +1,98 @@
+// Internal state of the occk library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/occk.h"
+
+namespace occk {
+
+constexpr uint32_t kTreeMagic = 0x6f63636bu;  // "occk"
+constexpr int kMaxL = 8;
+
+void set_error(const std::string& msg);
+
+struct Func {
+  double c[3];
+  double exp;
+  double norm;
+  int pw[3];   // Cartesian powers (0/1)
+};
+
+// One screened ordered AO function pair.
+struct Pair {
+  int32_t r, s;
+  double P[3];
+  int32_t leaf;
+};
+
+// Translation operator description; the matrix itself is generated on the GPU.
+enum OpType : int32_t { kOpM2M = 0, kOpL2L = 1, kOpM2L = 2 };
+struct OpDesc {
+  int32_t type;
+  int32_t weighted;   // rows scaled by the L2P weights (leaf-level L2L/M2L)
+  double d[3];        // displacement: Xc - Xp (M2M/L2L) or X - X' (M2L)
+};
+
+struct DeviceState;   // defined in the HIP translation unit
+
+struct Tree {
+  uint32_t magic = kTreeMagic;
+  occk_tree_params params{};
+  int L = 0, Q = 0, nbasis = 0, ndim = 0;
+  std::vector<Func> funcs;
+  std::vector<Pair> pairs;
+  double lo[3]{}, mid[3]{}, W = 0;
+  int lmin = -1;
+  // boxes[level] = sorted integer coordinates (x, y, z)
+  std::vector<std::vector<std::array<int32_t, 3>>> boxes;
+  std::vector<std::unordered_map<int64_t, int32_t>> index;
+  // interaction lists per level: CSR over the boxes of that level
+  std::vector<std::vector<int32_t>> il_ptr, il_idx;
+  // leaves
+  std::vector<std::vector<int32_t>> leaf_funcs;   // sorted function indices
+  std::vector<std::vector<int32_t>> leaf_pairs;   // indices into pairs
+  // operators
+  std::vector<OpDesc> ops;
+  std::vector<int32_t> op_up;     // [level][octant] -> op (M2M), -1 if unused
+  std::vector<int32_t> op_down;   // [level][octant] -> op (L2L)
+  // M2L op per (level, displacement key)
+  std::vector<std::unordered_map<int64_t, int32_t>> op_m2l;
+  int64_t m2m_nnz = 0;
+
+  DeviceState* dev = nullptr;
+
+  double h(int level) const { return W / double(int64_t(1) << level); }
+  int nsplit() const { return ndim; }
+  void centre(int level, const std::array<int32_t, 3>& c, double out[3]) const;
+  int32_t parent(int level, int32_t box) const;
+  int nleaf() const { return int(boxes.back().size()); }
+};
+
+inline int64_t coord_key(int32_t x, int32_t y, int32_t z) {
+  return int64_t(x) + 4096 * (int64_t(y) + 4096 * int64_t(z));
+}
+
+// Real form: component (l,0) -> l*l, Re(l,m) -> l*l+2m-1, Im(l,m) -> l*l+2m.
+inline int rq0(int l) { return l * l; }
+inline int rqre(int l, int m) { return l * l + 2 * m - 1; }
+inline int rqim(int l, int m) { return l * l + 2 * m; }
+
+// Dense real-form AO multipole block of one leaf (Q x nb x nb), FP64, host.
+void leaf_multipoles(const Tree& t, int leaf, double* out);
+
+// Builds everything host-side; throws std::runtime_error / std::bad_alloc.
+Tree* build_tree(const occk_system* sys, const occk_tree_params* p);
+
+// Device side (far_k.hip)
+void device_free(Tree* t);
+int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
+              int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
+              void* stream);
+int32_t debug_mfma_probe(int ia, int ka, int jb, double* host_out);
+int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);
+
+}  // namespace occk

@@ -1,0 +1,236 @@
+"""Thin ctypes binding of libocck (include/occk.h).  Argument marshalling only:
+every step of the far-field exchange runs in the library's HIP kernels.
+PyTorch provides device memory and streams."""
+from __future__ import annotations
+
+import ctypes as ct
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libocck.so")
+
+OK, EINVAL, ENOMEM, EHIP, EHANDLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+RANK_FIXED, RANK_LEARNED = 0, 1
+MAX_LEVELS = 13
+
+
+class OcckError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"occk error {code}: {msg}")
+        self.code = code
+
+
+class _System(ct.Structure):
+    _fields_ = [("natoms", ct.c_int32), ("xyz", ct.POINTER(ct.c_double)),
+                ("nshell", ct.c_int32), ("shell_atom", ct.POINTER(ct.c_int32)),
+                ("shell_l", ct.POINTER(ct.c_int32)), ("shell_exp", ct.POINTER(ct.c_double))]
+
+
+class _Params(ct.Structure):
+    _fields_ = [("split_mask", ct.c_int32), ("depth", ct.c_int32), ("ws", ct.c_int32),
+                ("lmax", ct.c_int32), ("pair_log_thresh", ct.c_double)]
+
+
+class _Info(ct.Structure):
+    _fields_ = [("nbasis", ct.c_int32), ("lmax", ct.c_int32), ("ncomp", ct.c_int32),
+                ("depth", ct.c_int32), ("lmin", ct.c_int32), ("nleaf", ct.c_int32),
+                ("nbox", ct.c_int32), ("boxes_per_level", ct.c_int32 * MAX_LEVELS),
+                ("il_per_level", ct.c_int32 * MAX_LEVELS), ("n_il", ct.c_int64),
+                ("n_edges", ct.c_int64), ("npairs", ct.c_int64), ("sum_nb", ct.c_int64),
+                ("sum_nb2", ct.c_int64), ("max_nb", ct.c_int32), ("n_ops", ct.c_int32),
+                ("m2m_nnz", ct.c_int64), ("lo", ct.c_double * 3), ("width", ct.c_double),
+                ("mid", ct.c_double * 3)]
+
+
+class _Opts(ct.Structure):
+    _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
+                ("jblock", ct.c_int32), ("accumulate", ct.c_int32)]
+
+
+EXPORTS = {
+    "occk_abi_version": (ct.c_int32, []),
+    "occk_last_error": (ct.c_char_p, []),
+    "occk_build_tree": (ct.c_int32, [ct.POINTER(_System), ct.POINTER(_Params), ct.POINTER(ct.c_void_p)]),
+    "occk_free_tree": (ct.c_int32, [ct.c_void_p]),
+    "occk_tree_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(_Info)]),
+    "occk_tree_export": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                      ct.c_void_p]),
+    "occk_tree_leaf": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.c_void_p,
+                                    ct.c_void_p]),
+    "occk_far_K": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
+                                ct.c_int32, ct.c_int32, ct.POINTER(_Opts), ct.c_void_p, ct.c_int64,
+                                ct.c_void_p]),
+    "occk_debug_mfma_probe": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]),
+    "occk_debug_buffer": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(ct.c_int64)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libocck.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                              "`python -m paper_1708_05353_amd.build` (no CPU fallback exists)")
+        L = ct.CDLL(_LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise OcckError(code, lib().occk_last_error().decode())
+
+
+def _ptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(ct.POINTER(ctype))
+
+
+@dataclass
+class TreeInfo:
+    nbasis: int
+    lmax: int
+    ncomp: int
+    depth: int
+    lmin: int
+    nleaf: int
+    nbox: int
+    boxes_per_level: list
+    il_per_level: list
+    n_il: int
+    n_edges: int
+    npairs: int
+    sum_nb: int
+    sum_nb2: int
+    max_nb: int
+    n_ops: int
+    m2m_nnz: int
+    lo: tuple
+    width: float
+    mid: tuple
+
+
+class Tree:
+    """Handle of occk_build_tree (Step 1: pairs, boxes, lists, AO multipoles)."""
+
+    def __init__(self, system, params):
+        L = lib()
+        xyz = np.ascontiguousarray(system.xyz, dtype=np.float64)
+        sa = np.ascontiguousarray(system.shell_atom, dtype=np.int32)
+        sl = np.ascontiguousarray(system.shell_l, dtype=np.int32)
+        se = np.ascontiguousarray(system.shell_exp, dtype=np.float64)
+        s = _System(int(xyz.shape[0]), _ptr(xyz, ct.c_double), int(sl.shape[0]), _ptr(sa, ct.c_int32),
+                    _ptr(sl, ct.c_int32), _ptr(se, ct.c_double))
+        p = _Params(int(params.split_mask), int(params.depth), int(params.ws), int(params.lmax),
+                    float(params.pair_log_thresh))
+        h = ct.c_void_p()
+        _check(L.occk_build_tree(ct.byref(s), ct.byref(p), ct.byref(h)))
+        self._h = h
+        self.info = self._info()
+
+    def _info(self) -> TreeInfo:
+        inf = _Info()
+        _check(lib().occk_tree_info(self._h, ct.byref(inf)))
+        return TreeInfo(inf.nbasis, inf.lmax, inf.ncomp, inf.depth, inf.lmin, inf.nleaf, inf.nbox,
+                        list(inf.boxes_per_level)[: inf.depth + 1], list(inf.il_per_level)[: inf.depth + 1],
+                        inf.n_il, inf.n_edges, inf.npairs, inf.sum_nb, inf.sum_nb2, inf.max_nb, inf.n_ops,
+                        inf.m2m_nnz, tuple(inf.lo), inf.width, tuple(inf.mid))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        inf = self.info
+        leaf = np.zeros((inf.nleaf, 3), np.int32)
+        lev = np.zeros(inf.n_il, np.int32)
+        tgt = np.zeros(inf.n_il, np.int32)
+        src = np.zeros(inf.n_il, np.int32)
+        pl = np.zeros(inf.npairs, np.int32)
+        _check(lib().occk_tree_export(self._h, leaf.ctypes.data, lev.ctypes.data, tgt.ctypes.data,
+                                      src.ctypes.data, pl.ctypes.data))
+        return leaf, lev, tgt, src, pl
+
+    def leaf(self, b: int):
+        nb = ct.c_int32()
+        _check(lib().occk_tree_leaf(self._h, int(b), ct.byref(nb), None, None))
+        f = np.zeros(nb.value, np.int32)
+        O = np.zeros((self.info.ncomp, nb.value, nb.value))
+        _check(lib().occk_tree_leaf(self._h, int(b), ct.byref(nb), f.ctypes.data, O.ctypes.data))
+        return f, O
+
+    def debug_buffer(self, which: int) -> np.ndarray:
+        n = ct.c_int64()
+        _check(lib().occk_debug_buffer(self._h, int(which), None, ct.byref(n)))
+        out = np.zeros(n.value)
+        _check(lib().occk_debug_buffer(self._h, int(which), out.ctypes.data, ct.byref(n)))
+        return out
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _check(lib().occk_free_tree(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------
+    def flops(self, ni: int, nj: int) -> dict:
+        """Algorithmic flop counts of one occk_far_K call (paper-as-written,
+        all (j, i) columns carried through the translations)."""
+        inf = self.info
+        Q = inf.ncomp
+        nc = ni * nj
+        if inf.lmin < 0:
+            return dict(half=0, omega=0, m2m=0, m2l=0, l2l=0, l2p=0, total=0)
+        f = dict(
+            half=2 * Q * inf.npairs * nj,
+            omega=2 * Q * nj * ni * inf.sum_nb,
+            m2m=2 * inf.m2m_nnz * nc * inf.n_edges,
+            m2l=2 * Q * Q * nc * inf.n_il,
+            l2l=2 * inf.m2m_nnz * nc * inf.n_edges,
+            l2p=2 * Q * nj * ni * inf.sum_nb,
+        )
+        f["total"] = sum(f.values())
+        return f
+
+
+def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,
+          jblock: int = 0, accumulate: bool = False, stream=None):
+    """K[:, i0:i1] (+)= 2 sum_{j in [j0,j1)} (rj|ji)_ff on the GPU.
+
+    C: torch.float64 CUDA tensor (nbasis, ldc) row-major; K: torch.float64 CUDA
+    tensor (nbasis, ldk).  Asynchronous on ``stream`` (default: torch's current
+    stream)."""
+    import torch
+    nocc = int(C.shape[1])
+    i0, i1 = (0, nocc) if i_range is None else i_range
+    j0, j1 = (0, nocc) if j_range is None else j_range
+    for t in (C, K):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError("C and K must be row-major 2-D float64 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(C.device)
+    opts = _Opts(int(precision), RANK_FIXED, None, int(jblock), int(bool(accumulate)))
+    _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
+                            int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
+                            ct.c_void_p(stream.cuda_stream)))
+
+
+def debug_mfma_probe(ia: int, ka: int, jb: int) -> np.ndarray:
+    out = np.zeros((64, 4))
+    _check(lib().occk_debug_mfma_probe(int(ia), int(ka), int(jb), out.ctypes.data))
+    return out

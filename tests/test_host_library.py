@@ -1,0 +1,173 @@
+"""Host side of libocck (no GPU needed): exported symbols, argument
+validation and error codes, and parity of the library's tree and AO
+multipoles with the independent oracle."""
+import ctypes as ct
+import math
+import re
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import harmonics as H
+from oracle.fmm import Setup
+from paper_1708_05353_amd import occk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "occk.h")).read()
+    names = set(re.findall(r"\b(occk_[a-z_]+)\s*\(", hdr))
+    assert names, "no declarations found"
+    L = occk.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert L.occk_abi_version() == 1
+
+
+def _real_form(Oc, L):
+    Or = np.zeros(Oc.shape, dtype=np.float64)
+    for l in range(L + 1):
+        Or[l * l] = Oc[H.idx(l, 0)].real
+        for m in range(1, l + 1):
+            Or[l * l + 2 * m - 1] = Oc[H.idx(l, m)].real
+            Or[l * l + 2 * m] = Oc[H.idx(l, m)].imag
+    return Or
+
+
+@pytest.mark.parametrize("case", ["chain", "sheet", "water"])
+def test_tree_and_multipoles_match_oracle(case):
+    if case == "chain":
+        wl = workloads.tiny_chain()
+    elif case == "sheet":
+        wl = workloads.graphene_flake(n=2, lmax=4, nocc=12, depth=3)
+    else:
+        wl = workloads.water_cluster(20, 40, lmax=3)
+    tr = occk.Tree(wl.system, wl.params)
+    st = Setup(wl.system, wl.params)
+    ot = st.tree
+    leaf, lev, tgt, src, pl = tr.export()
+    assert [tuple(x) for x in leaf] == [tuple(x) for x in ot.boxes[ot.depth]]
+    assert np.array_equal(pl, ot.pair_leaf)
+    assert tr.info.lmin == ot.lmin
+    # interaction lists as sets of (level, target, source) keys
+    key = lambda c: c[0] + 4096 * (c[1] + 4096 * c[2])
+    ref = set()
+    for l in range(ot.depth + 1):
+        for b, lst in enumerate(ot.il[l]):
+            for b2 in lst:
+                ref.add((l, key(ot.boxes[l][b]), key(ot.boxes[l][b2])))
+    assert set(zip(lev.tolist(), tgt.tolist(), src.tolist())) == ref
+    L = wl.params.lmax
+    for b in range(tr.info.nleaf):
+        f, O = tr.leaf(b)
+        assert np.array_equal(f, st.leaf_funcs[b])
+        Or = _real_form(st.leaf_O[b], L)
+        assert np.abs(O - Or).max() <= 1e-12 * max(np.abs(Or).max(), 1e-300)
+
+
+def test_info_counts_tiny_chain():
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    inf = tr.info
+    assert (inf.nbasis, inf.nleaf, inf.n_il, inf.lmin) == (80, 8, 24, 2)
+    assert inf.il_per_level == [0, 0, 2, 22]
+    assert inf.npairs == 6400
+    assert inf.lo[0] == pytest.approx(-1.015) and inf.width / 8 == pytest.approx(5.1125)
+
+
+def _sys_struct(wl):
+    s = wl.system
+    keep = []
+    xyz = np.ascontiguousarray(s.xyz); keep.append(xyz)
+    sa = np.ascontiguousarray(s.shell_atom, np.int32); keep.append(sa)
+    sl = np.ascontiguousarray(s.shell_l, np.int32); keep.append(sl)
+    se = np.ascontiguousarray(s.shell_exp); keep.append(se)
+    st = occk._System(xyz.shape[0], occk._ptr(xyz, ct.c_double), len(sl), occk._ptr(sa, ct.c_int32),
+                      occk._ptr(sl, ct.c_int32), occk._ptr(se, ct.c_double))
+    return st, keep
+
+
+@pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 13), ("ws", -1), ("lmax", 9),
+                                         ("split_mask", 0), ("split_mask", 9), ("pair_log_thresh", -1.0)])
+def test_build_tree_rejects_bad_params(field, value):
+    wl = workloads.tiny_chain()
+    st, keep = _sys_struct(wl)
+    p = wl.params
+    pr = occk._Params(p.split_mask, p.depth, p.ws, p.lmax, p.pair_log_thresh)
+    setattr(pr, field, value)
+    h = ct.c_void_p()
+    code = occk.lib().occk_build_tree(ct.byref(st), ct.byref(pr), ct.byref(h))
+    assert code == occk.EINVAL
+    assert occk.lib().occk_last_error().decode()
+    assert not h.value
+
+
+def test_build_tree_rejects_bad_system():
+    wl = workloads.tiny_chain()
+    st, keep = _sys_struct(wl)
+    p = wl.params
+    pr = occk._Params(p.split_mask, p.depth, p.ws, p.lmax, p.pair_log_thresh)
+    keep[2][3] = 2          # d shell not supported
+    h = ct.c_void_p()
+    assert occk.lib().occk_build_tree(ct.byref(st), ct.byref(pr), ct.byref(h)) == occk.EINVAL
+    keep[2][3] = 0
+    keep[0][1, 0] = math.nan
+    assert occk.lib().occk_build_tree(ct.byref(st), ct.byref(pr), ct.byref(h)) == occk.EINVAL
+    assert occk.lib().occk_build_tree(None, ct.byref(pr), ct.byref(h)) == occk.EINVAL
+
+
+def test_far_K_validates_before_device_work():
+    """Every bad argument is rejected on the host; the fake device pointers are
+    never dereferenced (this runs without a GPU)."""
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    L = occk.lib()
+    C = ct.c_void_p(0x100000)
+    K = ct.c_void_p(0x900000)
+    f = lambda *a: L.occk_far_K(tr.handle, *a)
+    opts = occk._Opts(0, 0, None, 0, 0)
+    assert f(None, 20, 20, 0, 20, 0, 20, ct.byref(opts), K, 20, None) == occk.EINVAL
+    assert f(C, 10, 20, 0, 20, 0, 20, ct.byref(opts), K, 20, None) == occk.EINVAL   # ldc < nocc
+    assert f(C, 20, 20, 5, 3, 0, 20, ct.byref(opts), K, 20, None) == occk.EINVAL    # i0 > i1
+    assert f(C, 20, 20, 0, 21, 0, 20, ct.byref(opts), K, 21, None) == occk.EINVAL   # i1 > nocc
+    assert f(C, 20, 20, 0, 20, -1, 20, ct.byref(opts), K, 20, None) == occk.EINVAL
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(opts), K, 10, None) == occk.EINVAL   # ldk < i1
+    assert f(ct.c_void_p(0x100003), 20, 20, 0, 20, 0, 20, ct.byref(opts), K, 20, None) == occk.EINVAL
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(opts), ct.c_void_p(0x100000 + 800), 20, None) == occk.EINVAL
+    bad = occk._Opts(7, 0, None, 0, 0)
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(bad), K, 20, None) == occk.EINVAL
+    learned = occk._Opts(0, 1, None, 0, 0)
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(learned), K, 20, None) == occk.ESTATE
+    neg = occk._Opts(0, 0, None, -4, 0)
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(neg), K, 20, None) == occk.EINVAL
+
+
+def test_handles():
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    h = tr.handle.value
+    L = occk.lib()
+    assert L.occk_free_tree(None) == occk.OK
+    tr.free()
+    assert L.occk_free_tree(ct.c_void_p(h)) == occk.EHANDLE          # freed
+    inf = occk._Info()
+    assert L.occk_tree_info(ct.c_void_p(h), ct.byref(inf)) == occk.EHANDLE
+    fake = ct.create_string_buffer(4096)
+    assert L.occk_tree_info(ct.cast(fake, ct.c_void_p), ct.byref(inf)) == occk.EHANDLE  # forged
+
+
+def test_boundary_tie_is_an_error():
+    """A pair centre on a leaf boundary is ambiguous and rejected."""
+    import copy
+    s = copy.deepcopy(workloads.tiny_chain().system)
+    s.xyz = np.array([[0.0, 0, 0], [10.0, 0, 0], [5.225, 0, 0]])
+    s.shell_atom = np.array([0, 1, 2], np.int32)
+    s.shell_l = np.zeros(3, np.int32)
+    s.shell_exp = np.array([1.0, 1.0, 1.0])
+    p = workloads.TreeParams(1, 1, 0, 2, 1.0)
+    with pytest.raises(occk.OcckError) as e:
+        occk.Tree(s, p)
+    assert e.value.code == occk.EINVAL
