@@ -1,10 +1,16 @@
 """Far-field occupied exchange throughput on one MI355X.
 
 One step = one occk_far_K call: the whole hot path (operator generation,
-half and full MO transforms, upward/interaction-list/downward translations,
-L2P and the K reduction) on the alkane-chain workload (C400H802 stand-in:
-nbasis 9610, nocc 1601, 1-D tree of depth 8, ws 2, L = 2), inputs resident in
-HBM.  Prints one JSON line.
+half and full MO transforms, upward / interaction-list / downward
+translations, L2P and the K reduction) for all occupied i and j, on the
+alkane-chain workload (C400H802 stand-in: nbasis 9610, nocc 1601, 1-D tree of
+depth 8, ws 2, L = 2), inputs resident in HBM.  Prints one JSON line.
+
+value = algorithmic flops of one call / measured time (GFLOP/s).  The
+roofline object reports the dominant kernel class, timed with HIP events on
+the library's stream inside the timed region.  cpu_baseline times the FP64
+oracle on a bounded j sample of the same workload and scales it linearly in
+the number of j columns.
 """
 from __future__ import annotations
 
@@ -18,7 +24,58 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15 / 3.0}
+PEAK_FLOPS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15 / 3.0}
+PEAK_HBM = 8.0e12
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4}
+
+
+def class_costs(info, ni, nj, jb, prec):
+    """Algorithmic flops and bytes per call for each kernel class.
+
+    GEMMs: flops of the dense contractions the method performs (half transform
+    counted over the screened pairs).  Translations: flops of the dense M2L
+    and the structurally nonzero M2M/L2L entries; compulsory bytes = every
+    source box read once, every target box written once, per j batch."""
+    Q = info.ncomp
+    nc = ni * nj
+    s = ELEM_BYTES[prec]
+    nb = info.boxes_per_level
+    lmin, D = info.lmin, info.depth
+    nblk = -(-nj // jb)
+    ncol = jb * ni
+    up_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, D))
+    down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
+    z = info.m2m_nnz
+    return {
+        "half": (2 * Q * info.npairs * nj, (info.sum_nb2 * Q + info.sum_nb * nj * (1 + Q)) * s),
+        "omega": (2 * Q * nj * ni * info.sum_nb, (info.sum_nb * Q * nj + info.nleaf * Q * nc) * s),
+        "up": (2 * z * nc * info.n_edges, up_boxes * Q * ncol * s * nblk),
+        "down": (2 * Q * Q * nc * info.n_il + 2 * z * nc * info.n_edges, down_boxes * Q * ncol * s * nblk),
+        "l2p": (2 * Q * nj * ni * info.sum_nb, (info.nleaf * Q * nc + info.sum_nb * Q * nj) * s),
+        "reduce": (0, (info.sum_nb * ni + info.nbasis * ni) * 8),
+    }
+
+
+def cpu_baseline(wl, C, flops_total, nocc, jsample):
+    import numpy as np
+    from oracle.fmm import Setup, far_K as oracle_far_K
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    st = Setup(wl.system, wl.params)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle_far_K(st, C, j_range=(0, jsample))
+    t = time.perf_counter() - t0
+    t_full = t * nocc / jsample
+    return {"value": round(flops_total / t_full / 1e9, 4), "unit": "GFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"oracle far_K for j in [0,{jsample}) of {nocc} (all i): {t:.1f} s, scaled x{nocc / jsample:.1f} "
+                      f"(cost is linear in the j columns); oracle setup {t_setup:.0f} s excluded, as the tree build "
+                      f"is excluded on the GPU"}
 
 
 def main():
@@ -28,15 +85,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--lmax", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--jblock", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-j", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
-              "the path would shard over the output index i (see DESIGN.md).", file=sys.stderr)
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "split over the output index i is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import workloads
@@ -55,27 +112,57 @@ def main():
     Cd = torch.from_numpy(C).to(dev)
     K = torch.zeros((wl.system.nbasis, nocc), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
+    call = lambda: occk.far_K(tree, Cd, K, precision=prec, jblock=args.jblock, stream=stream)
     t0 = time.perf_counter()
-    occk.far_K(tree, Cd, K, precision=prec, stream=stream)     # uploads tree, allocates workspace
+    call()                      # uploads the tree and allocates the workspace
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
-    print(f"[bench] orbitals {t_orb:.1f}s tree {t_tree:.1f}s first call {t_first:.1f}s", file=sys.stderr,
-          flush=True)
+    print(f"[bench] orbitals {t_orb:.1f}s tree {t_tree:.1f}s first call {t_first:.1f}s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        occk.far_K(tree, Cd, K, precision=prec, stream=stream)
+        call()
     torch.cuda.synchronize()
+    jb = tree.workspace_jblock()
+    tree.profile(True)
+    tree.profile_read()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
-    for k in range(args.steps):
-        occk.far_K(tree, Cd, K, precision=prec, stream=stream)
+    for _ in range(args.steps):
+        call()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    prof = tree.profile_read()
+    tree.profile(False)
     ms = ev0.elapsed_time(ev1) / args.steps
     fl = tree.flops(nocc, nocc)
     value = fl["total"] / (ms * 1e-3) / 1e9
+    print(f"[bench] {ms:.2f} ms/step, {value:.0f} GFLOP/s", file=sys.stderr, flush=True)
+
+    costs = class_costs(tree.info, nocc, nocc, jb, args.precision)
+    breakdown = {}
+    for cls, (flops, nbytes) in costs.items():
+        t_ms, nl = prof[cls]
+        if t_ms <= 0:
+            continue
+        per_call_ms = t_ms / args.steps
+        breakdown[cls] = {"ms_per_step": round(per_call_ms, 3), "launches_per_step": nl // args.steps,
+                          "TFLOP/s": round(flops / (per_call_ms * 1e-3) / 1e12, 2),
+                          "GB/s": round(nbytes / (per_call_ms * 1e-3) / 1e9, 1)}
+    dom = max(breakdown, key=lambda c: breakdown[c]["ms_per_step"])
+    flops, nbytes = costs[dom]
+    t_dom = breakdown[dom]["ms_per_step"] * 1e-3
+    hbm_bound = nbytes / PEAK_HBM > flops / PEAK_FLOPS[args.precision]
+    if hbm_bound:
+        ach = nbytes / t_dom / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                "frac": round(ach / (PEAK_HBM / 1e9), 4), "traffic": None, "kernel": dom}
+    else:
+        ach = flops / t_dom / 1e12
+        pk = PEAK_FLOPS[args.precision] / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(pk, 1), "unit": "TFLOP/s",
+                "frac": round(ach / pk, 4), "traffic": None, "kernel": dom}
     out = {
         "metric": "far-field K_ri GFLOP/s",
         "value": round(value, 1),
@@ -89,12 +176,17 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"alkane chain C400H802 stand-in, nbasis 9610, nocc 1601, L={args.lmax}, "
-                               f"1-D depth 8, ws 2",
-                   "precision": args.precision, "flops_per_step": fl["total"],
-                   "pct_peak": round(100 * value * 1e9 / PEAK[args.precision], 2),
-                   "wall_s_timed": round(wall, 3)},
+        "config": {"workload": f"alkane chain (C400H802 stand-in): nbasis 9610, nocc 1601, L={args.lmax}, "
+                               f"1-D tree depth 8, ws 2; all i and j",
+                   "precision": args.precision, "jblock": jb, "flops_per_step": fl["total"],
+                   "pct_peak": round(100 * value * 1e9 / PEAK_FLOPS[args.precision], 2),
+                   "tree_build_s": round(t_tree, 2), "wall_s_timed": round(wall, 3)},
+        "roofline": roof,
+        "breakdown": breakdown,
     }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, C, fl["total"], nocc, args.cpu_sample_j)
     print(json.dumps(out), flush=True)
 
 

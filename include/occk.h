@@ -176,13 +176,43 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
                    int32_t i0, int32_t i1, int32_t j0, int32_t j1,
                    const occk_far_opts* opts, double* K, int64_t ldk, void* hip_stream);
 
+/* Workspace of the handle's last occk_far_K: the j batch width used (-1
+ * before the first call) and the device bytes held by the handle.  Either
+ * pointer may be NULL. */
+int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes);
+
+/* ---- per-kernel timing ---- */
+
+/* kernel classes of one occk_far_K call */
+enum {
+  OCCK_K_OPGEN = 0,   /* translation operators, FP64 recurrences              */
+  OCCK_K_HALF = 1,    /* H = O^B C_B[:, J]            Eq. (15a)                */
+  OCCK_K_OMEGA = 2,   /* Omega = C_B^T H               Eq. (15b)                */
+  OCCK_K_UP = 3,      /* all upward translation launches, Eq. (17a)            */
+  OCCK_K_DOWN = 4,    /* all interaction-list + downward launches, Eq. (17b,c) */
+  OCCK_K_L2P = 5,     /* per-leaf K partials, Eq. (18)                          */
+  OCCK_K_REDUCE = 6,  /* sum of the per-leaf partials into K                    */
+  OCCK_K_CONVERT = 7, /* operand conversion of the mixed-precision paths       */
+  OCCK_K_NCLASS = 8
+};
+
+/* While enabled, every occk_far_K on the handle records a HIP event pair on
+ * its stream around each kernel class (a small serialisation cost). */
+int32_t occk_profile_enable(occk_tree* tree, int32_t enable);
+
+/* Waits for the recorded events and returns, per class, the summed elapsed
+ * milliseconds ms[OCCK_K_NCLASS] and launch counts launches[OCCK_K_NCLASS]
+ * (either may be NULL) since the previous read; then clears them. */
+int32_t occk_profile_read(occk_tree* tree, double* ms, int64_t* launches);
+
 /* ---- diagnostics (not needed by callers of the method) ---- */
 
-/* Lane-layout probe of the FP64 MFMA used by the kernels: multiplies a 16x4
- * one-hot A (1 at row ia, column ka) by a 4x16 one-hot B (1 at row ka, column
- * jb) on the GPU and writes every lane's four accumulator values to
- * host_out[64*4].  Synchronous.  EINVAL on out-of-range indices. */
-int32_t occk_debug_mfma_probe(int32_t ia, int32_t ka, int32_t jb, double* host_out);
+/* Lane-layout probe of the MFMA instructions used by the kernels: multiplies a
+ * one-hot 16xK A (1 at row ia, column ka) by a one-hot Kx16 B (1 at row ka,
+ * column jb) on the GPU and writes every lane's four accumulator values to
+ * host_out[64*4].  kind 0: FP64 16x16x4 (ka < 4), 1: FP32 16x16x4 (ka < 4),
+ * 2: BF16 16x16x32 (ka < 32).  Synchronous.  EINVAL on out-of-range input. */
+int32_t occk_debug_mfma_probe(int32_t kind, int32_t ia, int32_t ka, int32_t jb, double* host_out);
 
 /* Copies a workspace buffer of the handle's last occk_far_K call to host
  * memory after a device synchronisation: which = 0 translation operators,

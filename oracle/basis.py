@@ -70,18 +70,19 @@ def shell_pairs(system, thresh: float):
 
 
 def function_pairs(system, fn: Functions, thresh: float):
-    """(r, s, P) for every ordered function pair of every kept shell pair."""
+    """(r, s, P) for every ordered function pair of every kept shell pair, in
+    the order (shell pair, function of the first shell, function of the second)."""
     s1, s2 = shell_pairs(system, thresh)
-    first = np.zeros(len(system.shell_l) + 1, dtype=np.int64)
-    first[1:] = np.cumsum(2 * np.asarray(system.shell_l) + 1)
-    rr, ss = [], []
-    for a, b in zip(s1, s2):
-        for r in range(first[a], first[a + 1]):
-            for s in range(first[b], first[b + 1]):
-                rr.append(r)
-                ss.append(s)
-    r = np.array(rr, dtype=np.int64)
-    s = np.array(ss, dtype=np.int64)
+    nf = 2 * np.asarray(system.shell_l, dtype=np.int64) + 1
+    first = np.zeros(len(nf) + 1, dtype=np.int64)
+    first[1:] = np.cumsum(nf)
+    na, nb = nf[s1], nf[s2]
+    cnt = na * nb
+    start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    k = np.arange(int(cnt.sum()), dtype=np.int64) - start       # index inside the shell pair
+    nbr = np.repeat(nb, cnt)
+    r = np.repeat(first[s1], cnt) + k // nbr
+    s = np.repeat(first[s2], cnt) + k % nbr
     ea, eb = fn.exp[r], fn.exp[s]
     P = (ea[:, None] * fn.center[r] + eb[:, None] * fn.center[s]) / (ea + eb)[:, None]
     return r, s, P

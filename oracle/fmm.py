@@ -92,9 +92,12 @@ class Setup:
             loc = {int(v): n for n, v in enumerate(f)}
             X = t.centre(t.depth, t.boxes[t.depth][b])
             om = ao_multipoles(self.fn, self.r[k], self.s[k], X, self.L, nquad)
-            dense = np.zeros((Q, len(f), len(f)), dtype=np.complex128)
-            for n, kk in enumerate(k):
-                dense[:, loc[int(self.r[kk])], loc[int(self.s[kk])]] += om[n]
+            dense = np.zeros((len(f), len(f), Q), dtype=np.complex128)
+            a = np.searchsorted(f, self.r[k])
+            b = np.searchsorted(f, self.s[k])
+            np.add.at(dense, (a, b), om)
+            dense = np.ascontiguousarray(dense.transpose(2, 0, 1))
+            del loc
             self.leaf_funcs.append(f)
             self.leaf_O.append(dense)
 
@@ -192,9 +195,10 @@ def far_K_direct(setup: Setup, C: np.ndarray, i_range=None, j_range=None, nquad=
             f = setup.leaf_funcs[leaf]
             loc = {int(v): n for n, v in enumerate(f)}
             om = ao_multipoles(setup.fn, setup.r[k], setup.s[k], X, L, nquad)
-            dense = np.zeros((H.ncomp(L), len(f), len(f)), dtype=np.complex128)
-            for n, kk in enumerate(k):
-                dense[:, loc[int(setup.r[kk])], loc[int(setup.s[kk])]] += om[n]
+            dense = np.zeros((len(f), len(f), H.ncomp(L)), dtype=np.complex128)
+            np.add.at(dense, (np.searchsorted(f, setup.r[k]), np.searchsorted(f, setup.s[k])), om)
+            dense = np.ascontiguousarray(dense.transpose(2, 0, 1))
+            del loc
             cache[key] = (dense, X)
         return cache[key]
 

@@ -236,12 +236,13 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
   OCCK_GUARD_END
 }
 
-int32_t occk_debug_mfma_probe(int32_t ia, int32_t ka, int32_t jb, double* host_out) {
-  if (!host_out || ia < 0 || ia > 15 || jb < 0 || jb > 15 || ka < 0 || ka > 3) {
+int32_t occk_debug_mfma_probe(int32_t kind, int32_t ia, int32_t ka, int32_t jb, double* host_out) {
+  const int kmax = kind == 2 ? 31 : 3;
+  if (!host_out || kind < 0 || kind > 2 || ia < 0 || ia > 15 || jb < 0 || jb > 15 || ka < 0 || ka > kmax) {
     set_error("occk_debug_mfma_probe: bad arguments");
     return OCCK_EINVAL;
   }
-  return debug_mfma_probe(ia, ka, jb, host_out);
+  return debug_mfma_probe(kind, ia, ka, jb, host_out);
 }
 
 int32_t occk_debug_buffer(occk_tree* tree, int32_t which, double* host, int64_t* count) {
@@ -255,6 +256,34 @@ int32_t occk_debug_buffer(occk_tree* tree, int32_t which, double* host, int64_t*
     return OCCK_EINVAL;
   }
   return debug_buffer(t, which, host, count);
+}
+
+int32_t occk_profile_enable(occk_tree* tree, int32_t enable) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_profile_enable: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  t->profile = enable ? 1 : 0;
+  return OCCK_OK;
+}
+
+int32_t occk_profile_read(occk_tree* tree, double* ms, int64_t* launches) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_profile_read: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  return profile_read(t, ms, launches);
+}
+
+int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_workspace_info: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  return workspace_info(t, jblock, bytes);
 }
 
 }  // extern "C"

@@ -433,6 +433,37 @@ struct DeviceState {
   DevBuf<GemmTile> t_half, t_omega, t_l2p;
   int n_half = 0, n_omega = 0, n_l2p = 0;
   size_t bytes = 0;
+  // profiling: (class, start, end) event pairs recorded on the call's stream
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;
+  std::vector<int64_t> launches;
+};
+
+struct ProfScope {   // records a start/end event pair around a group of launches
+  DeviceState* ds;
+  int cls;
+  hipStream_t st;
+  size_t idx;
+  int nlaunch;
+  ProfScope(DeviceState* d, bool on, int c, hipStream_t s, int n = 1) : ds(on ? d : nullptr), cls(c), st(s), nlaunch(n) {
+    if (!ds) return;
+    while (ds->ev_pool.size() < ds->ev_used + 2) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      ds->ev_pool.push_back(e);
+    }
+    idx = ds->ev_used;
+    ds->ev_used += 2;
+    HIP_OK(hipEventRecord(ds->ev_pool[idx], st));
+  }
+  ~ProfScope() {
+    if (!ds) return;
+    (void)hipEventRecord(ds->ev_pool[idx + 1], st);
+    ds->ev_class.push_back(cls);
+    if (ds->launches.size() < OCCK_K_NCLASS) ds->launches.assign(OCCK_K_NCLASS, 0);
+    ds->launches[cls] += nlaunch;
+  }
 };
 
 static size_t device_cap() {
@@ -690,6 +721,8 @@ void device_free(Tree* t) {
 }
 
 static void free_state(DeviceState* ds) {
+  for (hipEvent_t e : ds->ev_pool) (void)hipEventDestroy(e);
+  ds->ev_pool.clear();
   ds->O.free();
   ds->funcs.free();
   ds->opparam.free();
@@ -752,24 +785,46 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
     const int Q = t->Q;
     const int64_t ncol = int64_t(jb) * ni;
     const int64_t box_stride = int64_t(Q) * ncol;
-    hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p,
-                       t->L, Q);
-    HIP_OK(hipGetLastError());
+    const bool prof = t->profile != 0;
+    {
+      ProfScope ps(ds, prof, OCCK_K_OPGEN, st);
+      hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p,
+                         t->L, Q);
+      HIP_OK(hipGetLastError());
+    }
     const int nblk = (nj + jb - 1) / jb;
     for (int kb = 0; kb < nblk; ++kb) {
       const int64_t jstart = j0 + int64_t(kb) * jb;
-      hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
-                         ds->t_half.p, C, ldc, jstart, int64_t(j1), 0);
-      hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3(unsigned(ds->n_omega)), dim3(256), 0, st, ds->d_omega.p,
-                         ds->t_omega.p, C, ldc, int64_t(i0), int64_t(i1), 0);
-      for (const Pass& ps : ds->up) launch_translate(t, ps, ds->data.p, box_stride, ncol, ds->ops.p, st);
-      for (const Pass& ps : ds->down) launch_translate(t, ps, ds->data.p, box_stride, ncol, ds->ops.p, st);
-      hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_l2p)), dim3(256), 0, st, ds->d_l2p.p,
-                         ds->t_l2p.p, C, ldc, int64_t(0), int64_t(0), kb > 0 ? 1 : 0);
+      {
+        ProfScope ps(ds, prof, OCCK_K_HALF, st);
+        hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
+                           ds->t_half.p, C, ldc, jstart, int64_t(j1), 0);
+      }
+      {
+        ProfScope ps(ds, prof, OCCK_K_OMEGA, st);
+        hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3(unsigned(ds->n_omega)), dim3(256), 0, st, ds->d_omega.p,
+                           ds->t_omega.p, C, ldc, int64_t(i0), int64_t(i1), 0);
+      }
+      {
+        ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
+        for (const Pass& p : ds->up) launch_translate(t, p, ds->data.p, box_stride, ncol, ds->ops.p, st);
+      }
+      {
+        ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
+        for (const Pass& p : ds->down) launch_translate(t, p, ds->data.p, box_stride, ncol, ds->ops.p, st);
+      }
+      {
+        ProfScope ps(ds, prof, OCCK_K_L2P, st);
+        hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_l2p)), dim3(256), 0, st, ds->d_l2p.p,
+                           ds->t_l2p.p, C, ldc, int64_t(0), int64_t(0), kb > 0 ? 1 : 0);
+      }
       HIP_OK(hipGetLastError());
     }
-    hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
-                       ds->KB.p, int64_t(ni), ds->occ_ptr.p, ds->occ_row.p, K, ldk, i0, opts->accumulate);
+    {
+      ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
+      hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
+                         ds->KB.p, int64_t(ni), ds->occ_ptr.p, ds->occ_row.p, K, ldk, i0, opts->accumulate);
+    }
     HIP_OK(hipGetLastError());
   } catch (const HipError& e) {
     set_error(e.what());
@@ -785,23 +840,46 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
 // --------------------------------------------------------------------------
 // diagnostics
 // --------------------------------------------------------------------------
-// MFMA lane-layout probe: A[i][k] = 1 at (i,k) = (ia,ka) else 0 and B[k][j] = 1
-// at (kb,jb) gives D = e_ia e_jb^T when ka == kb; every lane stores its 4
-// outputs.  out: [64 lanes][4] doubles.
-__global__ void mfma_probe_kernel(double* out, int ia, int ka, int jb) {
+// MFMA lane-layout probe: a one-hot A (1 at row ia, column ka) times a
+// one-hot B (1 at row ka, column jb) gives D = e_ia e_jb^T; every lane stores
+// its accumulator values.  kind 0: v_mfma_f64_16x16x4f64 (A[i][k] in lane
+// i+16k), 1: v_mfma_f32_16x16x4f32 (same operand layout), 2:
+// v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i+16(k/8), element k%8; B[k][j]
+// in lane j+16(k/8), element k%8).  out: [64 lanes][4].
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__global__ void mfma_probe_kernel(double* out, int kind, int ia, int ka, int jb) {
   const int lane = threadIdx.x;
-  const double a = ((lane & 15) == ia && (lane >> 4) == ka) ? 1.0 : 0.0;
-  const double b = ((lane & 15) == jb && (lane >> 4) == ka) ? 1.0 : 0.0;
-  d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];
+  if (kind == 0) {
+    const double a = ((lane & 15) == ia && (lane >> 4) == ka) ? 1.0 : 0.0;
+    const double b = ((lane & 15) == jb && (lane >> 4) == ka) ? 1.0 : 0.0;
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];
+  } else if (kind == 1) {
+    const float a = ((lane & 15) == ia && (lane >> 4) == ka) ? 1.0f : 0.0f;
+    const float b = ((lane & 15) == jb && (lane >> 4) == ka) ? 1.0f : 0.0f;
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];
+  } else {
+    bf16x8 a, b;
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * (lane >> 4) + e;
+      a[e] = ((lane & 15) == ia && k == ka) ? (__bf16)1.0f : (__bf16)0.0f;
+      b[e] = ((lane & 15) == jb && k == ka) ? (__bf16)1.0f : (__bf16)0.0f;
+    }
+    f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[lane * 4 + r] = acc[r];
+  }
 }
 
-int32_t debug_mfma_probe(int ia, int ka, int jb, double* host_out) {
+int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out) {
   try {
     double* d = nullptr;
     HIP_OK(hipMalloc(&d, 256 * sizeof(double)));
-    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, 0, d, ia, ka, jb);
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, 0, d, kind, ia, ka, jb);
     HIP_OK(hipGetLastError());
     HIP_OK(hipMemcpy(host_out, d, 256 * sizeof(double), hipMemcpyDeviceToHost));
     HIP_OK(hipFree(d));
@@ -831,6 +909,43 @@ int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count) {
       set_error(e.what());
       return OCCK_EHIP;
     }
+  }
+  return OCCK_OK;
+}
+
+// Sums the recorded event pairs per kernel class (synchronises on them) and clears.
+int32_t profile_read(Tree* t, double* ms, int64_t* launches) {
+  for (int c = 0; c < OCCK_K_NCLASS; ++c) {
+    if (ms) ms[c] = 0.0;
+    if (launches) launches[c] = 0;
+  }
+  DeviceState* ds = t->dev;
+  if (!ds) return OCCK_OK;
+  try {
+    for (size_t k = 0; k < ds->ev_class.size(); ++k) {
+      HIP_OK(hipEventSynchronize(ds->ev_pool[2 * k + 1]));
+      float e = 0.f;
+      HIP_OK(hipEventElapsedTime(&e, ds->ev_pool[2 * k], ds->ev_pool[2 * k + 1]));
+      if (ms) ms[ds->ev_class[k]] += double(e);
+    }
+    if (launches && !ds->launches.empty())
+      for (int c = 0; c < OCCK_K_NCLASS; ++c) launches[c] = ds->launches[c];
+  } catch (const HipError& e) {
+    set_error(e.what());
+    return OCCK_EHIP;
+  }
+  ds->ev_class.clear();
+  ds->ev_used = 0;
+  ds->launches.assign(OCCK_K_NCLASS, 0);
+  return OCCK_OK;
+}
+
+int32_t workspace_info(Tree* t, int32_t* jblock, int64_t* bytes) {
+  DeviceState* ds = t->dev;
+  if (jblock) *jblock = ds ? ds->ws_jb : -1;
+  if (bytes) {
+    *bytes = 0;
+    if (ds) *bytes = int64_t(ds->bytes + (ds->H.n + ds->data.n + ds->KB.n) * sizeof(double) + ds->ops.n * sizeof(double));
   }
   return OCCK_OK;
 }

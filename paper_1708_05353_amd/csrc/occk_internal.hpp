@@ -64,6 +64,7 @@ struct Tree {
   int64_t m2m_nnz = 0;
 
   DeviceState* dev = nullptr;
+  int profile = 0;
 
   double h(int level) const { return W / double(int64_t(1) << level); }
   int nsplit() const { return ndim; }
@@ -92,7 +93,9 @@ void device_free(Tree* t);
 int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
               int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
               void* stream);
-int32_t debug_mfma_probe(int ia, int ka, int jb, double* host_out);
+int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);
 int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);
+int32_t profile_read(Tree* t, double* ms, int64_t* launches);
+int32_t workspace_info(Tree* t, int32_t* jblock, int64_t* bytes);
 
 }  // namespace occk

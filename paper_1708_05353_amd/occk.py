@@ -64,9 +64,14 @@ EXPORTS = {
     "occk_far_K": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
                                 ct.c_int32, ct.c_int32, ct.POINTER(_Opts), ct.c_void_p, ct.c_int64,
                                 ct.c_void_p]),
-    "occk_debug_mfma_probe": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]),
+    "occk_debug_mfma_probe": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]),
     "occk_debug_buffer": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(ct.c_int64)]),
+    "occk_workspace_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)]),
+    "occk_profile_enable": (ct.c_int32, [ct.c_void_p, ct.c_int32]),
+    "occk_profile_read": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
 }
+
+KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert"]
 
 _lib = None
 
@@ -176,6 +181,27 @@ class Tree:
         _check(lib().occk_debug_buffer(self._h, int(which), out.ctypes.data, ct.byref(n)))
         return out
 
+    def workspace_jblock(self) -> int:
+        jb = ct.c_int32()
+        nb = ct.c_int64()
+        _check(lib().occk_workspace_info(self._h, ct.byref(jb), ct.byref(nb)))
+        return jb.value
+
+    def workspace_bytes(self) -> int:
+        jb = ct.c_int32()
+        nb = ct.c_int64()
+        _check(lib().occk_workspace_info(self._h, ct.byref(jb), ct.byref(nb)))
+        return nb.value
+
+    def profile(self, enable: bool = True):
+        _check(lib().occk_profile_enable(self._h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), np.int64)
+        _check(lib().occk_profile_read(self._h, ms.ctypes.data, n.ctypes.data))
+        return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(KERNEL_CLASSES)}
+
     def free(self):
         if self._h is not None and self._h.value:
             _check(lib().occk_free_tree(self._h))
@@ -230,7 +256,7 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
                             ct.c_void_p(stream.cuda_stream)))
 
 
-def debug_mfma_probe(ia: int, ka: int, jb: int) -> np.ndarray:
+def debug_mfma_probe(kind: int, ia: int, ka: int, jb: int) -> np.ndarray:
     out = np.zeros((64, 4))
-    _check(lib().occk_debug_mfma_probe(int(ia), int(ka), int(jb), out.ctypes.data))
+    _check(lib().occk_debug_mfma_probe(int(kind), int(ia), int(ka), int(jb), out.ctypes.data))
     return out
