@@ -40,9 +40,16 @@ enum {
   OCCK_ESTATE = -6       /* operation not valid in the handle's current state  */
 };
 
-/* arithmetic of the contractions (translation operators are always generated
- * in FP64 and K is always accumulated in FP64) */
-enum { OCCK_PREC_FP64 = 0, OCCK_PREC_FP32 = 1, OCCK_PREC_BF16X3 = 2 };
+/* Arithmetic of the contractions.  Translation operators are always generated
+ * in FP64 (then rounded for the mixed modes) and the per-leaf K partials and K
+ * are always accumulated in FP64.
+ *   FP64    every contraction on FP64 MFMA
+ *   FP32    FP32 operands, FP32 MFMA, FP32 accumulation
+ *   BF16X3  half/Omega/L2P as split-BF16 products hi*hi + hi*lo + lo*hi with
+ *           FP32 accumulation (~2^-16 per product); translations on FP32 MFMA
+ *   BF16X6  three-way split, six products (~2^-24 per product); translations
+ *           on FP32 MFMA */
+enum { OCCK_PREC_FP64 = 0, OCCK_PREC_FP32 = 1, OCCK_PREC_BF16X3 = 2, OCCK_PREC_BF16X6 = 3 };
 enum { OCCK_RANK_FIXED = 0, OCCK_RANK_LEARNED = 1 };
 
 /* Molecular system: atoms and uncontracted normalised Cartesian Gaussian

@@ -144,9 +144,9 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
         Hb, Om = [], {D: []}
         for b in range(setup.nleaf):
             CB = C[setup.leaf_funcs[b]]
-            h = np.einsum("qrs,sj->qrj", setup.leaf_O[b], CB[:, jb0:jb1])        # O^{rj}
+            h = np.matmul(setup.leaf_O[b], CB[:, jb0:jb1])                      # O^{rj}_q = O^{rs}_q C_sj
             Hb.append(h)
-            Om[D].append(np.einsum("ri,qrj->qij", CB[:, i0:i1], h))             # O^{ij}
+            Om[D].append(np.matmul(CB[:, i0:i1].T, h))                           # O^{ij}_q = sum_r C_ri O^{rj}_q
         # Step 3: upward
         for lev in range(D - 1, t.lmin - 1, -1):
             acc = [np.zeros_like(Om[D][0]) for _ in t.boxes[lev]]
@@ -169,7 +169,8 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
             Ml[lev] = cur
         # Step 6: K^ff
         for b in range(setup.nleaf):
-            K[setup.leaf_funcs[b]] += 2.0 * np.einsum("qrj,qij->ri", Hb[b], Ml[D][b])
+            # sum_j sum_q O^{rj}_q Mloc^{ij}_q
+            K[setup.leaf_funcs[b]] += 2.0 * np.matmul(Hb[b], Ml[D][b].transpose(0, 2, 1)).sum(0)
     if return_imag:
         return K.real, float(np.abs(K.imag).max())
     return K.real

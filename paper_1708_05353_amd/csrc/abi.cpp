@@ -215,7 +215,7 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
   }
   occk_far_opts o{};
   if (opts) o = *opts;
-  if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X3) {
+  if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X6) {
     set_error("occk_far_K: unknown precision");
     return OCCK_EINVAL;
   }

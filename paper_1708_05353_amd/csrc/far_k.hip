@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "occk_internal.hpp"
@@ -43,13 +44,13 @@ struct HipError : std::runtime_error {
 // --------------------------------------------------------------------------
 // device-side descriptors
 // --------------------------------------------------------------------------
-struct GemmDesc {
-  const double* A;     // A(m,k) = A[m*sam + k*sak]
+struct GemmDesc {       // element types follow the kernel's mode (output: OutT)
+  const void* A;       // A(m,k) = A[m*sam + k*sak]
   int64_t sam, sak;
-  const double* B;     // B(k,n) = B[k*ldb + n]                (gidx == nullptr)
+  const void* B;       // B(k,n) = B[k*ldb + n]                (gidx == nullptr)
   int64_t ldb;
   const int32_t* gidx; // B(k,n) = Cuser[gidx[k]*ldcu + boff + n] (gather from C)
-  double* C;           // C(m,n) = C[m*ldc + n]
+  void* C;             // C(m,n) = C[m*ldc + n]
   int64_t ldc;
   int32_t M, N, K, pad;
 };
@@ -201,105 +202,247 @@ __global__ __launch_bounds__(64) void opgen_kernel(const OpParam* __restrict__ p
 }
 
 // --------------------------------------------------------------------------
-// grouped FP64 GEMM on MFMA 16x16x4: 64x64 output tile per 256-thread block,
-// each wave a 32x32 quadrant (2x2 MFMA tiles), K in steps of 16 through LDS.
-// MFMA layouts (v_mfma_f64_16x16x4f64): A[i][k] in lane i + 16k, B[k][j] in
-// lane j + 16k, D[i][j] in lane j + 16*(i%4), element i/4 (rows interleaved;
-// checked with occk_debug_mfma_probe).
+// arithmetic modes of the contractions
+//   kModeF64    FP64 operands, v_mfma_f64_16x16x4f64
+//   kModeF32    FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation
+//   kModeBF16x3 FP32 operands split as x = hi + lo (bf16 each, round to
+//               nearest even); a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//               v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// MFMA layouts (checked with occk_debug_mfma_probe):
+//   f64/f32 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+//   bf16 16x16x32: A[i][k] in lane i + 16(k/8) element k%8, B likewise;
+//   f64 D[i][j] in lane j + 16(i%4) element i/4 (rows interleaved),
+//   f32 D[i][j] in lane j + 16(i/4) element i%4.
 // --------------------------------------------------------------------------
-template <bool A_KCONTIG>
-__global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restrict__ descs,
-                                                       const GemmTile* __restrict__ tiles,
-                                                       const double* __restrict__ Cuser, int64_t ldcu,
-                                                       int64_t boff, int64_t blim, int accumulate) {
-  __shared__ double As[16][64 + 1];
-  __shared__ double Bs[16][64 + 1];
+//   kModeBF16x6 three-way split x = hi + mid + lo; six products
+//               (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid), ~2^-24 relative
+enum { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16x6 = 3 };
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+template <int MODE> struct ModeT;
+template <> struct ModeT<kModeF64> { using T = double; using Acc = d4; static constexpr int KT = 16; };
+template <> struct ModeT<kModeF32> { using T = float; using Acc = f4; static constexpr int KT = 16; };
+template <> struct ModeT<kModeBF16x3> { using T = float; using Acc = f4; static constexpr int KT = 32; };
+template <> struct ModeT<kModeBF16x6> { using T = float; using Acc = f4; static constexpr int KT = 32; };
+
+__device__ inline uint32_t bf16_rne_bits(float x) {   // bf16 bits (in the low half) of x, round to nearest even
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// x[e] -> hi[e] + lo[e] as bf16 vectors
+__device__ inline void split8(const float* x, bf16x8& hi, bf16x8& lo) {
+  s8v h, l;
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t hb = bf16_rne_bits(x[e]);
+    const float hf = __uint_as_float(hb << 16);
+    h[e] = short(hb);
+    l[e] = short(bf16_rne_bits(x[e] - hf));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// x[e] -> hi[e] + mid[e] + lo[e] as bf16 vectors
+__device__ inline void split8x3(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+  s8v h, m, l;
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t hb = bf16_rne_bits(x[e]);
+    const float r1 = x[e] - __uint_as_float(hb << 16);
+    const uint32_t mb = bf16_rne_bits(r1);
+    const float r2 = r1 - __uint_as_float(mb << 16);
+    h[e] = short(hb);
+    m[e] = short(mb);
+    l[e] = short(bf16_rne_bits(r2));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  mid = __builtin_bit_cast(bf16x8, m);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+__device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// output row of accumulator element r for lane group g = lane/16 inside a 16-row tile
+template <class Acc> __device__ inline int acc_row(int g, int r);
+template <> __device__ inline int acc_row<d4>(int g, int r) { return g + 4 * r; }
+template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; }
+
+// --------------------------------------------------------------------------
+// grouped GEMM: C(m,n) (+)= sum_k A(m,k) B(k,n) over a list of problems;
+// 64x64 output tile per 256-thread block, each wave a 32x32 quadrant (2x2
+// MFMA tiles), K staged through LDS in steps of KT.
+// --------------------------------------------------------------------------
+template <int MODE, bool A_KCONTIG, class OutT>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
+                                                   const GemmTile* __restrict__ tiles,
+                                                   const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
+                                                   int64_t boff, int64_t blim, int accumulate) {
+  using T = typename ModeT<MODE>::T;
+  using Acc = typename ModeT<MODE>::Acc;
+  constexpr int KT = ModeT<MODE>::KT;
+  constexpr int E = KT / 4;          // elements per thread per operand tile
+  __shared__ T As[KT][64 + 1];
+  __shared__ T Bs[KT][64 + 1];
   const GemmTile tl = tiles[blockIdx.x];
   const GemmDesc d = descs[tl.prob];
+  const T* A = static_cast<const T*>(d.A);
   const int m0 = tl.mt * 64, n0 = tl.nt * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  d4 acc[2][2];
+  Acc acc[2][2];
   for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-
-  // per-thread load coordinates
-  // A: k-contiguous -> thread loads row m = tid/4, k = (tid%4)*4 .. +3
-  //    m-contiguous -> thread loads k = tid/16, m = (tid%16)*4 .. +3
-  // B: thread loads k = tid/16, n = (tid%16)*4 .. +3
-  const int bk = tid >> 4, bn = (tid & 15) * 4;
-  double ra[4], rb[4];
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+  // FP32 accumulators feeding an FP64 output are flushed into FP64 registers
+  // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT terms.
+  constexpr bool kFlush = std::is_same<OutT, double>::value && MODE != kModeF64;
+  constexpr int FLUSH = 8;
+  double acc64[kFlush ? 2 : 1][kFlush ? 2 : 1][kFlush ? 4 : 1];
+  if constexpr (kFlush)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  int ktile = 0;
+  // A: k-contiguous -> row am = tid/4, k = (tid%4)*E ..; m-contiguous -> k = tid/(64/E), m = (tid%(64/E))*E ..
+  // B: k = tid/(64/E), n = (tid%(64/E))*E ..
+  constexpr int TPR = 64 / E;
+  const int bk = tid / TPR, bn = (tid % TPR) * E;
+  T ra[E], rb[E];
   auto load = [&](int k0) {
     if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * 4;
+      const int am = tid >> 2, ak = (tid & 3) * E;
       const int gm = m0 + am;
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < E; ++u) {
         const int gk = k0 + ak + u;
-        ra[u] = (gm < d.M && gk < d.K) ? d.A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : 0.0;
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
       }
     } else {
-      const int ak = tid >> 4, am = (tid & 15) * 4;
+      const int ak = tid / TPR, am = (tid % TPR) * E;
       const int gk = k0 + ak;
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < E; ++u) {
         const int gm = m0 + am + u;
-        ra[u] = (gm < d.M && gk < d.K) ? d.A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : 0.0;
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
       }
     }
     const int gk = k0 + bk;
     if (gk < d.K) {
       if (d.gidx) {
-        const double* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
-        for (int u = 0; u < 4; ++u) {
+        const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
+        for (int u = 0; u < E; ++u) {
           const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : 0.0;
+          rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
         }
       } else {
-        const double* row = d.B + int64_t(gk) * d.ldb;
-        for (int u = 0; u < 4; ++u) {
+        const T* row = static_cast<const T*>(d.B) + int64_t(gk) * d.ldb;
+        for (int u = 0; u < E; ++u) {
           const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N) ? row[gn] : 0.0;
+          rb[u] = (gn < d.N) ? row[gn] : T(0);
         }
       }
     } else {
-      for (int u = 0; u < 4; ++u) rb[u] = 0.0;
+      for (int u = 0; u < E; ++u) rb[u] = T(0);
     }
   };
   auto store = [&]() {
     if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * 4;
-      for (int u = 0; u < 4; ++u) As[ak + u][am] = ra[u];
+      const int am = tid >> 2, ak = (tid & 3) * E;
+      for (int u = 0; u < E; ++u) As[ak + u][am] = ra[u];
     } else {
-      const int ak = tid >> 4, am = (tid & 15) * 4;
-      for (int u = 0; u < 4; ++u) As[ak][am + u] = ra[u];
+      const int ak = tid / TPR, am = (tid % TPR) * E;
+      for (int u = 0; u < E; ++u) As[ak][am + u] = ra[u];
     }
-    for (int u = 0; u < 4; ++u) Bs[bk][bn + u] = rb[u];
+    for (int u = 0; u < E; ++u) Bs[bk][bn + u] = rb[u];
   };
 
   load(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  for (int k0 = 0; k0 < d.K; k0 += KT) {
     store();
     __syncthreads();
-    if (k0 + 16 < d.K) load(k0 + 16);
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a[2], b[2];
-      for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+    if (k0 + KT < d.K) load(k0 + KT);
+    if constexpr (MODE == kModeBF16x6) {
+      const int kb = 8 * (lane >> 4);
+      bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
+      for (int i = 0; i < 2; ++i) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
+        split8x3(x, ah[i], am[i], al[i]);
+      }
+      for (int j = 0; j < 2; ++j) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
+        split8x3(x, bh[j], bm[j], bl[j]);
+      }
       for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < 2; ++j) {   // smallest terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (MODE == kModeBF16x3) {
+      const int kb = 8 * (lane >> 4);
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+      for (int i = 0; i < 2; ++i) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
+        split8(x, ah[i], al[i]);
+      }
+      for (int j = 0; j < 2; ++j) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
+        split8(x, bh[j], bl[j]);
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T a[2], b[2];
+        for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+      }
     }
     __syncthreads();
+    if constexpr (kFlush) {
+      if (++ktile == FLUSH) {
+        ktile = 0;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
+            acc[i][j] = Acc{};
+          }
+      }
+    }
   }
+  if constexpr (kFlush)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
+  OutT* Cout = static_cast<OutT*>(d.C);
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn + j * 16 + (lane & 15);
       if (col >= d.N) continue;
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
         if (row >= d.M) continue;
-        double* c = d.C + int64_t(row) * d.ldc + col;
-        *c = accumulate ? *c + acc[i][j][r] : acc[i][j][r];
+        OutT* c = Cout + int64_t(row) * d.ldc + col;
+        OutT v;
+        if constexpr (kFlush) v = OutT(acc64[i][j][r]);
+        else v = OutT(acc[i][j][r]);
+        *c = accumulate ? *c + v : v;
       }
     }
 }
@@ -310,16 +453,16 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(const GemmDesc* __restric
 // holds MT 16-row tiles x 4 column tiles of accumulators.  Blocks are
 // renumbered so that each XCD walks contiguous (column tile, target) ranges:
 // neighbouring targets then share their sources in that XCD's L2.
+// T = double: FP64 MFMA; T = float: FP32 MFMA.
 // --------------------------------------------------------------------------
-template <int MT>
-__global__ __launch_bounds__(256) void translate_f64_kernel(double* __restrict__ data, int64_t box_stride,
-                                                            int64_t ncol, int Q, int KS,
-                                                            const int32_t* __restrict__ tgt_box,
-                                                            const int32_t* __restrict__ src_ptr,
-                                                            const int32_t* __restrict__ src_box,
-                                                            const int32_t* __restrict__ src_op,
-                                                            const double* __restrict__ ops, int ntgt,
-                                                            int64_t nblocks) {
+template <class T, int MT>
+__global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
+                                                        int Q, int KS, const int32_t* __restrict__ tgt_box,
+                                                        const int32_t* __restrict__ src_ptr,
+                                                        const int32_t* __restrict__ src_box,
+                                                        const int32_t* __restrict__ src_op,
+                                                        const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+  using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
@@ -327,37 +470,47 @@ __global__ __launch_bounds__(256) void translate_f64_kernel(double* __restrict__
   const int64_t ct = logical / ntgt;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t colbase = ct * 256 + wave * 64;
-  d4 acc[MT][4];
+  Acc acc[MT][4];
   for (int i = 0; i < MT; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
   const int64_t opsz = int64_t(MT) * KS * 64;
   const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
   for (int e = e0; e < e1; ++e) {
-    const double* X = data + int64_t(src_box[e]) * box_stride;
-    const double* T = ops + int64_t(src_op[e]) * opsz;
+    const T* X = data + int64_t(src_box[e]) * box_stride;
+    const T* Tm = ops + int64_t(src_op[e]) * opsz;
     for (int ks = 0; ks < KS; ++ks) {
       const int row = ks * 4 + (lane >> 4);
-      double b[4];
+      T b[4];
       for (int j = 0; j < 4; ++j) {
         const int64_t col = colbase + j * 16 + (lane & 15);
-        b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : 0.0;
+        b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : T(0);
       }
       for (int i = 0; i < MT; ++i) {
-        const double a = T[(int64_t(i) * KS + ks) * 64 + lane];
-        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[j], acc[i][j], 0, 0, 0);
+        const T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a, b[j], acc[i][j]);
       }
     }
   }
-  double* Y = data + int64_t(tgt_box[t]) * box_stride;
+  T* Y = data + int64_t(tgt_box[t]) * box_stride;
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 4; ++j) {
       const int64_t col = colbase + j * 16 + (lane & 15);
       if (col >= ncol) continue;
       for (int r = 0; r < 4; ++r) {
-        const int row = i * 16 + (lane >> 4) + 4 * r;
-        if (row < Q) Y[int64_t(row) * ncol + col] = acc[i][j][r];
+        const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
+        if (row < Q) Y[int64_t(row) * ncol + col] = T(acc[i][j][r]);
       }
     }
+}
+
+// out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
+__global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
+                                int64_t rows, int64_t cols) {
+  const int64_t n = rows * cols;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    out[r * ldo + c] = float(in[r * ldi + c]);
+  }
 }
 
 // K[r, i0 + i] = (acc ? K : 0) + sum_{e in occ(r)} KB[row_e, i]   (fixed order)
@@ -416,19 +569,23 @@ struct Pass {           // one translation launch
 struct DeviceState {
   int device = -1;
   // per tree
-  DevBuf<double> O;               // leaf AO multipole blocks
+  DevBuf<double> O;               // leaf AO multipole blocks (FP64)
+  DevBuf<float> Of;               // FP32 copy for the mixed paths (made on first use)
   std::vector<int64_t> O_off;     // per leaf, elements
   DevBuf<int32_t> funcs;          // concatenated leaf function lists
   std::vector<int64_t> f_off;     // per leaf
   DevBuf<OpParam> opparam;
-  DevBuf<double> ops;
+  DevBuf<double> ops;             // FP64 operators (always generated in FP64)
+  DevBuf<float> opsf;             // rounded copy for the mixed paths
   std::vector<Pass> up, down;     // up[k]: level depth-1-k ; down[k]: level lmin+k
   DevBuf<int32_t> occ_ptr, occ_row;
   int nbox = 0;                    // boxes on levels lmin..depth
   std::vector<int32_t> leaf_box;   // leaf -> box slot
-  // per workspace shape
-  int ws_jb = -1, ws_ni = -1;
-  DevBuf<double> H, data, KB;
+  // per workspace shape (j batch, n_i, precision)
+  int ws_jb = -1, ws_ni = -1, ws_prec = -1;
+  DevBuf<char> H, data;           // element type of the precision (double / float)
+  DevBuf<double> KB;              // per-leaf K partials, always FP64
+  DevBuf<float> Cf;               // FP32 copy of C for the mixed paths
   DevBuf<GemmDesc> d_half, d_omega, d_l2p;
   DevBuf<GemmTile> t_half, t_omega, t_l2p;
   int n_half = 0, n_omega = 0, n_l2p = 0;
@@ -611,37 +768,41 @@ static void tiles_for(std::vector<GemmTile>& tiles, int prob, int M, int N) {
     for (int nt = 0; nt < (N + 63) / 64; ++nt) tiles.push_back({prob, mt, nt, 0});
 }
 
-static void setup_workspace(Tree* t, int jb, int ni) {
+static void setup_workspace(Tree* t, int jb, int ni, int prec) {
   DeviceState* ds = t->dev;
-  if (ds->ws_jb == jb && ds->ws_ni == ni) return;
+  if (ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec) return;
   const int Q = t->Q, nl = t->nleaf();
+  const size_t es = prec == OCCK_PREC_FP64 ? 8 : 4;
   const int64_t sum_nb = ds->f_off[nl];
   const int64_t ncol = int64_t(jb) * ni;
-  const size_t need = size_t(sum_nb) * Q * jb * 8 + size_t(2) * ds->nbox * Q * size_t(ncol) * 8 +
+  const size_t need = size_t(sum_nb) * Q * jb * es + size_t(2) * ds->nbox * Q * size_t(ncol) * es +
                       size_t(sum_nb) * ni * 8;
   if (need + ds->bytes > device_cap()) throw std::bad_alloc();
   ds->ws_jb = -1;   // invalid until every buffer and descriptor is in place
   ds->ws_ni = -1;
+  ds->ws_prec = -1;
   ds->H.free();
   ds->data.free();
   ds->KB.free();
-  ds->H.alloc(size_t(sum_nb) * Q * jb);
-  ds->data.alloc(size_t(2) * ds->nbox * Q * size_t(ncol));
+  ds->H.alloc(size_t(sum_nb) * Q * jb * es);
+  ds->data.alloc(size_t(2) * ds->nbox * Q * size_t(ncol) * es);
   ds->KB.alloc(size_t(sum_nb) * ni);
   const int64_t box_stride = int64_t(Q) * ncol;
+  const char* Obase = prec == OCCK_PREC_FP64 ? reinterpret_cast<const char*>(ds->O.p)
+                                             : reinterpret_cast<const char*>(ds->Of.p);
   std::vector<GemmDesc> dh, dom, dl;
   std::vector<GemmTile> th, tom, tl2;
   for (int b = 0; b < nl; ++b) {
     const int nb = int(t->leaf_funcs[b].size());
-    const int64_t hoff = ds->f_off[b] * Q * jb;   // H^B[t][q][j], ld Q*jb
+    const int64_t hoff = ds->f_off[b] * Q * jb;   // H^B[t][q][j], ld Q*jb (elements)
     const int32_t* g = ds->funcs.p + ds->f_off[b];
     for (int q = 0; q < Q; ++q) {  // H_q = O^B_q C_B[:, J]
       GemmDesc d{};
-      d.A = ds->O.p + ds->O_off[b] + int64_t(q) * nb * nb;
+      d.A = Obase + (ds->O_off[b] + int64_t(q) * nb * nb) * es;
       d.sam = nb;
       d.sak = 1;
       d.gidx = g;
-      d.C = ds->H.p + hoff + int64_t(q) * jb;
+      d.C = ds->H.p + (hoff + int64_t(q) * jb) * es;
       d.ldc = int64_t(Q) * jb;
       d.M = nb;
       d.N = jb;
@@ -651,11 +812,11 @@ static void setup_workspace(Tree* t, int jb, int ni) {
     }
     {  // Omega[(q,j), i] = sum_t H[t][(q,j)] C[f(t), i0+i]
       GemmDesc d{};
-      d.A = ds->H.p + hoff;
+      d.A = ds->H.p + hoff * es;
       d.sam = 1;
       d.sak = int64_t(Q) * jb;
       d.gidx = g;
-      d.C = ds->data.p + int64_t(ds->leaf_box[b]) * box_stride;
+      d.C = ds->data.p + int64_t(ds->leaf_box[b]) * box_stride * es;
       d.ldc = ni;
       d.M = Q * jb;
       d.N = ni;
@@ -665,10 +826,10 @@ static void setup_workspace(Tree* t, int jb, int ni) {
     }
     {  // KB[r, i] (+)= sum_(q,j) H[r][(q,j)] Mloc[(q,j), i]
       GemmDesc d{};
-      d.A = ds->H.p + hoff;
+      d.A = ds->H.p + hoff * es;
       d.sam = int64_t(Q) * jb;
       d.sak = 1;
-      d.B = ds->data.p + int64_t(ds->nbox + ds->leaf_box[b]) * box_stride;
+      d.B = ds->data.p + int64_t(ds->nbox + ds->leaf_box[b]) * box_stride * es;
       d.ldb = ni;
       d.C = ds->KB.p + ds->f_off[b] * ni;
       d.ldc = ni;
@@ -690,18 +851,20 @@ static void setup_workspace(Tree* t, int jb, int ni) {
   ds->n_l2p = int(tl2.size());
   ds->ws_jb = jb;
   ds->ws_ni = ni;
+  ds->ws_prec = prec;
 }
 
-static void launch_translate(const Tree* t, const Pass& ps, double* data, int64_t box_stride, int64_t ncol,
-                             const double* ops, hipStream_t st) {
+template <class T>
+static void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
+                             hipStream_t st) {
   const int Q = t->Q, KS = ksteps_of(Q);
   const int64_t nct = (ncol + 255) / 256;
   const int64_t nblocks = nct * ps.ntgt;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_TR(MT)                                                                                      \
-  hipLaunchKernelGGL(translate_f64_kernel<MT>, dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
-                     ncol, Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
+#define OCCK_TR(MT)                                                                                           \
+  hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, ncol, \
+                     Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
   switch (mtiles_of(Q)) {
     case 1: OCCK_TR(1); break;
     case 2: OCCK_TR(2); break;
@@ -715,6 +878,15 @@ static void launch_translate(const Tree* t, const Pass& ps, double* data, int64_
   HIP_OK(hipGetLastError());
 }
 
+static void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                            hipStream_t st) {
+  const int64_t n = rows * cols;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+  if (n == 0) return;
+  hipLaunchKernelGGL(to_float_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  HIP_OK(hipGetLastError());
+}
+
 void device_free(Tree* t) {
   if (t->dev) free_state(t->dev);
   t->dev = nullptr;
@@ -723,6 +895,9 @@ void device_free(Tree* t) {
 static void free_state(DeviceState* ds) {
   for (hipEvent_t e : ds->ev_pool) (void)hipEventDestroy(e);
   ds->ev_pool.clear();
+  ds->Of.free();
+  ds->opsf.free();
+  ds->Cf.free();
   ds->O.free();
   ds->funcs.free();
   ds->opparam.free();
@@ -739,7 +914,7 @@ static void free_state(DeviceState* ds) {
   delete ds;
 }
 
-static int auto_jblock(const Tree* t, int nj, int ni) {
+static int auto_jblock(const Tree* t, int nj, int ni, size_t es) {
   const size_t cap = device_cap();
   const int Q = t->Q;
   int64_t sum_nb = 0;
@@ -749,20 +924,56 @@ static int auto_jblock(const Tree* t, int nj, int ni) {
   const size_t budget = std::min(cap / 2, size_t(32) << 30);
   int jb = std::min(nj, 256);
   while (jb > 1) {
-    const size_t need = size_t(sum_nb) * Q * jb * 8 + size_t(2) * nbox * Q * size_t(jb) * ni * 8;
+    const size_t need = size_t(sum_nb) * Q * jb * es + size_t(2) * nbox * Q * size_t(jb) * ni * es;
     if (need <= budget) break;
     jb = (jb + 1) / 2;
   }
   return std::max(1, jb);
 }
 
+// One j batch: half transform, Omega, upward, downward, L2P.
+template <int MODE>
+static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
+                        int j0, int j1, int jb, int ni, bool prof, hipStream_t st) {
+  using T = typename ModeT<MODE>::T;
+  const int Q = t->Q;
+  const int64_t ncol = int64_t(jb) * ni;
+  const int64_t box_stride = int64_t(Q) * ncol;
+  T* data = reinterpret_cast<T*>(ds->data.p);
+  const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops.p) : reinterpret_cast<const T*>(ds->opsf.p);
+  const int nj = j1 - j0;
+  const int nblk = (nj + jb - 1) / jb;
+  for (int kb = 0; kb < nblk; ++kb) {
+    const int64_t jstart = j0 + int64_t(kb) * jb;
+    {
+      ProfScope ps(ds, prof, OCCK_K_HALF, st);
+      hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
+                         ds->t_half.p, Cg, ldcg, jstart, int64_t(j1), 0);
+    }
+    {
+      ProfScope ps(ds, prof, OCCK_K_OMEGA, st);
+      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(unsigned(ds->n_omega)), dim3(256), 0, st,
+                         ds->d_omega.p, ds->t_omega.p, Cg, ldcg, int64_t(i0), int64_t(i1), 0);
+    }
+    {
+      ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
+      for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, ncol, ops, st);
+    }
+    {
+      ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
+      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, ncol, ops, st);
+    }
+    {
+      ProfScope ps(ds, prof, OCCK_K_L2P, st);
+      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2p)), dim3(256), 0, st,
+                         ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, int64_t(0), int64_t(0), kb > 0 ? 1 : 0);
+    }
+    HIP_OK(hipGetLastError());
+  }
+}
+
 int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1, int32_t j0,
               int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk, void* stream) {
-  (void)nocc;
-  if (opts->precision != OCCK_PREC_FP64) {
-    set_error("occk_far_K: only FP64 precision is built in this library version");
-    return OCCK_EINVAL;
-  }
   if (opts->rank_mode != OCCK_RANK_FIXED) {
     set_error("occk_far_K: learned ranks are not built in this library version");
     return OCCK_ESTATE;
@@ -770,6 +981,8 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int ni = i1 - i0, nj = j1 - j0;
   const int nbasis = t->nbasis;
+  const int prec = opts->precision;
+  const bool mixed = prec != OCCK_PREC_FP64;
   try {
     if (t->lmin < 0 || nj == 0 || ni == 0) {   // no far field: nothing to upload
       if (!opts->accumulate && ni > 0)
@@ -779,12 +992,16 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       return OCCK_OK;
     }
     if (!t->dev) upload_tree(t);
-    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni);
-    setup_workspace(t, jb, ni);
     DeviceState* ds = t->dev;
+    if (mixed && !ds->Of.p) {   // FP32 copies of the per-tree operands (once)
+      ds->Of.alloc(ds->O.n);
+      ds->opsf.alloc(ds->ops.n);
+      launch_to_float(ds->O.p, 0, ds->Of.p, 0, 1, int64_t(ds->O.n), st);
+    }
+    const size_t es = mixed ? 4 : 8;
+    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es);
+    setup_workspace(t, jb, ni, prec);
     const int Q = t->Q;
-    const int64_t ncol = int64_t(jb) * ni;
-    const int64_t box_stride = int64_t(Q) * ncol;
     const bool prof = t->profile != 0;
     {
       ProfScope ps(ds, prof, OCCK_K_OPGEN, st);
@@ -792,34 +1009,20 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
                          t->L, Q);
       HIP_OK(hipGetLastError());
     }
-    const int nblk = (nj + jb - 1) / jb;
-    for (int kb = 0; kb < nblk; ++kb) {
-      const int64_t jstart = j0 + int64_t(kb) * jb;
-      {
-        ProfScope ps(ds, prof, OCCK_K_HALF, st);
-        hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
-                           ds->t_half.p, C, ldc, jstart, int64_t(j1), 0);
-      }
-      {
-        ProfScope ps(ds, prof, OCCK_K_OMEGA, st);
-        hipLaunchKernelGGL(gemm_f64_kernel<false>, dim3(unsigned(ds->n_omega)), dim3(256), 0, st, ds->d_omega.p,
-                           ds->t_omega.p, C, ldc, int64_t(i0), int64_t(i1), 0);
-      }
-      {
-        ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
-        for (const Pass& p : ds->up) launch_translate(t, p, ds->data.p, box_stride, ncol, ds->ops.p, st);
-      }
-      {
-        ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
-        for (const Pass& p : ds->down) launch_translate(t, p, ds->data.p, box_stride, ncol, ds->ops.p, st);
-      }
-      {
-        ProfScope ps(ds, prof, OCCK_K_L2P, st);
-        hipLaunchKernelGGL(gemm_f64_kernel<true>, dim3(unsigned(ds->n_l2p)), dim3(256), 0, st, ds->d_l2p.p,
-                           ds->t_l2p.p, C, ldc, int64_t(0), int64_t(0), kb > 0 ? 1 : 0);
-      }
-      HIP_OK(hipGetLastError());
+    if (mixed) {
+      ProfScope ps(ds, prof, OCCK_K_CONVERT, st, 2);
+      launch_to_float(ds->ops.p, 0, ds->opsf.p, 0, 1, int64_t(ds->ops.n), st);
+      ds->Cf.alloc(size_t(nbasis) * nocc);
+      launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
+    if (prec == OCCK_PREC_FP64)
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st);
+    else if (prec == OCCK_PREC_FP32)
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
+    else if (prec == OCCK_PREC_BF16X3)
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
+    else
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
@@ -836,7 +1039,6 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
   return OCCK_OK;
 }
 
-
 // --------------------------------------------------------------------------
 // diagnostics
 // --------------------------------------------------------------------------
@@ -846,8 +1048,6 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
 // i+16k), 1: v_mfma_f32_16x16x4f32 (same operand layout), 2:
 // v_mfma_f32_16x16x32_bf16 (A[i][k] in lane i+16(k/8), element k%8; B[k][j]
 // in lane j+16(k/8), element k%8).  out: [64 lanes][4].
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 __global__ void mfma_probe_kernel(double* out, int kind, int ia, int ka, int jb) {
   const int lane = threadIdx.x;
   if (kind == 0) {
@@ -899,12 +1099,25 @@ int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count) {
     set_error("no device state");
     return OCCK_ESTATE;
   }
-  const DevBuf<double>* b = which == 0 ? &ds->ops : which == 1 ? &ds->H : which == 2 ? &ds->data : &ds->KB;
-  if (count) *count = int64_t(b->n);
-  if (host && b->n) {
+  // element counts in doubles (FP64 path) or in the buffer's own element size
+  const void* p = nullptr;
+  size_t bytes = 0, es = 8;
+  if (which == 0) { p = ds->ops.p; bytes = ds->ops.n * 8; }
+  else if (which == 1) { p = ds->H.p; bytes = ds->H.n; es = ds->ws_prec == OCCK_PREC_FP64 ? 8 : 4; }
+  else if (which == 2) { p = ds->data.p; bytes = ds->data.n; es = ds->ws_prec == OCCK_PREC_FP64 ? 8 : 4; }
+  else { p = ds->KB.p; bytes = ds->KB.n * 8; }
+  const size_t n = bytes / es;
+  if (count) *count = int64_t(n);
+  if (host && n) {
     try {
       HIP_OK(hipDeviceSynchronize());
-      HIP_OK(hipMemcpy(host, b->p, b->n * sizeof(double), hipMemcpyDeviceToHost));
+      if (es == 8) {
+        HIP_OK(hipMemcpy(host, p, bytes, hipMemcpyDeviceToHost));
+      } else {
+        std::vector<float> tmp(n);
+        HIP_OK(hipMemcpy(tmp.data(), p, bytes, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < n; ++k) host[k] = tmp[k];
+      }
     } catch (const HipError& e) {
       set_error(e.what());
       return OCCK_EHIP;
@@ -945,7 +1158,9 @@ int32_t workspace_info(Tree* t, int32_t* jblock, int64_t* bytes) {
   if (jblock) *jblock = ds ? ds->ws_jb : -1;
   if (bytes) {
     *bytes = 0;
-    if (ds) *bytes = int64_t(ds->bytes + (ds->H.n + ds->data.n + ds->KB.n) * sizeof(double) + ds->ops.n * sizeof(double));
+    if (ds)
+      *bytes = int64_t(ds->bytes + ds->H.n + ds->data.n + ds->KB.n * 8 + ds->ops.n * 8 + ds->opsf.n * 4 +
+                       ds->Of.n * 4 + ds->Cf.n * 4);
   }
   return OCCK_OK;
 }

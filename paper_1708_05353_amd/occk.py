@@ -13,7 +13,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libocck.so")
 
 OK, EINVAL, ENOMEM, EHIP, EHANDLE, ENONFINITE, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16X6 = 0, 1, 2, 3
 RANK_FIXED, RANK_LEARNED = 0, 1
 MAX_LEVELS = 13
 
