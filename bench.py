@@ -24,9 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FLOPS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15 / 3.0}
+PEAK_FLOPS = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15 / 3.0, "bf16x6": 2.5e15 / 6.0}
 PEAK_HBM = 8.0e12
-ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4}
+ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
 
 
 def class_costs(info, ni, nj, jb, prec):
@@ -78,13 +78,78 @@ def cpu_baseline(wl, C, flops_total, nocc, jsample):
                       f"is excluded on the GPU"}
 
 
+def bench_batch(args):
+    """16 water clusters of 20..100 molecules: one tuned persistent launch vs 16
+    separate occk_far_K launches of the same precision vs 16 plain FP64 ones."""
+    import torch
+
+    import workloads
+    from paper_1708_05353_amd import occk
+
+    prec_name = args.precision if args.precision != "fp64" else "fp32"
+    prec = {"fp32": occk.PREC_FP32, "bf16x3": occk.PREC_BF16X3, "bf16x6": occk.PREC_BF16X6}[prec_name]
+    wls = workloads.water_batch()
+    trees, Cs, Ks, flops = [], [], [], 0
+    for wl in wls:
+        C = wl.orbitals()
+        tr = occk.Tree(wl.system, wl.params)
+        trees.append(tr)
+        Cs.append(torch.from_numpy(C).cuda())
+        Ks.append(torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda"))
+        flops += tr.flops(C.shape[1], C.shape[1])["total"]
+    noccs = [C.shape[1] for C in Cs]
+    plan = occk.Batch(trees, noccs, prec)
+    choice = plan.tune(Cs, Ks)
+    torch.cuda.synchronize()
+
+    def timeit(fn, steps):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    t_batch = timeit(lambda: plan.run(Cs, Ks), args.steps)
+    K_batch = [K.clone() for K in Ks]
+    plan.free()
+
+    def separate(code):
+        for tr, C, K in zip(trees, Cs, Ks):
+            occk.far_K(tr, C, K, precision=code, jblock=0)
+    t_sep = timeit(lambda: separate(prec), args.steps)
+    dev = max(float((a - b).abs().max() / b.abs().max()) for a, b in zip(K_batch, Ks))
+    t_f64 = timeit(lambda: separate(occk.PREC_FP64), args.steps)
+    value = flops / (t_batch * 1e-3) / 1e9
+    out = {
+        "metric": "far-field K_ri GFLOP/s (16-system batch)",
+        "value": round(value, 1), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t_batch, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[prec_name], "data": "synthetic",
+        "config": {"workload": "16 water clusters (20..100 molecules, nbasis 480..2400), 3-D depth 3, ws 2, L=2, "
+                               "all i and j of each",
+                   "precision": prec_name, "autotuned": {"blocks_per_cu": choice[0], "gemm_tiles_per_task": choice[1],
+                                                          "translation_tiles_per_task": choice[2]},
+                   "flops_per_step": flops},
+        "separate_launches_ms": round(t_sep, 3), "separate_fp64_ms": round(t_f64, 3),
+        "speedup_vs_separate": round(t_sep / t_batch, 3), "speedup_vs_fp64": round(t_f64 / t_batch, 3),
+        "batched_vs_separate_rel_diff": dev,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16"])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--lmax", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--jblock", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-j", type=int, default=2)
@@ -94,12 +159,17 @@ def main():
               "split over the output index i is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "batch16":
+        bench_batch(args)
+        return
+
     import torch
 
     import workloads
     from paper_1708_05353_amd import occk
 
-    prec = {"fp64": occk.PREC_FP64, "fp32": occk.PREC_FP32, "bf16x3": occk.PREC_BF16X3}[args.precision]
+    prec = {"fp64": occk.PREC_FP64, "fp32": occk.PREC_FP32, "bf16x3": occk.PREC_BF16X3,
+            "bf16x6": occk.PREC_BF16X6}[args.precision]
     wl = workloads.alkane_chain(lmax=args.lmax)
     t0 = time.perf_counter()
     C = wl.orbitals()
@@ -174,7 +244,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.precision],
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "bf16x6": "bf16x6"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"alkane chain (C400H802 stand-in): nbasis 9610, nocc 1601, L={args.lmax}, "
                                f"1-D tree depth 8, ws 2; all i and j",

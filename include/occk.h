@@ -88,6 +88,7 @@ typedef struct occk_tree_params {
 
 typedef struct occk_tree occk_tree;
 typedef struct occk_selector occk_selector;
+typedef struct occk_batch occk_batch;
 
 #define OCCK_MAX_LEVELS 13
 
@@ -187,6 +188,50 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
  * before the first call) and the device bytes held by the handle.  Either
  * pointer may be NULL. */
 int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes);
+
+/* ---- many systems in one persistent launch ---- */
+
+/* Plan for evaluating K^ff of nsys independent systems (all i, all j of
+ * each, one j batch per system) in one persistent (cooperative) kernel
+ * launch: the same steps as occk_far_K (Eqs. 15-18, operator generation and
+ * operand conversion included) become tasks grouped by stage; the blocks
+ * share the tasks of a stage and meet at a grid barrier between stages.  trees: live handles with a far field and a common lmax;
+ * the plan keeps pointers to them (free the plan first).  nocc[k]: occupied
+ * count of system k.  opts: precision (any OCCK_PREC_*); rank_mode must be
+ * FIXED; jblock and accumulate are ignored (K is overwritten).  Uploads the
+ * trees and allocates every workspace (synchronous).  Errors: EINVAL,
+ * EHANDLE, ENOMEM, EHIP. */
+int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* nocc, const occk_far_opts* opts,
+                          occk_batch** out);
+
+/* One persistent cooperative launch on hip_stream.
+ * C[k]: device, row-major nbasis_k x ldc[k] FP64 (ldc[k] >= nocc[k]);
+ * K[k]: device, row-major nbasis_k x ldk[k] FP64, columns 0..nocc[k]-1 are
+ * overwritten with K^ff.  Asynchronous.  Calls on one plan must not overlap
+ * (they share the workspaces).  A standalone occk_far_K on one of the trees
+ * replaces its workspace; the next run rebuilds the plan's tables
+ * (synchronously). */
+int32_t occk_batch_run(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
+                       const int64_t* ldk, void* hip_stream);
+
+/* Autotuner: runs the batch once per candidate configuration (blocks per
+ * compute unit 1/2/4, GEMM tiles per task 1/2, translation column tiles per
+ * task 1/4) after a warm-up, keeps the fastest and reports it in
+ * choice[3] = {blocks per CU, GEMM tiles per task, translation tiles per
+ * task} (may be NULL).  Writes K like occk_batch_run.  Synchronous. */
+int32_t occk_batch_tune(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
+                        const int64_t* ldk, void* hip_stream, int32_t* choice);
+
+/* nsys and the first cap nocc values of the plan. */
+int32_t occk_batch_shape(const occk_batch* plan, int32_t* nsys, int32_t* nocc, int32_t cap);
+
+/* config[6] = {blocks per CU, GEMM tiles per task, translation tiles per
+ * task, number of tasks, number of stages, resident-block limit per CU} of
+ * the plan's current configuration. */
+int32_t occk_batch_config(const occk_batch* plan, int32_t* config);
+
+/* Frees the plan (after a device synchronisation); NULL is accepted. */
+int32_t occk_batch_free(occk_batch* plan);
 
 /* ---- per-kernel timing ---- */
 

@@ -24,6 +24,13 @@ static bool live(const Tree* t) {
   return t && g_live.count(t) && t->magic == kTreeMagic;
 }
 
+static std::unordered_set<const void*> g_plans;
+
+static bool plan_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return p && g_plans.count(p);
+}
+
 }  // namespace occk
 
 using namespace occk;
@@ -284,6 +291,150 @@ int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes) {
     return OCCK_EHANDLE;
   }
   return workspace_info(t, jblock, bytes);
+}
+
+int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* nocc, const occk_far_opts* opts,
+                          occk_batch** out) {
+  if (!out) {
+    set_error("occk_batch_create: out is NULL");
+    return OCCK_EINVAL;
+  }
+  *out = nullptr;
+  if (nsys < 1 || nsys > 4096 || !trees || !nocc) {
+    set_error("occk_batch_create: need 1 <= nsys <= 4096 and non-NULL trees, nocc");
+    return OCCK_EINVAL;
+  }
+  occk_far_opts o{};
+  if (opts) o = *opts;
+  if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X6) {
+    set_error("occk_batch_create: unknown precision");
+    return OCCK_EINVAL;
+  }
+  if (o.rank_mode != OCCK_RANK_FIXED) {
+    set_error("occk_batch_create: only fixed ranks are batched");
+    return OCCK_EINVAL;
+  }
+  std::vector<Tree*> ts(nsys);
+  for (int k = 0; k < nsys; ++k) {
+    Tree* t = reinterpret_cast<Tree*>(trees[k]);
+    if (!live(t)) {
+      set_error("occk_batch_create: a tree handle is not live");
+      return OCCK_EHANDLE;
+    }
+    for (int k2 = 0; k2 < k; ++k2)
+      if (ts[k2] == t) {
+        set_error("occk_batch_create: a tree appears twice");
+        return OCCK_EINVAL;
+      }
+    if (t->lmin < 0) {
+      set_error("occk_batch_create: a system has no far field");
+      return OCCK_EINVAL;
+    }
+    if (t->L != reinterpret_cast<Tree*>(trees[0])->L) {
+      set_error("occk_batch_create: all systems must share lmax");
+      return OCCK_EINVAL;
+    }
+    if (nocc[k] < 1) {
+      set_error("occk_batch_create: nocc must be >= 1");
+      return OCCK_EINVAL;
+    }
+    ts[k] = t;
+  }
+  void* plan = nullptr;
+  int32_t rc = OCCK_OK;
+  OCCK_GUARD_BEGIN
+  rc = batch_create(nsys, ts.data(), nocc, o.precision, &plan);
+  OCCK_GUARD_END
+  if (rc != OCCK_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_plans.insert(plan);
+  }
+  *out = reinterpret_cast<occk_batch*>(plan);
+  return OCCK_OK;
+}
+
+int32_t occk_batch_shape(const occk_batch* plan, int32_t* nsys, int32_t* nocc, int32_t cap) {
+  if (!plan_live(plan)) {
+    set_error("occk_batch_shape: plan is not live");
+    return OCCK_EHANDLE;
+  }
+  return batch_shape(plan, nsys, nocc, cap, nullptr);
+}
+
+int32_t occk_batch_config(const occk_batch* plan, int32_t* config) {
+  if (!plan_live(plan)) {
+    set_error("occk_batch_config: plan is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!config) {
+    set_error("occk_batch_config: config is NULL");
+    return OCCK_EINVAL;
+  }
+  return batch_shape(plan, nullptr, nullptr, 0, config);
+}
+
+static int32_t check_io(int nsys, const double* const* C, const int64_t* ldc, double* const* K, const int64_t* ldk) {
+  if (!C || !ldc || !K || !ldk) {
+    set_error("batch: NULL array argument");
+    return OCCK_EINVAL;
+  }
+  for (int k = 0; k < nsys; ++k)
+    if (!C[k] || !K[k] || ((reinterpret_cast<uintptr_t>(C[k]) | reinterpret_cast<uintptr_t>(K[k])) & 7)) {
+      set_error("batch: C and K pointers must be non-NULL and 8-byte aligned");
+      return OCCK_EINVAL;
+    }
+  return OCCK_OK;
+}
+
+int32_t occk_batch_run(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
+                       const int64_t* ldk, void* hip_stream) {
+  if (!plan_live(plan)) {
+    set_error("occk_batch_run: plan is not live");
+    return OCCK_EHANDLE;
+  }
+  int32_t nsys = 0;
+  int32_t rc = occk_batch_shape(plan, &nsys, nullptr, 0);
+  if (rc != OCCK_OK) return rc;
+  if ((rc = check_io(nsys, C, ldc, K, ldk)) != OCCK_OK) return rc;
+  std::vector<int32_t> nocc(nsys);
+  occk_batch_shape(plan, &nsys, nocc.data(), nsys);
+  for (int k = 0; k < nsys; ++k)
+    if (ldc[k] < nocc[k] || ldk[k] < nocc[k]) {
+      set_error("occk_batch_run: need ldc >= nocc and ldk >= nocc");
+      return OCCK_EINVAL;
+    }
+  OCCK_GUARD_BEGIN
+  return batch_run(plan, C, ldc, K, ldk, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_batch_tune(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
+                        const int64_t* ldk, void* hip_stream, int32_t* choice) {
+  if (!plan_live(plan)) {
+    set_error("occk_batch_tune: plan is not live");
+    return OCCK_EHANDLE;
+  }
+  int32_t nsys = 0;
+  occk_batch_shape(plan, &nsys, nullptr, 0);
+  int32_t rc = check_io(nsys, C, ldc, K, ldk);
+  if (rc != OCCK_OK) return rc;
+  OCCK_GUARD_BEGIN
+  return batch_tune(plan, C, ldc, K, ldk, hip_stream, choice);
+  OCCK_GUARD_END
+}
+
+int32_t occk_batch_free(occk_batch* plan) {
+  if (!plan) return OCCK_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_plans.count(plan)) {
+      set_error("occk_batch_free: plan is not live");
+      return OCCK_EHANDLE;
+    }
+    g_plans.erase(plan);
+  }
+  return batch_free(plan);
 }
 
 }  // extern "C"

@@ -1,0 +1,121 @@
+// Device-side state of a tree handle and host helpers shared by the
+// standalone and batched paths.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+#define HIP_OK(x)                                                                    \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess) throw occk::HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+namespace occk {
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+// --------------------------------------------------------------------------
+// host orchestration
+// --------------------------------------------------------------------------
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void free() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void upload(const std::vector<T>& v) {
+    free();
+    n = v.size();
+    if (n == 0) return;
+    HIP_OK(hipMalloc(&p, n * sizeof(T)));
+    HIP_OK(hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void alloc(size_t count) {
+    if (count <= n && p) return;
+    free();
+    if (count == 0) return;
+    HIP_OK(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+};
+
+struct Pass {           // one translation launch
+  int ntgt = 0;
+  DevBuf<int32_t> tgt_box, src_ptr, src_box, src_op;
+};
+
+struct DeviceState {
+  int device = -1;
+  // per tree
+  DevBuf<double> O;               // leaf AO multipole blocks (FP64)
+  DevBuf<float> Of;               // FP32 copy for the mixed paths (made on first use)
+  std::vector<int64_t> O_off;     // per leaf, elements
+  DevBuf<int32_t> funcs;          // concatenated leaf function lists
+  std::vector<int64_t> f_off;     // per leaf
+  DevBuf<OpParam> opparam;
+  DevBuf<double> ops;             // FP64 operators (always generated in FP64)
+  DevBuf<float> opsf;             // rounded copy for the mixed paths
+  std::vector<Pass> up, down;     // up[k]: level depth-1-k ; down[k]: level lmin+k
+  DevBuf<int32_t> occ_ptr, occ_row;
+  int nbox = 0;                    // boxes on levels lmin..depth
+  std::vector<int32_t> leaf_box;   // leaf -> box slot
+  // per workspace shape (j batch, n_i, precision)
+  int ws_jb = -1, ws_ni = -1, ws_prec = -1;
+  DevBuf<char> H, data;           // element type of the precision (double / float)
+  DevBuf<double> KB;              // per-leaf K partials, always FP64
+  DevBuf<float> Cf;               // FP32 copy of C for the mixed paths
+  DevBuf<GemmDesc> d_half, d_omega, d_l2p;
+  DevBuf<GemmTile> t_half, t_omega, t_l2p;
+  int n_half = 0, n_omega = 0, n_l2p = 0;
+  size_t bytes = 0;
+  // profiling: (class, start, end) event pairs recorded on the call's stream
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<int> ev_class;
+  std::vector<int64_t> launches;
+};
+
+struct ProfScope {   // records a start/end event pair around a group of launches
+  DeviceState* ds;
+  int cls;
+  hipStream_t st;
+  size_t idx;
+  int nlaunch;
+  ProfScope(DeviceState* d, bool on, int c, hipStream_t s, int n = 1) : ds(on ? d : nullptr), cls(c), st(s), nlaunch(n) {
+    if (!ds) return;
+    while (ds->ev_pool.size() < ds->ev_used + 2) {
+      hipEvent_t e;
+      HIP_OK(hipEventCreate(&e));
+      ds->ev_pool.push_back(e);
+    }
+    idx = ds->ev_used;
+    ds->ev_used += 2;
+    HIP_OK(hipEventRecord(ds->ev_pool[idx], st));
+  }
+  ~ProfScope() {
+    if (!ds) return;
+    (void)hipEventRecord(ds->ev_pool[idx + 1], st);
+    ds->ev_class.push_back(cls);
+    if (ds->launches.size() < OCCK_K_NCLASS) ds->launches.assign(OCCK_K_NCLASS, 0);
+    ds->launches[cls] += nlaunch;
+  }
+};
+
+size_t device_cap();
+void upload_tree(Tree* t);
+void setup_workspace(Tree* t, int jb, int ni, int prec);
+void ensure_mixed_operands(Tree* t, hipStream_t st);
+void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                     hipStream_t st);
+
+}  // namespace occk

@@ -25,605 +25,12 @@
 #include <type_traits>
 #include <vector>
 
-#include "occk_internal.hpp"
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-
-#define HIP_OK(x)                                                                    \
-  do {                                                                               \
-    hipError_t e_ = (x);                                                             \
-    if (e_ != hipSuccess) throw HipError(std::string(#x) + ": " + hipGetErrorString(e_)); \
-  } while (0)
+#include "device.hpp"
 
 namespace occk {
 
-struct HipError : std::runtime_error {
-  using std::runtime_error::runtime_error;
-};
-
-// --------------------------------------------------------------------------
-// device-side descriptors
-// --------------------------------------------------------------------------
-struct GemmDesc {       // element types follow the kernel's mode (output: OutT)
-  const void* A;       // A(m,k) = A[m*sam + k*sak]
-  int64_t sam, sak;
-  const void* B;       // B(k,n) = B[k*ldb + n]                (gidx == nullptr)
-  int64_t ldb;
-  const int32_t* gidx; // B(k,n) = Cuser[gidx[k]*ldcu + boff + n] (gather from C)
-  void* C;             // C(m,n) = C[m*ldc + n]
-  int64_t ldc;
-  int32_t M, N, K, pad;
-};
-struct GemmTile {
-  int32_t prob, mt, nt, pad;
-};
-struct OpParam {
-  int32_t type, weighted;
-  double d[3];
-};
-
-__host__ __device__ static inline int mtiles_of(int Q) { return (Q + 15) / 16; }
-__host__ __device__ static inline int ksteps_of(int Q) { return (Q + 3) / 4; }
-static inline int64_t opsize_of(int Q) { return int64_t(mtiles_of(Q)) * ksteps_of(Q) * 64; }
-
-// --------------------------------------------------------------------------
-// operator generation (FP64, one workgroup per operator)
-// --------------------------------------------------------------------------
-struct Cplx {
-  double re, im;
-};
-__device__ inline Cplx cmul(Cplx a, Cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
-__device__ inline Cplx cscale(Cplx a, double s) { return {a.re * s, a.im * s}; }
-
-// table index for 0 <= m <= l
-__device__ inline int tix(int l, int m) { return l * (l + 1) / 2 + m; }
-
-// X_{l,m} for any sign of m from the m >= 0 table: X_{l,-m} = (-1)^m conj(X_{l,m})
-__device__ inline Cplx tget(const Cplx* tab, int l, int m) {
-  if (m >= 0) return tab[tix(l, m)];
-  Cplx v = tab[tix(l, -m)];
-  v.im = -v.im;
-  if ((-m) & 1) { v.re = -v.re; v.im = -v.im; }
-  return v;
-}
-
-// regular O_{l,m}(v), l <= L (Eq. 4a):
-//   O_{m,m} = -(x - i y)/(2m) O_{m-1,m-1},  O_{m+1,m} = z O_{m,m},
-//   O_{l+1,m} = ((2l+1) z O_{l,m} - r^2 O_{l-1,m}) / ((l+1)^2 - m^2)
-__device__ void regular_table(int L, const double* v, Cplx* tab) {
-  const double x = v[0], y = v[1], z = v[2], r2 = x * x + y * y + z * z;
-  tab[0] = {1.0, 0.0};
-  for (int m = 0; m <= L; ++m) {
-    if (m > 0) tab[tix(m, m)] = cscale(cmul({x, -y}, tab[tix(m - 1, m - 1)]), -1.0 / (2.0 * m));
-    if (m + 1 <= L) tab[tix(m + 1, m)] = cscale(tab[tix(m, m)], z);
-    for (int l = m + 1; l + 1 <= L; ++l) {
-      const double inv = 1.0 / double((l + 1) * (l + 1) - m * m);
-      const Cplx a = tab[tix(l, m)], b = tab[tix(l - 1, m)];
-      tab[tix(l + 1, m)] = {((2 * l + 1) * z * a.re - r2 * b.re) * inv, ((2 * l + 1) * z * a.im - r2 * b.im) * inv};
-    }
-  }
-}
-
-// irregular M_{l,m}(v), l <= L (Eq. 4b):
-//   M_{0,0} = 1/r,  M_{m,m} = -(2m-1)(x + i y)/r^2 M_{m-1,m-1},
-//   M_{m+1,m} = (2m+1) z M_{m,m}/r^2,
-//   M_{l+1,m} = ((2l+1) z M_{l,m} - (l^2 - m^2) M_{l-1,m}) / r^2
-__device__ void irregular_table(int L, const double* v, Cplx* tab) {
-  const double x = v[0], y = v[1], z = v[2], r2 = x * x + y * y + z * z;
-  const double ir2 = 1.0 / r2;
-  tab[0] = {1.0 / sqrt(r2), 0.0};
-  for (int m = 0; m <= L; ++m) {
-    if (m > 0) tab[tix(m, m)] = cscale(cmul({x, y}, tab[tix(m - 1, m - 1)]), -(2.0 * m - 1.0) * ir2);
-    if (m + 1 <= L) tab[tix(m + 1, m)] = cscale(tab[tix(m, m)], (2 * m + 1) * z * ir2);
-    for (int l = m + 1; l + 1 <= L; ++l) {
-      const Cplx a = tab[tix(l, m)], b = tab[tix(l - 1, m)];
-      const double c = double(l * l - m * m);
-      tab[tix(l + 1, m)] = {((2 * l + 1) * z * a.re - c * b.re) * ir2, ((2 * l + 1) * z * a.im - c * b.im) * ir2};
-    }
-  }
-}
-
-// complex coefficient c(l,m; l',m') of one translation
-__device__ inline Cplx coef(int type, const Cplx* tab, int l, int m, int lp, int mp) {
-  if (type == kOpM2M) {  // O_{l-l', m-m'}(d)
-    if (lp > l || abs(m - mp) > l - lp) return {0.0, 0.0};
-    return tget(tab, l - lp, m - mp);
-  }
-  if (type == kOpL2L) {  // O_{l'-l, m'-m}(d)
-    if (lp < l || abs(mp - m) > lp - l) return {0.0, 0.0};
-    return tget(tab, lp - l, mp - m);
-  }
-  Cplx v = tget(tab, l + lp, m + mp);  // (-1)^l M_{l+l', m+m'}(R)
-  if (l & 1) { v.re = -v.re; v.im = -v.im; }
-  return v;
-}
-
-// real component q -> (l, m, part): part 0 = (l,0) or Re, 1 = Im
-__device__ inline void decode(int q, int& l, int& m, int& part) {
-  l = 0;
-  while ((l + 1) * (l + 1) <= q) ++l;
-  const int k = q - l * l;
-  if (k == 0) { m = 0; part = 0; }
-  else { m = (k + 1) / 2; part = (k & 1) ? 0 : 1; }
-}
-
-// Real-form matrix entry T[row][col] of a translation acting on real-form
-// vectors (m >= 0 components; negative m implied by X_{-m} = (-1)^m conj X_m).
-__device__ double real_entry(int type, const Cplx* tab, int row, int col) {
-  int l, m, pr, lp, mu, pc;
-  decode(row, l, m, pr);
-  decode(col, lp, mu, pc);
-  const Cplx z1 = coef(type, tab, l, m, lp, mu);
-  if (mu == 0) return pr == 0 ? z1.re : z1.im;
-  Cplx z2 = coef(type, tab, l, m, lp, -mu);
-  if (mu & 1) { z2.re = -z2.re; z2.im = -z2.im; }
-  if (pc == 0) {  // coefficient of Re(x)
-    const Cplx s{z1.re + z2.re, z1.im + z2.im};
-    return pr == 0 ? s.re : s.im;
-  }
-  const Cplx d{z1.re - z2.re, z1.im - z2.im};  // coefficient of Im(x)
-  return pr == 0 ? -d.im : d.re;
-}
-
-// L2P weights folded into leaf-level operators: K = 2 sum_lm O^{rj} Mloc^{ij}
-// = sum_q w_q H_q Mloc_q with w = 2 for (l,0), 4 for Re, -4 for Im rows.
-__device__ inline double l2p_weight(int q) {
-  int l, m, p;
-  decode(q, l, m, p);
-  if (m == 0) return 2.0;
-  return p == 0 ? 4.0 : -4.0;
-}
-
-// ops layout ("fragment order" of the FP64 MFMA A operand): element
-// ((mt*KS + ks)*64 + lane) holds T[mt*16 + lane%16][ks*4 + lane/16].
-__global__ __launch_bounds__(64) void opgen_kernel(const OpParam* __restrict__ params, double* __restrict__ ops,
-                                                   int L, int Q) {
-  __shared__ Cplx tab[(2 * kMaxL + 1) * (2 * kMaxL + 2) / 2];
-  const OpParam p = params[blockIdx.x];
-  if (threadIdx.x == 0) {
-    if (p.type == kOpM2L) irregular_table(2 * L, p.d, tab);
-    else regular_table(L, p.d, tab);
-  }
-  __syncthreads();
-  const int MT = mtiles_of(Q), KS = ksteps_of(Q);
-  double* out = ops + int64_t(blockIdx.x) * MT * KS * 64;
-  for (int e = threadIdx.x; e < MT * KS * 64; e += 64) {
-    const int lane = e & 63;
-    const int frag = e >> 6;
-    const int mt = frag / KS, ks = frag % KS;
-    const int row = mt * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
-    double v = 0.0;
-    if (row < Q && col < Q) {
-      v = real_entry(p.type, tab, row, col);
-      if (p.weighted) v *= l2p_weight(row);
-    }
-    out[e] = v;
-  }
-}
-
-// --------------------------------------------------------------------------
-// arithmetic modes of the contractions
-//   kModeF64    FP64 operands, v_mfma_f64_16x16x4f64
-//   kModeF32    FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation
-//   kModeBF16x3 FP32 operands split as x = hi + lo (bf16 each, round to
-//               nearest even); a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
-//               v_mfma_f32_16x16x32_bf16 with FP32 accumulation
-// MFMA layouts (checked with occk_debug_mfma_probe):
-//   f64/f32 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
-//   bf16 16x16x32: A[i][k] in lane i + 16(k/8) element k%8, B likewise;
-//   f64 D[i][j] in lane j + 16(i%4) element i/4 (rows interleaved),
-//   f32 D[i][j] in lane j + 16(i/4) element i%4.
-// --------------------------------------------------------------------------
-//   kModeBF16x6 three-way split x = hi + mid + lo; six products
-//               (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid), ~2^-24 relative
-enum { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16x6 = 3 };
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s8v __attribute__((ext_vector_type(8)));
-
-template <int MODE> struct ModeT;
-template <> struct ModeT<kModeF64> { using T = double; using Acc = d4; static constexpr int KT = 16; };
-template <> struct ModeT<kModeF32> { using T = float; using Acc = f4; static constexpr int KT = 16; };
-template <> struct ModeT<kModeBF16x3> { using T = float; using Acc = f4; static constexpr int KT = 32; };
-template <> struct ModeT<kModeBF16x6> { using T = float; using Acc = f4; static constexpr int KT = 32; };
-
-__device__ inline uint32_t bf16_rne_bits(float x) {   // bf16 bits (in the low half) of x, round to nearest even
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-
-// x[e] -> hi[e] + lo[e] as bf16 vectors
-__device__ inline void split8(const float* x, bf16x8& hi, bf16x8& lo) {
-  s8v h, l;
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t hb = bf16_rne_bits(x[e]);
-    const float hf = __uint_as_float(hb << 16);
-    h[e] = short(hb);
-    l[e] = short(bf16_rne_bits(x[e] - hf));
-  }
-  hi = __builtin_bit_cast(bf16x8, h);
-  lo = __builtin_bit_cast(bf16x8, l);
-}
-
-// x[e] -> hi[e] + mid[e] + lo[e] as bf16 vectors
-__device__ inline void split8x3(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
-  s8v h, m, l;
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t hb = bf16_rne_bits(x[e]);
-    const float r1 = x[e] - __uint_as_float(hb << 16);
-    const uint32_t mb = bf16_rne_bits(r1);
-    const float r2 = r1 - __uint_as_float(mb << 16);
-    h[e] = short(hb);
-    m[e] = short(mb);
-    l[e] = short(bf16_rne_bits(r2));
-  }
-  hi = __builtin_bit_cast(bf16x8, h);
-  mid = __builtin_bit_cast(bf16x8, m);
-  lo = __builtin_bit_cast(bf16x8, l);
-}
-
-__device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-
-// output row of accumulator element r for lane group g = lane/16 inside a 16-row tile
-template <class Acc> __device__ inline int acc_row(int g, int r);
-template <> __device__ inline int acc_row<d4>(int g, int r) { return g + 4 * r; }
-template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; }
-
-// --------------------------------------------------------------------------
-// grouped GEMM: C(m,n) (+)= sum_k A(m,k) B(k,n) over a list of problems;
-// 64x64 output tile per 256-thread block, each wave a 32x32 quadrant (2x2
-// MFMA tiles), K staged through LDS in steps of KT.
-// --------------------------------------------------------------------------
-template <int MODE, bool A_KCONTIG, class OutT>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
-                                                   const GemmTile* __restrict__ tiles,
-                                                   const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
-                                                   int64_t boff, int64_t blim, int accumulate) {
-  using T = typename ModeT<MODE>::T;
-  using Acc = typename ModeT<MODE>::Acc;
-  constexpr int KT = ModeT<MODE>::KT;
-  constexpr int E = KT / 4;          // elements per thread per operand tile
-  __shared__ T As[KT][64 + 1];
-  __shared__ T Bs[KT][64 + 1];
-  const GemmTile tl = tiles[blockIdx.x];
-  const GemmDesc d = descs[tl.prob];
-  const T* A = static_cast<const T*>(d.A);
-  const int m0 = tl.mt * 64, n0 = tl.nt * 64;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
-  // FP32 accumulators feeding an FP64 output are flushed into FP64 registers
-  // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT terms.
-  constexpr bool kFlush = std::is_same<OutT, double>::value && MODE != kModeF64;
-  constexpr int FLUSH = 8;
-  double acc64[kFlush ? 2 : 1][kFlush ? 2 : 1][kFlush ? 4 : 1];
-  if constexpr (kFlush)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
-        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
-  int ktile = 0;
-  // A: k-contiguous -> row am = tid/4, k = (tid%4)*E ..; m-contiguous -> k = tid/(64/E), m = (tid%(64/E))*E ..
-  // B: k = tid/(64/E), n = (tid%(64/E))*E ..
-  constexpr int TPR = 64 / E;
-  const int bk = tid / TPR, bn = (tid % TPR) * E;
-  T ra[E], rb[E];
-  auto load = [&](int k0) {
-    if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * E;
-      const int gm = m0 + am;
-      for (int u = 0; u < E; ++u) {
-        const int gk = k0 + ak + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
-      }
-    } else {
-      const int ak = tid / TPR, am = (tid % TPR) * E;
-      const int gk = k0 + ak;
-      for (int u = 0; u < E; ++u) {
-        const int gm = m0 + am + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
-      }
-    }
-    const int gk = k0 + bk;
-    if (gk < d.K) {
-      if (d.gidx) {
-        const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
-        for (int u = 0; u < E; ++u) {
-          const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
-        }
-      } else {
-        const T* row = static_cast<const T*>(d.B) + int64_t(gk) * d.ldb;
-        for (int u = 0; u < E; ++u) {
-          const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N) ? row[gn] : T(0);
-        }
-      }
-    } else {
-      for (int u = 0; u < E; ++u) rb[u] = T(0);
-    }
-  };
-  auto store = [&]() {
-    if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * E;
-      for (int u = 0; u < E; ++u) As[ak + u][am] = ra[u];
-    } else {
-      const int ak = tid / TPR, am = (tid % TPR) * E;
-      for (int u = 0; u < E; ++u) As[ak][am + u] = ra[u];
-    }
-    for (int u = 0; u < E; ++u) Bs[bk][bn + u] = rb[u];
-  };
-
-  load(0);
-  for (int k0 = 0; k0 < d.K; k0 += KT) {
-    store();
-    __syncthreads();
-    if (k0 + KT < d.K) load(k0 + KT);
-    if constexpr (MODE == kModeBF16x6) {
-      const int kb = 8 * (lane >> 4);
-      bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
-      for (int i = 0; i < 2; ++i) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
-        split8x3(x, ah[i], am[i], al[i]);
-      }
-      for (int j = 0; j < 2; ++j) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
-        split8x3(x, bh[j], bm[j], bl[j]);
-      }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {   // smallest terms first
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    } else if constexpr (MODE == kModeBF16x3) {
-      const int kb = 8 * (lane >> 4);
-      bf16x8 ah[2], al[2], bh[2], bl[2];
-      for (int i = 0; i < 2; ++i) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
-        split8(x, ah[i], al[i]);
-      }
-      for (int j = 0; j < 2; ++j) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
-        split8(x, bh[j], bl[j]);
-      }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    } else {
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += 4) {
-        const int kr = kk + (lane >> 4);
-        T a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
-        for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
-      }
-    }
-    __syncthreads();
-    if constexpr (kFlush) {
-      if (++ktile == FLUSH) {
-        ktile = 0;
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) {
-            for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
-            acc[i][j] = Acc{};
-          }
-      }
-    }
-  }
-  if constexpr (kFlush)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
-        for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
-  OutT* Cout = static_cast<OutT*>(d.C);
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + wn + j * 16 + (lane & 15);
-      if (col >= d.N) continue;
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row >= d.M) continue;
-        OutT* c = Cout + int64_t(row) * d.ldc + col;
-        OutT v;
-        if constexpr (kFlush) v = OutT(acc64[i][j][r]);
-        else v = OutT(acc[i][j][r]);
-        *c = accumulate ? *c + v : v;
-      }
-    }
-}
-
-// --------------------------------------------------------------------------
-// translation: out[t] = sum_{e in CSR(t)} T[op_e] * data[src_e]   (overwrite)
-// Each box is Q rows x ncol columns.  Block = 4 waves x 64 columns; each wave
-// holds MT 16-row tiles x 4 column tiles of accumulators.  Blocks are
-// renumbered so that each XCD walks contiguous (column tile, target) ranges:
-// neighbouring targets then share their sources in that XCD's L2.
-// T = double: FP64 MFMA; T = float: FP32 MFMA.
-// --------------------------------------------------------------------------
-template <class T, int MT>
-__global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
-                                                        int Q, int KS, const int32_t* __restrict__ tgt_box,
-                                                        const int32_t* __restrict__ src_ptr,
-                                                        const int32_t* __restrict__ src_box,
-                                                        const int32_t* __restrict__ src_op,
-                                                        const T* __restrict__ ops, int ntgt, int64_t nblocks) {
-  using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
-  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
-  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (logical >= nblocks) return;
-  const int t = int(logical % ntgt);
-  const int64_t ct = logical / ntgt;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t colbase = ct * 256 + wave * 64;
-  Acc acc[MT][4];
-  for (int i = 0; i < MT; ++i)
-    for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
-  const int64_t opsz = int64_t(MT) * KS * 64;
-  const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
-  for (int e = e0; e < e1; ++e) {
-    const T* X = data + int64_t(src_box[e]) * box_stride;
-    const T* Tm = ops + int64_t(src_op[e]) * opsz;
-    for (int ks = 0; ks < KS; ++ks) {
-      const int row = ks * 4 + (lane >> 4);
-      T b[4];
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = colbase + j * 16 + (lane & 15);
-        b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : T(0);
-      }
-      for (int i = 0; i < MT; ++i) {
-        const T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a, b[j], acc[i][j]);
-      }
-    }
-  }
-  T* Y = data + int64_t(tgt_box[t]) * box_stride;
-  for (int i = 0; i < MT; ++i)
-    for (int j = 0; j < 4; ++j) {
-      const int64_t col = colbase + j * 16 + (lane & 15);
-      if (col >= ncol) continue;
-      for (int r = 0; r < 4; ++r) {
-        const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row < Q) Y[int64_t(row) * ncol + col] = T(acc[i][j][r]);
-      }
-    }
-}
-
-// out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
-__global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
-                                int64_t rows, int64_t cols) {
-  const int64_t n = rows * cols;
-  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t r = e / cols, c = e % cols;
-    out[r * ldo + c] = float(in[r * ldi + c]);
-  }
-}
-
-// K[r, i0 + i] = (acc ? K : 0) + sum_{e in occ(r)} KB[row_e, i]   (fixed order)
-__global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ KB, int64_t ni,
-                                                     const int32_t* __restrict__ occ_ptr,
-                                                     const int32_t* __restrict__ occ_row, double* __restrict__ K,
-                                                     int64_t ldk, int i0, int accumulate) {
-  const int r = blockIdx.y;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= ni) return;
-  double s = 0.0;
-  for (int e = occ_ptr[r]; e < occ_ptr[r + 1]; ++e) s += KB[int64_t(occ_row[e]) * ni + i];
-  double* k = K + int64_t(r) * ldk + i0 + i;
-  *k = accumulate ? *k + s : s;
-}
-
-__global__ void zero_cols_kernel(double* __restrict__ K, int64_t ldk, int i0, int64_t ni) {
-  const int r = blockIdx.y;
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i < ni) K[int64_t(r) * ldk + i0 + i] = 0.0;
-}
-
-// --------------------------------------------------------------------------
-// host orchestration
-// --------------------------------------------------------------------------
-template <class T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t n = 0;
-  void free() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  void upload(const std::vector<T>& v) {
-    free();
-    n = v.size();
-    if (n == 0) return;
-    HIP_OK(hipMalloc(&p, n * sizeof(T)));
-    HIP_OK(hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice));
-  }
-  void alloc(size_t count) {
-    if (count <= n && p) return;
-    free();
-    if (count == 0) return;
-    HIP_OK(hipMalloc(&p, count * sizeof(T)));
-    n = count;
-  }
-};
-
-struct Pass {           // one translation launch
-  int ntgt = 0;
-  DevBuf<int32_t> tgt_box, src_ptr, src_box, src_op;
-};
-
-struct DeviceState {
-  int device = -1;
-  // per tree
-  DevBuf<double> O;               // leaf AO multipole blocks (FP64)
-  DevBuf<float> Of;               // FP32 copy for the mixed paths (made on first use)
-  std::vector<int64_t> O_off;     // per leaf, elements
-  DevBuf<int32_t> funcs;          // concatenated leaf function lists
-  std::vector<int64_t> f_off;     // per leaf
-  DevBuf<OpParam> opparam;
-  DevBuf<double> ops;             // FP64 operators (always generated in FP64)
-  DevBuf<float> opsf;             // rounded copy for the mixed paths
-  std::vector<Pass> up, down;     // up[k]: level depth-1-k ; down[k]: level lmin+k
-  DevBuf<int32_t> occ_ptr, occ_row;
-  int nbox = 0;                    // boxes on levels lmin..depth
-  std::vector<int32_t> leaf_box;   // leaf -> box slot
-  // per workspace shape (j batch, n_i, precision)
-  int ws_jb = -1, ws_ni = -1, ws_prec = -1;
-  DevBuf<char> H, data;           // element type of the precision (double / float)
-  DevBuf<double> KB;              // per-leaf K partials, always FP64
-  DevBuf<float> Cf;               // FP32 copy of C for the mixed paths
-  DevBuf<GemmDesc> d_half, d_omega, d_l2p;
-  DevBuf<GemmTile> t_half, t_omega, t_l2p;
-  int n_half = 0, n_omega = 0, n_l2p = 0;
-  size_t bytes = 0;
-  // profiling: (class, start, end) event pairs recorded on the call's stream
-  std::vector<hipEvent_t> ev_pool;
-  size_t ev_used = 0;
-  std::vector<int> ev_class;
-  std::vector<int64_t> launches;
-};
-
-struct ProfScope {   // records a start/end event pair around a group of launches
-  DeviceState* ds;
-  int cls;
-  hipStream_t st;
-  size_t idx;
-  int nlaunch;
-  ProfScope(DeviceState* d, bool on, int c, hipStream_t s, int n = 1) : ds(on ? d : nullptr), cls(c), st(s), nlaunch(n) {
-    if (!ds) return;
-    while (ds->ev_pool.size() < ds->ev_used + 2) {
-      hipEvent_t e;
-      HIP_OK(hipEventCreate(&e));
-      ds->ev_pool.push_back(e);
-    }
-    idx = ds->ev_used;
-    ds->ev_used += 2;
-    HIP_OK(hipEventRecord(ds->ev_pool[idx], st));
-  }
-  ~ProfScope() {
-    if (!ds) return;
-    (void)hipEventRecord(ds->ev_pool[idx + 1], st);
-    ds->ev_class.push_back(cls);
-    if (ds->launches.size() < OCCK_K_NCLASS) ds->launches.assign(OCCK_K_NCLASS, 0);
-    ds->launches[cls] += nlaunch;
-  }
-};
-
-static size_t device_cap() {
+size_t device_cap() {
   const char* s = std::getenv("OCCK_MAX_DEVICE_BYTES");
   if (s && *s) return size_t(std::strtoull(s, nullptr, 10));
   return size_t(96) << 30;
@@ -633,7 +40,7 @@ static void free_state(DeviceState* ds);
 
 static void upload_tree_into(Tree* t, DeviceState* ds);
 
-static void upload_tree(Tree* t) {
+void upload_tree(Tree* t) {
   if (t->lmin < 0) throw std::invalid_argument("upload_tree: the tree has no far field");
   DeviceState* ds = new DeviceState();
   try {
@@ -768,7 +175,7 @@ static void tiles_for(std::vector<GemmTile>& tiles, int prob, int M, int N) {
     for (int nt = 0; nt < (N + 63) / 64; ++nt) tiles.push_back({prob, mt, nt, 0});
 }
 
-static void setup_workspace(Tree* t, int jb, int ni, int prec) {
+void setup_workspace(Tree* t, int jb, int ni, int prec) {
   DeviceState* ds = t->dev;
   if (ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec) return;
   const int Q = t->Q, nl = t->nleaf();
@@ -878,13 +285,22 @@ static void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box
   HIP_OK(hipGetLastError());
 }
 
-static void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
-                            hipStream_t st) {
+void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                     hipStream_t st) {
   const int64_t n = rows * cols;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
   if (n == 0) return;
   hipLaunchKernelGGL(to_float_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
   HIP_OK(hipGetLastError());
+}
+
+// FP32 copies of the per-tree operands for the mixed paths (made once).
+void ensure_mixed_operands(Tree* t, hipStream_t st) {
+  DeviceState* ds = t->dev;
+  if (ds->Of.p) return;
+  ds->Of.alloc(ds->O.n);
+  ds->opsf.alloc(ds->ops.n);
+  launch_to_float(ds->O.p, 0, ds->Of.p, 0, 1, int64_t(ds->O.n), st);
 }
 
 void device_free(Tree* t) {
@@ -993,11 +409,7 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
     }
     if (!t->dev) upload_tree(t);
     DeviceState* ds = t->dev;
-    if (mixed && !ds->Of.p) {   // FP32 copies of the per-tree operands (once)
-      ds->Of.alloc(ds->O.n);
-      ds->opsf.alloc(ds->ops.n);
-      launch_to_float(ds->O.p, 0, ds->Of.p, 0, 1, int64_t(ds->O.n), st);
-    }
+    if (mixed) ensure_mixed_operands(t, st);
     const size_t es = mixed ? 4 : 8;
     const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es);
     setup_workspace(t, jb, ni, prec);

@@ -1,0 +1,543 @@
+// Device code of the far-field exchange: descriptors, FP64 operator
+// generation, tile-level GEMM and translation routines (shared by the
+// per-stage kernels and the persistent batched kernel), reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "occk_internal.hpp"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace occk {
+
+// --------------------------------------------------------------------------
+// device-side descriptors
+// --------------------------------------------------------------------------
+struct GemmDesc {       // element types follow the kernel's mode (output: OutT)
+  const void* A;       // A(m,k) = A[m*sam + k*sak]
+  int64_t sam, sak;
+  const void* B;       // B(k,n) = B[k*ldb + n]                (gidx == nullptr)
+  int64_t ldb;
+  const int32_t* gidx; // B(k,n) = Cuser[gidx[k]*ldcu + boff + n] (gather from C)
+  void* C;             // C(m,n) = C[m*ldc + n]
+  int64_t ldc;
+  int32_t M, N, K, pad;
+};
+struct GemmTile {
+  int32_t prob, mt, nt, pad;
+};
+struct OpParam {
+  int32_t type, weighted;
+  double d[3];
+};
+
+__host__ __device__ static inline int mtiles_of(int Q) { return (Q + 15) / 16; }
+__host__ __device__ static inline int ksteps_of(int Q) { return (Q + 3) / 4; }
+static inline int64_t opsize_of(int Q) { return int64_t(mtiles_of(Q)) * ksteps_of(Q) * 64; }
+
+// --------------------------------------------------------------------------
+// operator generation (FP64, one workgroup per operator)
+// --------------------------------------------------------------------------
+struct Cplx {
+  double re, im;
+};
+__device__ inline Cplx cmul(Cplx a, Cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline Cplx cscale(Cplx a, double s) { return {a.re * s, a.im * s}; }
+
+// table index for 0 <= m <= l
+__device__ inline int tix(int l, int m) { return l * (l + 1) / 2 + m; }
+
+// X_{l,m} for any sign of m from the m >= 0 table: X_{l,-m} = (-1)^m conj(X_{l,m})
+__device__ inline Cplx tget(const Cplx* tab, int l, int m) {
+  if (m >= 0) return tab[tix(l, m)];
+  Cplx v = tab[tix(l, -m)];
+  v.im = -v.im;
+  if ((-m) & 1) { v.re = -v.re; v.im = -v.im; }
+  return v;
+}
+
+// regular O_{l,m}(v), l <= L (Eq. 4a):
+//   O_{m,m} = -(x - i y)/(2m) O_{m-1,m-1},  O_{m+1,m} = z O_{m,m},
+//   O_{l+1,m} = ((2l+1) z O_{l,m} - r^2 O_{l-1,m}) / ((l+1)^2 - m^2)
+static __device__ void regular_table(int L, const double* v, Cplx* tab) {
+  const double x = v[0], y = v[1], z = v[2], r2 = x * x + y * y + z * z;
+  tab[0] = {1.0, 0.0};
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) tab[tix(m, m)] = cscale(cmul({x, -y}, tab[tix(m - 1, m - 1)]), -1.0 / (2.0 * m));
+    if (m + 1 <= L) tab[tix(m + 1, m)] = cscale(tab[tix(m, m)], z);
+    for (int l = m + 1; l + 1 <= L; ++l) {
+      const double inv = 1.0 / double((l + 1) * (l + 1) - m * m);
+      const Cplx a = tab[tix(l, m)], b = tab[tix(l - 1, m)];
+      tab[tix(l + 1, m)] = {((2 * l + 1) * z * a.re - r2 * b.re) * inv, ((2 * l + 1) * z * a.im - r2 * b.im) * inv};
+    }
+  }
+}
+
+// irregular M_{l,m}(v), l <= L (Eq. 4b):
+//   M_{0,0} = 1/r,  M_{m,m} = -(2m-1)(x + i y)/r^2 M_{m-1,m-1},
+//   M_{m+1,m} = (2m+1) z M_{m,m}/r^2,
+//   M_{l+1,m} = ((2l+1) z M_{l,m} - (l^2 - m^2) M_{l-1,m}) / r^2
+static __device__ void irregular_table(int L, const double* v, Cplx* tab) {
+  const double x = v[0], y = v[1], z = v[2], r2 = x * x + y * y + z * z;
+  const double ir2 = 1.0 / r2;
+  tab[0] = {1.0 / sqrt(r2), 0.0};
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) tab[tix(m, m)] = cscale(cmul({x, y}, tab[tix(m - 1, m - 1)]), -(2.0 * m - 1.0) * ir2);
+    if (m + 1 <= L) tab[tix(m + 1, m)] = cscale(tab[tix(m, m)], (2 * m + 1) * z * ir2);
+    for (int l = m + 1; l + 1 <= L; ++l) {
+      const Cplx a = tab[tix(l, m)], b = tab[tix(l - 1, m)];
+      const double c = double(l * l - m * m);
+      tab[tix(l + 1, m)] = {((2 * l + 1) * z * a.re - c * b.re) * ir2, ((2 * l + 1) * z * a.im - c * b.im) * ir2};
+    }
+  }
+}
+
+// complex coefficient c(l,m; l',m') of one translation
+__device__ inline Cplx coef(int type, const Cplx* tab, int l, int m, int lp, int mp) {
+  if (type == kOpM2M) {  // O_{l-l', m-m'}(d)
+    if (lp > l || abs(m - mp) > l - lp) return {0.0, 0.0};
+    return tget(tab, l - lp, m - mp);
+  }
+  if (type == kOpL2L) {  // O_{l'-l, m'-m}(d)
+    if (lp < l || abs(mp - m) > lp - l) return {0.0, 0.0};
+    return tget(tab, lp - l, mp - m);
+  }
+  Cplx v = tget(tab, l + lp, m + mp);  // (-1)^l M_{l+l', m+m'}(R)
+  if (l & 1) { v.re = -v.re; v.im = -v.im; }
+  return v;
+}
+
+// real component q -> (l, m, part): part 0 = (l,0) or Re, 1 = Im
+__device__ inline void decode(int q, int& l, int& m, int& part) {
+  l = 0;
+  while ((l + 1) * (l + 1) <= q) ++l;
+  const int k = q - l * l;
+  if (k == 0) { m = 0; part = 0; }
+  else { m = (k + 1) / 2; part = (k & 1) ? 0 : 1; }
+}
+
+// Real-form matrix entry T[row][col] of a translation acting on real-form
+// vectors (m >= 0 components; negative m implied by X_{-m} = (-1)^m conj X_m).
+static __device__ double real_entry(int type, const Cplx* tab, int row, int col) {
+  int l, m, pr, lp, mu, pc;
+  decode(row, l, m, pr);
+  decode(col, lp, mu, pc);
+  const Cplx z1 = coef(type, tab, l, m, lp, mu);
+  if (mu == 0) return pr == 0 ? z1.re : z1.im;
+  Cplx z2 = coef(type, tab, l, m, lp, -mu);
+  if (mu & 1) { z2.re = -z2.re; z2.im = -z2.im; }
+  if (pc == 0) {  // coefficient of Re(x)
+    const Cplx s{z1.re + z2.re, z1.im + z2.im};
+    return pr == 0 ? s.re : s.im;
+  }
+  const Cplx d{z1.re - z2.re, z1.im - z2.im};  // coefficient of Im(x)
+  return pr == 0 ? -d.im : d.re;
+}
+
+// L2P weights folded into leaf-level operators: K = 2 sum_lm O^{rj} Mloc^{ij}
+// = sum_q w_q H_q Mloc_q with w = 2 for (l,0), 4 for Re, -4 for Im rows.
+__device__ inline double l2p_weight(int q) {
+  int l, m, p;
+  decode(q, l, m, p);
+  if (m == 0) return 2.0;
+  return p == 0 ? 4.0 : -4.0;
+}
+
+// ops layout ("fragment order" of the FP64/FP32 MFMA A operand): element
+// ((mt*KS + ks)*64 + lane) holds T[mt*16 + lane%16][ks*4 + lane/16].
+// Generates one operator with nthreads threads (thread index tid); tab is a
+// shared table of at least (2L+1)(2L+2)/2 entries.  The FP64 result is also
+// written rounded to FP32 when outf is non-null.
+static __device__ void opgen_one(const OpParam& p, double* out, float* outf, int L, int Q, Cplx* tab, int tid,
+                          int nthreads) {
+  if (tid == 0) {
+    if (p.type == kOpM2L) irregular_table(2 * L, p.d, tab);
+    else regular_table(L, p.d, tab);
+  }
+  __syncthreads();
+  const int MT = mtiles_of(Q), KS = ksteps_of(Q);
+  for (int e = tid; e < MT * KS * 64; e += nthreads) {
+    const int lane = e & 63;
+    const int frag = e >> 6;
+    const int mt = frag / KS, ks = frag % KS;
+    const int row = mt * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
+    double v = 0.0;
+    if (row < Q && col < Q) {
+      v = real_entry(p.type, tab, row, col);
+      if (p.weighted) v *= l2p_weight(row);
+    }
+    if (out) out[e] = v;
+    if (outf) outf[e] = float(v);
+  }
+  __syncthreads();
+}
+
+static __global__ __launch_bounds__(64) void opgen_kernel(const OpParam* __restrict__ params, double* __restrict__ ops,
+                                                   int L, int Q) {
+  __shared__ Cplx tab[(2 * kMaxL + 1) * (2 * kMaxL + 2) / 2];
+  const int64_t sz = int64_t(mtiles_of(Q)) * ksteps_of(Q) * 64;
+  opgen_one(params[blockIdx.x], ops + int64_t(blockIdx.x) * sz, nullptr, L, Q, tab, threadIdx.x, 64);
+}
+
+// --------------------------------------------------------------------------
+// arithmetic modes of the contractions
+//   kModeF64    FP64 operands, v_mfma_f64_16x16x4f64
+//   kModeF32    FP32 operands, v_mfma_f32_16x16x4f32, FP32 accumulation
+//   kModeBF16x3 FP32 operands split as x = hi + lo (bf16 each, round to
+//               nearest even); a*b ~ hi_a hi_b + hi_a lo_b + lo_a hi_b on
+//               v_mfma_f32_16x16x32_bf16 with FP32 accumulation
+// MFMA layouts (checked with occk_debug_mfma_probe):
+//   f64/f32 16x16x4: A[i][k] in lane i + 16k, B[k][j] in lane j + 16k;
+//   bf16 16x16x32: A[i][k] in lane i + 16(k/8) element k%8, B likewise;
+//   f64 D[i][j] in lane j + 16(i%4) element i/4 (rows interleaved),
+//   f32 D[i][j] in lane j + 16(i/4) element i%4.
+// --------------------------------------------------------------------------
+//   kModeBF16x6 three-way split x = hi + mid + lo; six products
+//               (hi hi, hi mid, mid hi, hi lo, lo hi, mid mid), ~2^-24 relative
+enum { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16x6 = 3 };
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s8v __attribute__((ext_vector_type(8)));
+
+template <int MODE> struct ModeT;
+template <> struct ModeT<kModeF64> { using T = double; using Acc = d4; static constexpr int KT = 16; };
+template <> struct ModeT<kModeF32> { using T = float; using Acc = f4; static constexpr int KT = 16; };
+template <> struct ModeT<kModeBF16x3> { using T = float; using Acc = f4; static constexpr int KT = 32; };
+template <> struct ModeT<kModeBF16x6> { using T = float; using Acc = f4; static constexpr int KT = 32; };
+
+__device__ inline uint32_t bf16_rne_bits(float x) {   // bf16 bits (in the low half) of x, round to nearest even
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// x[e] -> hi[e] + lo[e] as bf16 vectors
+__device__ inline void split8(const float* x, bf16x8& hi, bf16x8& lo) {
+  s8v h, l;
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t hb = bf16_rne_bits(x[e]);
+    const float hf = __uint_as_float(hb << 16);
+    h[e] = short(hb);
+    l[e] = short(bf16_rne_bits(x[e] - hf));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+// x[e] -> hi[e] + mid[e] + lo[e] as bf16 vectors
+__device__ inline void split8x3(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+  s8v h, m, l;
+  for (int e = 0; e < 8; ++e) {
+    const uint32_t hb = bf16_rne_bits(x[e]);
+    const float r1 = x[e] - __uint_as_float(hb << 16);
+    const uint32_t mb = bf16_rne_bits(r1);
+    const float r2 = r1 - __uint_as_float(mb << 16);
+    h[e] = short(hb);
+    m[e] = short(mb);
+    l[e] = short(bf16_rne_bits(r2));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  mid = __builtin_bit_cast(bf16x8, m);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+__device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+// output row of accumulator element r for lane group g = lane/16 inside a 16-row tile
+template <class Acc> __device__ inline int acc_row(int g, int r);
+template <> __device__ inline int acc_row<d4>(int g, int r) { return g + 4 * r; }
+template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; }
+
+// --------------------------------------------------------------------------
+// grouped GEMM: C(m,n) (+)= sum_k A(m,k) B(k,n) over a list of problems;
+// 64x64 output tile per 256-thread block, each wave a 32x32 quadrant (2x2
+// MFMA tiles), K staged through LDS in steps of KT.
+// --------------------------------------------------------------------------
+template <int MODE>
+struct GemmSmem {
+  typename ModeT<MODE>::T A[ModeT<MODE>::KT][64 + 1];
+  typename ModeT<MODE>::T B[ModeT<MODE>::KT][64 + 1];
+};
+
+template <int MODE, bool A_KCONTIG, class OutT>
+__device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
+                          int64_t ldcu, int64_t boff, int64_t blim, int accumulate, GemmSmem<MODE>& sm) {
+  using T = typename ModeT<MODE>::T;
+  using Acc = typename ModeT<MODE>::Acc;
+  constexpr int KT = ModeT<MODE>::KT;
+  constexpr int E = KT / 4;          // elements per thread per operand tile
+  auto& As = sm.A;
+  auto& Bs = sm.B;
+  const T* A = static_cast<const T*>(d.A);
+  const int m0 = mt * 64, n0 = nt * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  Acc acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+  // FP32 accumulators feeding an FP64 output are flushed into FP64 registers
+  // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT terms.
+  constexpr bool kFlush = std::is_same<OutT, double>::value && MODE != kModeF64;
+  constexpr int FLUSH = 8;
+  double acc64[kFlush ? 2 : 1][kFlush ? 2 : 1][kFlush ? 4 : 1];
+  if constexpr (kFlush)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  int ktile = 0;
+  // A: k-contiguous -> row am = tid/4, k = (tid%4)*E ..; m-contiguous -> k = tid/(64/E), m = (tid%(64/E))*E ..
+  // B: k = tid/(64/E), n = (tid%(64/E))*E ..
+  constexpr int TPR = 64 / E;
+  const int bk = tid / TPR, bn = (tid % TPR) * E;
+  T ra[E], rb[E];
+  auto load = [&](int k0) {
+    if (A_KCONTIG) {
+      const int am = tid >> 2, ak = (tid & 3) * E;
+      const int gm = m0 + am;
+      for (int u = 0; u < E; ++u) {
+        const int gk = k0 + ak + u;
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
+      }
+    } else {
+      const int ak = tid / TPR, am = (tid % TPR) * E;
+      const int gk = k0 + ak;
+      for (int u = 0; u < E; ++u) {
+        const int gm = m0 + am + u;
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
+      }
+    }
+    const int gk = k0 + bk;
+    if (gk < d.K) {
+      if (d.gidx) {
+        const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
+        for (int u = 0; u < E; ++u) {
+          const int gn = n0 + bn + u;
+          rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
+        }
+      } else {
+        const T* row = static_cast<const T*>(d.B) + int64_t(gk) * d.ldb;
+        for (int u = 0; u < E; ++u) {
+          const int gn = n0 + bn + u;
+          rb[u] = (gn < d.N) ? row[gn] : T(0);
+        }
+      }
+    } else {
+      for (int u = 0; u < E; ++u) rb[u] = T(0);
+    }
+  };
+  auto store = [&]() {
+    if (A_KCONTIG) {
+      const int am = tid >> 2, ak = (tid & 3) * E;
+      for (int u = 0; u < E; ++u) As[ak + u][am] = ra[u];
+    } else {
+      const int ak = tid / TPR, am = (tid % TPR) * E;
+      for (int u = 0; u < E; ++u) As[ak][am + u] = ra[u];
+    }
+    for (int u = 0; u < E; ++u) Bs[bk][bn + u] = rb[u];
+  };
+
+  load(0);
+  for (int k0 = 0; k0 < d.K; k0 += KT) {
+    store();
+    __syncthreads();
+    if (k0 + KT < d.K) load(k0 + KT);
+    if constexpr (MODE == kModeBF16x6) {
+      const int kb = 8 * (lane >> 4);
+      bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
+      for (int i = 0; i < 2; ++i) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
+        split8x3(x, ah[i], am[i], al[i]);
+      }
+      for (int j = 0; j < 2; ++j) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
+        split8x3(x, bh[j], bm[j], bl[j]);
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {   // smallest terms first
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else if constexpr (MODE == kModeBF16x3) {
+      const int kb = 8 * (lane >> 4);
+      bf16x8 ah[2], al[2], bh[2], bl[2];
+      for (int i = 0; i < 2; ++i) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
+        split8(x, ah[i], al[i]);
+      }
+      for (int j = 0; j < 2; ++j) {
+        float x[8];
+        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
+        split8(x, bh[j], bl[j]);
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        T a[2], b[2];
+        for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+      }
+    }
+    __syncthreads();
+    if constexpr (kFlush) {
+      if (++ktile == FLUSH) {
+        ktile = 0;
+        for (int i = 0; i < 2; ++i)
+          for (int j = 0; j < 2; ++j) {
+            for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
+            acc[i][j] = Acc{};
+          }
+      }
+    }
+  }
+  if constexpr (kFlush)
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j)
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
+  OutT* Cout = static_cast<OutT*>(d.C);
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + (lane & 15);
+      if (col >= d.N) continue;
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
+        if (row >= d.M) continue;
+        OutT* c = Cout + int64_t(row) * d.ldc + col;
+        OutT v;
+        if constexpr (kFlush) v = OutT(acc64[i][j][r]);
+        else v = OutT(acc[i][j][r]);
+        *c = accumulate ? *c + v : v;
+      }
+    }
+  __syncthreads();   // LDS is reused by the caller's next tile
+}
+
+template <int MODE, bool A_KCONTIG, class OutT>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
+                                                   const GemmTile* __restrict__ tiles,
+                                                   const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
+                                                   int64_t boff, int64_t blim, int accumulate) {
+  __shared__ GemmSmem<MODE> sm;
+  const GemmTile tl = tiles[blockIdx.x];
+  gemm_tile<MODE, A_KCONTIG, OutT>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, boff, blim, accumulate, sm);
+}
+
+// --------------------------------------------------------------------------
+// translation: out[t] = sum_{e in CSR(t)} T[op_e] * data[src_e]   (overwrite)
+// Each box is Q rows x ncol columns.  Block = 4 waves x 64 columns; each wave
+// holds MT 16-row tiles x 4 column tiles of accumulators.  Blocks are
+// renumbered so that each XCD walks contiguous (column tile, target) ranges:
+// neighbouring targets then share their sources in that XCD's L2.
+// T = double: FP64 MFMA; T = float: FP32 MFMA.
+// --------------------------------------------------------------------------
+template <class T, int MT>
+__device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t ncol, int Q, int KS,
+                               const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
+                               const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
+                               const T* __restrict__ ops, int t, int64_t ct) {
+  using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t colbase = ct * 256 + wave * 64;
+  Acc acc[MT][4];
+  for (int i = 0; i < MT; ++i)
+    for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
+  const int64_t opsz = int64_t(MT) * KS * 64;
+  const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
+  for (int e = e0; e < e1; ++e) {
+    const T* X = data + int64_t(src_box[e]) * box_stride;
+    const T* Tm = ops + int64_t(src_op[e]) * opsz;
+    for (int ks = 0; ks < KS; ++ks) {
+      const int row = ks * 4 + (lane >> 4);
+      T b[4];
+      for (int j = 0; j < 4; ++j) {
+        const int64_t col = colbase + j * 16 + (lane & 15);
+        b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : T(0);
+      }
+      for (int i = 0; i < MT; ++i) {
+        const T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a, b[j], acc[i][j]);
+      }
+    }
+  }
+  T* Y = data + int64_t(tgt_box[t]) * box_stride;
+  for (int i = 0; i < MT; ++i)
+    for (int j = 0; j < 4; ++j) {
+      const int64_t col = colbase + j * 16 + (lane & 15);
+      if (col >= ncol) continue;
+      for (int r = 0; r < 4; ++r) {
+        const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
+        if (row < Q) Y[int64_t(row) * ncol + col] = T(acc[i][j][r]);
+      }
+    }
+}
+
+template <class T, int MT>
+__global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
+                                                        int Q, int KS, const int32_t* __restrict__ tgt_box,
+                                                        const int32_t* __restrict__ src_ptr,
+                                                        const int32_t* __restrict__ src_box,
+                                                        const int32_t* __restrict__ src_op,
+                                                        const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  translate_tile<T, MT>(data, box_stride, ncol, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
+                        int(logical % ntgt), logical / ntgt);
+}
+
+// out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
+static __global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
+                                int64_t rows, int64_t cols) {
+  const int64_t n = rows * cols;
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t r = e / cols, c = e % cols;
+    out[r * ldo + c] = float(in[r * ldi + c]);
+  }
+}
+
+// K[r, i0 + i] = (acc ? K : 0) + sum_{e in occ(r)} KB[row_e, i]   (fixed order)
+__device__ inline void reduce_elem(const double* __restrict__ KB, int64_t ni, const int32_t* __restrict__ occ_ptr,
+                                   const int32_t* __restrict__ occ_row, double* __restrict__ K, int64_t ldk, int i0,
+                                   int accumulate, int r, int64_t i) {
+  double s = 0.0;
+  for (int e = occ_ptr[r]; e < occ_ptr[r + 1]; ++e) s += KB[int64_t(occ_row[e]) * ni + i];
+  double* k = K + int64_t(r) * ldk + i0 + i;
+  *k = accumulate ? *k + s : s;
+}
+
+static __global__ __launch_bounds__(256) void reduce_kernel(const double* __restrict__ KB, int64_t ni,
+                                                     const int32_t* __restrict__ occ_ptr,
+                                                     const int32_t* __restrict__ occ_row, double* __restrict__ K,
+                                                     int64_t ldk, int i0, int accumulate) {
+  const int r = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= ni) return;
+  reduce_elem(KB, ni, occ_ptr, occ_row, K, ldk, i0, accumulate, r, i);
+}
+
+static __global__ void zero_cols_kernel(double* __restrict__ K, int64_t ldk, int i0, int64_t ni) {
+  const int r = blockIdx.y;
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < ni) K[int64_t(r) * ldk + i0 + i] = 0.0;
+}
+
+}  // namespace occk

@@ -66,6 +66,14 @@ EXPORTS = {
                                 ct.c_void_p]),
     "occk_debug_mfma_probe": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]),
     "occk_debug_buffer": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(ct.c_int64)]),
+    "occk_batch_create": (ct.c_int32, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(_Opts),
+                                       ct.POINTER(ct.c_void_p)]),
+    "occk_batch_run": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "occk_batch_tune": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                     ct.c_void_p]),
+    "occk_batch_shape": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_void_p, ct.c_int32]),
+    "occk_batch_config": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
+    "occk_batch_free": (ct.c_int32, [ct.c_void_p]),
     "occk_workspace_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)]),
     "occk_profile_enable": (ct.c_int32, [ct.c_void_p, ct.c_int32]),
     "occk_profile_read": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
@@ -260,3 +268,60 @@ def debug_mfma_probe(kind: int, ia: int, ka: int, jb: int) -> np.ndarray:
     out = np.zeros((64, 4))
     _check(lib().occk_debug_mfma_probe(int(kind), int(ia), int(ka), int(jb), out.ctypes.data))
     return out
+
+
+class Batch:
+    """Many systems in one persistent launch (occk_batch_*)."""
+
+    def __init__(self, trees, noccs, precision: int = PREC_FP32):
+        self.trees = list(trees)
+        arr = (ct.c_void_p * len(self.trees))(*[t.handle.value for t in self.trees])
+        no = np.ascontiguousarray(noccs, dtype=np.int32)
+        opts = _Opts(int(precision), RANK_FIXED, None, 0, 0)
+        h = ct.c_void_p()
+        _check(lib().occk_batch_create(len(self.trees), ct.cast(arr, ct.c_void_p), no.ctypes.data, ct.byref(opts),
+                                       ct.byref(h)))
+        self._h = h
+        self.noccs = [int(x) for x in no]
+
+    def _io(self, Cs, Ks):
+        n = len(self.trees)
+        self._keep = (
+            (ct.c_void_p * n)(*[c.data_ptr() for c in Cs]),
+            np.array([c.stride(0) for c in Cs], np.int64),
+            (ct.c_void_p * n)(*[k.data_ptr() for k in Ks]),
+            np.array([k.stride(0) for k in Ks], np.int64),
+        )
+        a, b, c, d = self._keep
+        return ct.cast(a, ct.c_void_p), b.ctypes.data, ct.cast(c, ct.c_void_p), d.ctypes.data
+
+    def run(self, Cs, Ks, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().occk_batch_run(self._h, *self._io(Cs, Ks), ct.c_void_p(stream.cuda_stream)))
+
+    def tune(self, Cs, Ks, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        ch = np.zeros(3, np.int32)
+        _check(lib().occk_batch_tune(self._h, *self._io(Cs, Ks), ct.c_void_p(stream.cuda_stream), ch.ctypes.data))
+        return tuple(int(x) for x in ch)
+
+    def config(self):
+        c = np.zeros(6, np.int32)
+        _check(lib().occk_batch_config(self._h, c.ctypes.data))
+        return dict(blocks_per_cu=int(c[0]), gemm_group=int(c[1]), trans_group=int(c[2]), ntasks=int(c[3]),
+                    nstage=int(c[4]), max_blocks_per_cu=int(c[5]))
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _check(lib().occk_batch_free(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

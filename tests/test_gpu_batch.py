@@ -1,0 +1,114 @@
+"""Many systems in one persistent launch (occk_batch_*).
+
+* FP64 batched K of every system matches the oracle to 1e-8 (normwise).
+* Each precision's batched K matches occk_far_K of the same precision
+  (different j batching, so only the summation order differs).
+* The autotuner returns a valid configuration and keeps results correct.
+* A standalone call on one of the trees (which replaces its workspace)
+  before a batched run is handled: the plan rebuilds its tables.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle.fmm import Setup, far_K as oracle_far_K
+
+from conftest import rel
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(6, 40), (9, 41), (12, 42), (15, 43), (7, 44)]   # (molecules, seed), uneven
+
+
+@pytest.fixture(scope="module")
+def systems():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_05353_amd import occk
+    out = []
+    for n, seed in SIZES:
+        wl = workloads.water_cluster(n, seed, depth=3)
+        C = wl.orbitals()
+        tr = occk.Tree(wl.system, wl.params)
+        if tr.info.lmin < 0:
+            continue
+        out.append((wl, C, tr))
+    assert len(out) >= 3
+    return out
+
+
+def _io(systems):
+    import torch
+    Cs = [torch.from_numpy(C).cuda() for wl, C, tr in systems]
+    Ks = [torch.full((wl.system.nbasis, C.shape[1]), 7.0, dtype=torch.float64, device="cuda")
+          for wl, C, tr in systems]
+    return Cs, Ks
+
+
+def test_batched_fp64_matches_oracle(systems):
+    import torch
+    from paper_1708_05353_amd import occk
+    Cs, Ks = _io(systems)
+    b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], occk.PREC_FP64)
+    print("[batch] fp64 run", flush=True)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    print("[batch] fp64 done", flush=True)
+    for (wl, C, tr), K in zip(systems, Ks):
+        ref = oracle_far_K(Setup(wl.system, wl.params), C)
+        assert rel(K.cpu().numpy(), ref) <= 1e-8
+    b.free()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 3, 2], ids=["fp64", "fp32", "bf16x6", "bf16x3"])
+def test_batched_equals_standalone(systems, prec):
+    import torch
+    from paper_1708_05353_amd import occk
+    Cs, Ks = _io(systems)
+    b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], prec)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    got = [K.cpu().numpy() for K in Ks]
+    b.free()
+    for (wl, C, tr), Cd, g in zip(systems, Cs, got):
+        K1 = torch.zeros_like(Cd)
+        occk.far_K(tr, Cd, K1, precision=prec, jblock=4)
+        torch.cuda.synchronize()
+        tol = 1e-12 if prec == 0 else 1e-6
+        assert rel(g, K1.cpu().numpy()) <= tol, prec
+
+
+def test_autotune_then_run(systems):
+    import torch
+    from paper_1708_05353_amd import occk
+    Cs, Ks = _io(systems)
+    b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], occk.PREC_FP32)
+    choice = b.tune(Cs, Ks)
+    assert choice[0] in (1, 2, 4) and choice[1] in (1, 2) and choice[2] in (1, 4)
+    cfg = b.config()
+    assert (cfg["blocks_per_cu"], cfg["gemm_group"], cfg["trans_group"]) == choice
+    for K in Ks:
+        K.fill_(3.0)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    wl, C, tr = systems[0]
+    ref = oracle_far_K(Setup(wl.system, wl.params), C)
+    assert rel(Ks[0].cpu().numpy(), ref) <= 1e-6
+    b.free()
+
+
+def test_plan_survives_standalone_call(systems):
+    import torch
+    from paper_1708_05353_amd import occk
+    Cs, Ks = _io(systems)
+    b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], occk.PREC_FP32)
+    wl, C, tr = systems[1]
+    K1 = torch.zeros_like(Cs[1])
+    occk.far_K(tr, Cs[1], K1, precision=occk.PREC_FP32, jblock=3)   # replaces that tree's workspace
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    ref = oracle_far_K(Setup(wl.system, wl.params), C)
+    assert rel(Ks[1].cpu().numpy(), ref) <= 1e-6
+    assert rel(K1.cpu().numpy(), ref) <= 1e-6
+    b.free()
