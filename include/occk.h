@@ -117,7 +117,7 @@ typedef struct occk_tree_info_t {
 
 typedef struct occk_far_opts {
   int32_t precision;           /* OCCK_PREC_*                                  */
-  int32_t rank_mode;           /* OCCK_RANK_*; LEARNED needs selector         */
+  int32_t rank_mode;           /* OCCK_RANK_*; LEARNED needs a live selector  */
   const occk_selector* selector;
   int32_t jblock;              /* occupied j columns per batch, 0 = automatic */
   int32_t accumulate;          /* 0: K[:, i0:i1] = K^ff, 1: K[:, i0:i1] += K^ff */
@@ -233,6 +233,79 @@ int32_t occk_batch_config(const occk_batch* plan, int32_t* config);
 /* Frees the plan (after a device synchronisation); NULL is accepted. */
 int32_t occk_batch_free(occk_batch* plan);
 
+/* ---- learned rank per interaction-list translation ---- */
+
+/* The selector is an MLP (24 features -> 64 -> 64 -> 8 outputs, ReLU) that
+ * predicts, for one interaction-list translation (Eq. 17b), the relative
+ * truncation error e_p of keeping only l, l' <= p, as log10(e_p)/4 for
+ * p = 1..8.  In OCCK_RANK_LEARNED mode every interaction-list translation of
+ * occk_far_K runs at the smallest p whose prediction is <= (log10_tau -
+ * margin)/4, and at lmax when none is (the fixed-rank method is the
+ * fallback); upward and downward translations always use lmax.  Features
+ * (index: value): 0 level/depth; 1 |R|/(h(2ws+2)); 2 rho; 3 log10 rho;
+ * 4..11 log10(n_l/(n_0 h^l))/4, l = 1..8 (0 beyond lmax); 12..19 l log10(rho)/4;
+ * 20 log10(n_0)/10; 21 ndim/3; 22 max_d|R_d|/(h(2ws+2)); 23 log10((n_0/|R|)/S)/4
+ * with S the sum of n_0/|R| over the target box's interaction list.  Here R is
+ * the box-centre displacement, h the box size of the level, rho =
+ * (sqrt(ndim) h/2)/|R| and n_l the norm of the source box's order-l multipole
+ * components over a column sketch of the current j batch.  Weights: flat FP32 vector
+ * W1[64][24], b1[64], W2[64][64], b2[64], W3[8][64], b3[8]. */
+#define OCCK_SELECTOR_NFEAT 24
+#define OCCK_SELECTOR_NOUT 8
+#define OCCK_SELECTOR_NPARAM 6280
+
+/* New selector with seeded He-normal weights (zero biases), rule
+ * log10_tau = -6, margin = 1. */
+int32_t occk_selector_create(int32_t seed, occk_selector** out);
+int32_t occk_selector_free(occk_selector* sel);
+/* Host copies of the flat FP32 weights [OCCK_SELECTOR_NPARAM]. */
+int32_t occk_selector_get_weights(const occk_selector* sel, float* theta);
+int32_t occk_selector_set_weights(occk_selector* sel, const float* theta);
+int32_t occk_selector_set_rule(occk_selector* sel, float log10_tau, float margin);
+
+/* Training data generated by the method: runs the FP64 half transform, Omega
+ * and upward passes of occk_far_K for the j batch [j0, j1) (all i), then, for
+ * up to max_samples interaction-list translations drawn with the seed, the
+ * features and the targets log10(max(e_p, 1e-16))/4, p = 1..8, where e_p is the
+ * Frobenius norm of the difference between the rank-p and the full-rank
+ * translation of the source box's multipoles, divided by the norm of the
+ * target box's complete local expansion (all sources, full rank), over 64
+ * sketch columns.  feat
+ * [max_samples*24] and target [max_samples*8] are host arrays; *nsamples
+ * receives the count.  Synchronous. */
+int32_t occk_selector_collect(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t j0, int32_t j1,
+                              int32_t max_samples, int32_t seed, float* feat, float* target, int32_t* nsamples,
+                              void* hip_stream);
+
+/* Adam on the mean squared error over (feat, target) host arrays of n
+ * samples: epochs passes in seeded random order, minibatches of batch, step
+ * size lr; FP32 forward/backward kernels on the GPU.  loss[epochs] (host, may be
+ * NULL) receives each epoch's mean loss.  Synchronous. */
+int32_t occk_selector_train(occk_selector* sel, const float* feat, const float* target, int32_t n, int32_t epochs,
+                            int32_t batch, float lr, int32_t seed, float* loss, void* hip_stream);
+
+/* Full-batch loss and gradient [OCCK_SELECTOR_NPARAM] at the current weights
+ * (FP32 kernels; for checking the backward pass).  Synchronous. */
+int32_t occk_selector_grad(occk_selector* sel, const float* feat, const float* target, int32_t n, float* loss,
+                           float* grad, void* hip_stream);
+
+/* BF16 inference on host features: outputs [n*8] and ranks [n] by the rule
+ * (either may be NULL), ranks capped at lmax.  Synchronous. */
+int32_t occk_selector_predict(occk_selector* sel, const float* feat, int32_t n, int32_t lmax, float* out,
+                              int32_t* rank, void* hip_stream);
+
+/* Weights file: "OCCKSEL1", int32 dims {24, 64, 8}, float {log10_tau, margin},
+ * the FP32 weights, uint64 FNV-1a checksum of the weight bytes.  load rejects
+ * a wrong header, checksum or non-finite weight (EINVAL / ENONFINITE) and then
+ * leaves the selector unchanged. */
+int32_t occk_selector_save(const occk_selector* sel, const char* path);
+int32_t occk_selector_load(occk_selector* sel, const char* path);
+
+/* Histogram hist[9] of the ranks chosen for interaction-list translations by
+ * the learned calls since the previous read, one count per translation per j
+ * batch (synchronises; then clears). */
+int32_t occk_rank_stats(occk_tree* tree, int64_t* hist);
+
 /* ---- per-kernel timing ---- */
 
 /* kernel classes of one occk_far_K call */
@@ -245,7 +318,8 @@ enum {
   OCCK_K_L2P = 5,     /* per-leaf K partials, Eq. (18)                          */
   OCCK_K_REDUCE = 6,  /* sum of the per-leaf partials into K                    */
   OCCK_K_CONVERT = 7, /* operand conversion of the mixed-precision paths       */
-  OCCK_K_NCLASS = 8
+  OCCK_K_SELECT = 8,  /* learned ranks: multipole norms, features, MLP         */
+  OCCK_K_NCLASS = 9
 };
 
 /* While enabled, every occk_far_K on the handle records a HIP event pair on

@@ -112,9 +112,20 @@ def _ranges(nocc, i_range, j_range):
     return i0, i1, j0, j1
 
 
+def truncate(T: np.ndarray, p: int) -> np.ndarray:
+    """Rank-p truncation of a square translation: only l <= p and l' <= p kept."""
+    n = (p + 1) * (p + 1)
+    out = np.zeros_like(T)
+    out[:n, :n] = T[:n, :n]
+    return out
+
+
 def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int = 64,
-          return_imag: bool = False):
-    """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM."""
+          return_imag: bool = False, m2l_rank=None):
+    """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM.
+
+    m2l_rank: optional int p (0 <= p <= L) applied to every interaction-list
+    translation (l, l' <= p), the uniform version of a per-interaction rank."""
     t, L = setup.tree, setup.L
     nocc = C.shape[1]
     i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
@@ -137,7 +148,8 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
     for lev in range(t.lmin, D + 1):
         for b, c in enumerate(t.boxes[lev]):
             for b2 in t.il[lev][b]:
-                m2l[(lev, b, b2)] = m2l_matrix(L, t.centre(lev, c) - t.centre(lev, t.boxes[lev][b2]))
+                T = m2l_matrix(L, t.centre(lev, c) - t.centre(lev, t.boxes[lev][b2]))
+                m2l[(lev, b, b2)] = T if m2l_rank is None else truncate(T, int(m2l_rank))
     for jb0 in range(j0, j1, jblock):
         jb1 = min(j1, jb0 + jblock)
         # Step 2: MO transforms at the leaves

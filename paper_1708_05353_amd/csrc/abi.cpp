@@ -25,6 +25,12 @@ static bool live(const Tree* t) {
 }
 
 static std::unordered_set<const void*> g_plans;
+static std::unordered_set<const void*> g_sels;
+
+static bool sel_live(const void* p) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return p && g_sels.count(p) && selector_live(p);
+}
 
 static bool plan_live(const void* p) {
   std::lock_guard<std::mutex> lk(g_mu);
@@ -230,8 +236,8 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
     set_error("occk_far_K: unknown rank_mode");
     return OCCK_EINVAL;
   }
-  if (o.rank_mode == OCCK_RANK_LEARNED && !o.selector) {
-    set_error("occk_far_K: LEARNED rank mode needs a selector");
+  if (o.rank_mode == OCCK_RANK_LEARNED && !sel_live(o.selector)) {
+    set_error("occk_far_K: LEARNED rank mode needs a live selector");
     return OCCK_ESTATE;
   }
   if (o.jblock < 0) {
@@ -435,6 +441,191 @@ int32_t occk_batch_free(occk_batch* plan) {
     g_plans.erase(plan);
   }
   return batch_free(plan);
+}
+
+int32_t occk_selector_create(int32_t seed, occk_selector** out) {
+  if (!out) {
+    set_error("occk_selector_create: out is NULL");
+    return OCCK_EINVAL;
+  }
+  *out = nullptr;
+  void* p = nullptr;
+  int32_t rc = OCCK_OK;
+  OCCK_GUARD_BEGIN
+  rc = selector_create(seed, &p);
+  OCCK_GUARD_END
+  if (rc != OCCK_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_sels.insert(p);
+  }
+  *out = reinterpret_cast<occk_selector*>(p);
+  return OCCK_OK;
+}
+
+int32_t occk_selector_free(occk_selector* sel) {
+  if (!sel) return OCCK_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_sels.count(sel)) {
+      set_error("occk_selector_free: selector is not live");
+      return OCCK_EHANDLE;
+    }
+    g_sels.erase(sel);
+  }
+  return selector_free(sel);
+}
+
+#define OCCK_SEL_CHECK(s)                          \
+  if (!sel_live(s)) {                              \
+    set_error("selector handle is not live");      \
+    return OCCK_EHANDLE;                           \
+  }
+
+int32_t occk_selector_get_weights(const occk_selector* sel, float* theta) {
+  OCCK_SEL_CHECK(sel)
+  if (!theta) {
+    set_error("theta is NULL");
+    return OCCK_EINVAL;
+  }
+  return selector_weights(const_cast<occk_selector*>(sel), theta, nullptr);
+}
+
+int32_t occk_selector_set_weights(occk_selector* sel, const float* theta) {
+  OCCK_SEL_CHECK(sel)
+  if (!theta) {
+    set_error("theta is NULL");
+    return OCCK_EINVAL;
+  }
+  for (int k = 0; k < OCCK_SELECTOR_NPARAM; ++k)
+    if (!std::isfinite(theta[k])) {
+      set_error("occk_selector_set_weights: non-finite weight");
+      return OCCK_ENONFINITE;
+    }
+  return selector_weights(sel, nullptr, theta);
+}
+
+int32_t occk_selector_set_rule(occk_selector* sel, float log10_tau, float margin) {
+  OCCK_SEL_CHECK(sel)
+  if (!std::isfinite(log10_tau) || !std::isfinite(margin)) {
+    set_error("occk_selector_set_rule: non-finite rule");
+    return OCCK_ENONFINITE;
+  }
+  selector_set_rule(sel, log10_tau, margin);
+  return OCCK_OK;
+}
+
+static int32_t check_samples(const float* X, const float* T, int32_t n, int nt) {
+  if (!X || (nt && !T) || n < 1) {
+    set_error("need n >= 1 and non-NULL sample arrays");
+    return OCCK_EINVAL;
+  }
+  for (int64_t k = 0; k < int64_t(n) * OCCK_SELECTOR_NFEAT; ++k)
+    if (!std::isfinite(X[k])) {
+      set_error("non-finite feature");
+      return OCCK_ENONFINITE;
+    }
+  for (int64_t k = 0; k < int64_t(n) * nt; ++k)
+    if (!std::isfinite(T[k])) {
+      set_error("non-finite target");
+      return OCCK_ENONFINITE;
+    }
+  return OCCK_OK;
+}
+
+int32_t occk_selector_train(occk_selector* sel, const float* feat, const float* target, int32_t n, int32_t epochs,
+                            int32_t batch, float lr, int32_t seed, float* loss, void* hip_stream) {
+  OCCK_SEL_CHECK(sel)
+  int32_t rc = check_samples(feat, target, n, OCCK_SELECTOR_NOUT);
+  if (rc != OCCK_OK) return rc;
+  if (epochs < 1 || batch < 1 || !(lr > 0.f) || !std::isfinite(lr)) {
+    set_error("occk_selector_train: need epochs >= 1, batch >= 1, lr > 0");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return selector_train(sel, feat, target, n, epochs, batch, lr, seed, loss, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_selector_grad(occk_selector* sel, const float* feat, const float* target, int32_t n, float* loss,
+                           float* grad, void* hip_stream) {
+  OCCK_SEL_CHECK(sel)
+  int32_t rc = check_samples(feat, target, n, OCCK_SELECTOR_NOUT);
+  if (rc != OCCK_OK) return rc;
+  if (!grad) {
+    set_error("grad is NULL");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return selector_grad(sel, feat, target, n, loss, grad, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_selector_predict(occk_selector* sel, const float* feat, int32_t n, int32_t lmax, float* out,
+                              int32_t* rank, void* hip_stream) {
+  OCCK_SEL_CHECK(sel)
+  int32_t rc = check_samples(feat, nullptr, n, 0);
+  if (rc != OCCK_OK) return rc;
+  if (lmax < 1 || lmax > 8) {
+    set_error("occk_selector_predict: lmax must be in [1, 8]");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return selector_predict(sel, feat, n, lmax, out, rank, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_selector_save(const occk_selector* sel, const char* path) {
+  OCCK_SEL_CHECK(sel)
+  if (!path) {
+    set_error("path is NULL");
+    return OCCK_EINVAL;
+  }
+  return selector_save(sel, path);
+}
+
+int32_t occk_selector_load(occk_selector* sel, const char* path) {
+  OCCK_SEL_CHECK(sel)
+  if (!path) {
+    set_error("path is NULL");
+    return OCCK_EINVAL;
+  }
+  return selector_load(sel, path);
+}
+
+int32_t occk_selector_collect(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t j0, int32_t j1,
+                              int32_t max_samples, int32_t seed, float* feat, float* target, int32_t* nsamples,
+                              void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_selector_collect: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!C || !feat || !target || !nsamples || max_samples < 1 || nocc < 1 || ldc < nocc ||
+      !(0 <= j0 && j0 < j1 && j1 <= nocc)) {
+    set_error("occk_selector_collect: bad arguments");
+    return OCCK_EINVAL;
+  }
+  if (t->lmin < 0) {
+    set_error("occk_selector_collect: the tree has no far field");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return selector_collect(t, C, ldc, nocc, j0, j1, max_samples, seed, feat, target, nsamples, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_rank_stats(occk_tree* tree, int64_t* hist) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_rank_stats: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!hist) {
+    set_error("hist is NULL");
+    return OCCK_EINVAL;
+  }
+  return rank_stats(t, hist);
 }
 
 }  // extern "C"

@@ -51,7 +51,13 @@ struct DevBuf {
 
 struct Pass {           // one translation launch
   int ntgt = 0;
+  int nent = 0;                    // CSR entries (sources over all targets)
   DevBuf<int32_t> tgt_box, src_ptr, src_box, src_op;
+  std::vector<int32_t> host_op;    // host copy of src_op
+  std::vector<int32_t> host_tgt;   // target (row) of each entry
+  DevBuf<int32_t> ent_tgt;         // device copy of host_tgt
+  DevBuf<int8_t> rank;             // per-entry rank of the learned mode
+  DevBuf<float> strength;          // per-target sum of source strengths (learned mode)
 };
 
 struct DeviceState {
@@ -83,6 +89,9 @@ struct DeviceState {
   size_t ev_used = 0;
   std::vector<int> ev_class;
   std::vector<int64_t> launches;
+  // learned ranks
+  DevBuf<float> box_norm;         // [nbox][L+1] multipole norms of the current batch
+  DevBuf<int64_t> rank_hist;      // M2L entries per chosen rank (accumulated)
 };
 
 struct ProfScope {   // records a start/end event pair around a group of launches
@@ -116,6 +125,14 @@ void upload_tree(Tree* t);
 void setup_workspace(Tree* t, int jb, int ni, int prec);
 void ensure_mixed_operands(Tree* t, hipStream_t st);
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                     hipStream_t st);
+template <class T>
+void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
+                      hipStream_t st, const int8_t* src_rank = nullptr);
+template <class T>
+void learned_ranks(Tree* t, DeviceState* ds, const void* sel, const T* data, int64_t box_stride, int64_t ncol,
+                   hipStream_t st);
+void run_upward_fp64(Tree* t, DeviceState* ds, const double* C, int64_t ldc, int i0, int i1, int j0, int j1,
                      hipStream_t st);
 
 }  // namespace occk

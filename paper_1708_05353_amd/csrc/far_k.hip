@@ -121,6 +121,8 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
       sp.push_back(int32_t(sb.size()));
     }
     ps.ntgt = int(par.size());
+    ps.nent = int(sb.size());
+    ps.host_op = so;
     ps.tgt_box.upload(tb);
     ps.src_ptr.upload(sp);
     ps.src_box.upload(sb);
@@ -149,6 +151,11 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
       sp.push_back(int32_t(sb.size()));
     }
     ps.ntgt = int(bx.size());
+    ps.nent = int(sb.size());
+    ps.host_op = so;
+    for (int32_t b = 0; b < ps.ntgt; ++b)
+      for (int32_t e = sp[b]; e < sp[b + 1]; ++e) ps.host_tgt.push_back(b);
+    ps.ent_tgt.upload(ps.host_tgt);
     ps.tgt_box.upload(tb);
     ps.src_ptr.upload(sp);
     ps.src_box.upload(sb);
@@ -262,8 +269,8 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
 }
 
 template <class T>
-static void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
-                             hipStream_t st) {
+void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
+                      hipStream_t st, const int8_t* src_rank) {
   const int Q = t->Q, KS = ksteps_of(Q);
   const int64_t nct = (ncol + 255) / 256;
   const int64_t nblocks = nct * ps.ntgt;
@@ -271,7 +278,7 @@ static void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
 #define OCCK_TR(MT)                                                                                           \
   hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, ncol, \
-                     Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
+                     Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks, src_rank)
   switch (mtiles_of(Q)) {
     case 1: OCCK_TR(1); break;
     case 2: OCCK_TR(2); break;
@@ -284,6 +291,11 @@ static void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box
 #undef OCCK_TR
   HIP_OK(hipGetLastError());
 }
+
+template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, int64_t, const double*,
+                                       hipStream_t, const int8_t*);
+template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, int64_t, const float*, hipStream_t,
+                                      const int8_t*);
 
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st) {
@@ -319,7 +331,12 @@ static void free_state(DeviceState* ds) {
   ds->opparam.free();
   ds->ops.free();
   for (auto& p : ds->up) { p.tgt_box.free(); p.src_ptr.free(); p.src_box.free(); p.src_op.free(); }
-  for (auto& p : ds->down) { p.tgt_box.free(); p.src_ptr.free(); p.src_box.free(); p.src_op.free(); }
+  for (auto& p : ds->down) {
+    p.tgt_box.free(); p.src_ptr.free(); p.src_box.free(); p.src_op.free(); p.rank.free(); p.ent_tgt.free();
+    p.strength.free();
+  }
+  ds->box_norm.free();
+  ds->rank_hist.free();
   ds->occ_ptr.free();
   ds->occ_row.free();
   ds->H.free();
@@ -350,7 +367,8 @@ static int auto_jblock(const Tree* t, int nj, int ni, size_t es) {
 // One j batch: half transform, Omega, upward, downward, L2P.
 template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
-                        int j0, int j1, int jb, int ni, bool prof, hipStream_t st) {
+                        int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
+                        bool stop_after_up = false) {
   using T = typename ModeT<MODE>::T;
   const int Q = t->Q;
   const int64_t ncol = int64_t(jb) * ni;
@@ -375,9 +393,14 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
       for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, ncol, ops, st);
     }
+    if (stop_after_up) return;
+    if (sel) {
+      ProfScope ps(ds, prof, OCCK_K_SELECT, st, 1 + int(ds->down.size()));
+      learned_ranks<T>(t, ds, sel, data, box_stride, ncol, st);
+    }
     {
       ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
-      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, ncol, ops, st);
+      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, ncol, ops, st, sel ? p.rank.p : nullptr);
     }
     {
       ProfScope ps(ds, prof, OCCK_K_L2P, st);
@@ -388,12 +411,19 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   }
 }
 
+// half transform, Omega and the upward passes of one FP64 j batch [j0, j1)
+// (the batch must fit the workspace: setup_workspace(t, j1 - j0, i1 - i0, FP64))
+void run_upward_fp64(Tree* t, DeviceState* ds, const double* C, int64_t ldc, int i0, int i1, int j0, int j1,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p, t->L,
+                     t->Q);
+  HIP_OK(hipGetLastError());
+  run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, j1 - j0, i1 - i0, false, st, nullptr, true);
+}
+
 int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1, int32_t j0,
               int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk, void* stream) {
-  if (opts->rank_mode != OCCK_RANK_FIXED) {
-    set_error("occk_far_K: learned ranks are not built in this library version");
-    return OCCK_ESTATE;
-  }
+  const void* sel = opts->rank_mode == OCCK_RANK_LEARNED ? static_cast<const void*>(opts->selector) : nullptr;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const int ni = i1 - i0, nj = j1 - j0;
   const int nbasis = t->nbasis;
@@ -428,13 +458,13 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
     if (prec == OCCK_PREC_FP64)
-      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st);
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel);
     else if (prec == OCCK_PREC_FP32)
-      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
     else if (prec == OCCK_PREC_BF16X3)
-      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
     else
-      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st);
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,

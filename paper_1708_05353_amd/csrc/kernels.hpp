@@ -449,11 +449,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 // neighbouring targets then share their sources in that XCD's L2.
 // T = double: FP64 MFMA; T = float: FP32 MFMA.
 // --------------------------------------------------------------------------
+// src_rank (may be null): per CSR entry the rank p kept in that translation
+// (components l, l' <= p, i.e. the leading (p+1)^2 rows and columns).
 template <class T, int MT>
 __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t ncol, int Q, int KS,
                                const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
-                               const T* __restrict__ ops, int t, int64_t ct) {
+                               const T* __restrict__ ops, int t, int64_t ct,
+                               const int8_t* __restrict__ src_rank = nullptr) {
   using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t colbase = ct * 256 + wave * 64;
@@ -465,7 +468,13 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t
   for (int e = e0; e < e1; ++e) {
     const T* X = data + int64_t(src_box[e]) * box_stride;
     const T* Tm = ops + int64_t(src_op[e]) * opsz;
-    for (int ks = 0; ks < KS; ++ks) {
+    int nq = Q, kse = KS;
+    if (src_rank) {
+      const int p = src_rank[e];
+      nq = (p + 1) * (p + 1);
+      kse = (nq + 3) / 4;
+    }
+    for (int ks = 0; ks < kse; ++ks) {
       const int row = ks * 4 + (lane >> 4);
       T b[4];
       for (int j = 0; j < 4; ++j) {
@@ -473,7 +482,9 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t
         b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : T(0);
       }
       for (int i = 0; i < MT; ++i) {
-        const T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
+        if (i * 16 >= nq) break;
+        T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
+        if (nq < Q && (i * 16 + (lane & 15) >= nq || row >= nq)) a = T(0);
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a, b[j], acc[i][j]);
       }
     }
@@ -496,12 +507,13 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
                                                         const int32_t* __restrict__ src_ptr,
                                                         const int32_t* __restrict__ src_box,
                                                         const int32_t* __restrict__ src_op,
-                                                        const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+                                                        const T* __restrict__ ops, int ntgt, int64_t nblocks,
+                                                        const int8_t* __restrict__ src_rank) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
   translate_tile<T, MT>(data, box_stride, ncol, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
-                        int(logical % ntgt), logical / ntgt);
+                        int(logical % ntgt), logical / ntgt, src_rank);
 }
 
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols

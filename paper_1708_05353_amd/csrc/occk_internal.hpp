@@ -104,5 +104,19 @@ int32_t batch_tune(void* plan, const double* const* C, const int64_t* ldc, doubl
                    void* stream, int32_t* choice);
 int32_t batch_free(void* plan);
 int32_t batch_shape(const void* plan, int32_t* nsys, int32_t* nocc, int cap, int32_t* tuned);
+int32_t selector_create(int32_t seed, void** out);
+int32_t selector_free(void* sel);
+int32_t selector_weights(void* sel, float* get, const float* set);
+void selector_set_rule(void* sel, float log10_tau, float margin);
+int32_t selector_train(void* sel, const float* X, const float* T, int32_t n, int32_t epochs, int32_t batch, float lr,
+                       int32_t seed, float* loss, void* stream);
+int32_t selector_grad(void* sel, const float* X, const float* T, int32_t n, float* loss, float* grad, void* stream);
+int32_t selector_predict(void* sel, const float* X, int32_t n, int32_t lmax, float* z, int32_t* rank, void* stream);
+int32_t selector_save(const void* sel, const char* path);
+int32_t selector_load(void* sel, const char* path);
+int32_t selector_collect(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t j0, int32_t j1,
+                         int32_t max_samples, int32_t seed, float* feat, float* target, int32_t* nout, void* stream);
+int32_t rank_stats(Tree* t, int64_t* hist);
+bool selector_live(const void* sel);
 
 }  // namespace occk

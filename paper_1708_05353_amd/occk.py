@@ -74,12 +74,30 @@ EXPORTS = {
     "occk_batch_shape": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_void_p, ct.c_int32]),
     "occk_batch_config": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
     "occk_batch_free": (ct.c_int32, [ct.c_void_p]),
+    "occk_selector_create": (ct.c_int32, [ct.c_int32, ct.POINTER(ct.c_void_p)]),
+    "occk_selector_free": (ct.c_int32, [ct.c_void_p]),
+    "occk_selector_get_weights": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
+    "occk_selector_set_weights": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
+    "occk_selector_set_rule": (ct.c_int32, [ct.c_void_p, ct.c_float, ct.c_float]),
+    "occk_selector_collect": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
+                                           ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                           ct.POINTER(ct.c_int32), ct.c_void_p]),
+    "occk_selector_train": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32,
+                                         ct.c_float, ct.c_int32, ct.c_void_p, ct.c_void_p]),
+    "occk_selector_grad": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_float),
+                                        ct.c_void_p, ct.c_void_p]),
+    "occk_selector_predict": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_void_p, ct.c_void_p,
+                                           ct.c_void_p]),
+    "occk_selector_save": (ct.c_int32, [ct.c_void_p, ct.c_char_p]),
+    "occk_selector_load": (ct.c_int32, [ct.c_void_p, ct.c_char_p]),
+    "occk_rank_stats": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
     "occk_workspace_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int64)]),
     "occk_profile_enable": (ct.c_int32, [ct.c_void_p, ct.c_int32]),
     "occk_profile_read": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
 }
 
-KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert"]
+KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert", "select"]
+NFEAT, NOUT, NPARAM = 24, 8, 6280
 
 _lib = None
 
@@ -210,6 +228,11 @@ class Tree:
         _check(lib().occk_profile_read(self._h, ms.ctypes.data, n.ctypes.data))
         return {c: (float(ms[k]), int(n[k])) for k, c in enumerate(KERNEL_CLASSES)}
 
+    def rank_stats(self) -> np.ndarray:
+        h = np.zeros(9, np.int64)
+        _check(lib().occk_rank_stats(self._h, h.ctypes.data))
+        return h
+
     def free(self):
         if self._h is not None and self._h.value:
             _check(lib().occk_free_tree(self._h))
@@ -243,7 +266,7 @@ class Tree:
 
 
 def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,
-          jblock: int = 0, accumulate: bool = False, stream=None):
+          jblock: int = 0, accumulate: bool = False, stream=None, selector=None):
     """K[:, i0:i1] (+)= 2 sum_{j in [j0,j1)} (rj|ji)_ff on the GPU.
 
     C: torch.float64 CUDA tensor (nbasis, ldc) row-major; K: torch.float64 CUDA
@@ -258,7 +281,8 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
             raise ValueError("C and K must be row-major 2-D float64 CUDA tensors")
     if stream is None:
         stream = torch.cuda.current_stream(C.device)
-    opts = _Opts(int(precision), RANK_FIXED, None, int(jblock), int(bool(accumulate)))
+    opts = _Opts(int(precision), RANK_FIXED if selector is None else RANK_LEARNED,
+                 None if selector is None else selector.handle.value, int(jblock), int(bool(accumulate)))
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))
@@ -318,6 +342,95 @@ class Batch:
     def free(self):
         if self._h is not None and self._h.value:
             _check(lib().occk_batch_free(self._h))
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Selector:
+    """Learned rank per interaction-list translation (occk_selector_*)."""
+
+    def __init__(self, seed: int = 0):
+        h = ct.c_void_p()
+        _check(lib().occk_selector_create(int(seed), ct.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def weights(self) -> np.ndarray:
+        w = np.zeros(NPARAM, np.float32)
+        _check(lib().occk_selector_get_weights(self._h, w.ctypes.data))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, np.float32)
+        _check(lib().occk_selector_set_weights(self._h, w.ctypes.data))
+
+    def set_rule(self, log10_tau: float, margin: float):
+        _check(lib().occk_selector_set_rule(self._h, float(log10_tau), float(margin)))
+
+    @staticmethod
+    def collect(tree: Tree, C, j_range, max_samples: int, seed: int = 0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(C.device)
+        X = np.zeros((max_samples, NFEAT), np.float32)
+        T = np.zeros((max_samples, NOUT), np.float32)
+        n = ct.c_int32()
+        _check(lib().occk_selector_collect(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), int(C.shape[1]),
+                                           int(j_range[0]), int(j_range[1]), int(max_samples), int(seed),
+                                           X.ctypes.data, T.ctypes.data, ct.byref(n), ct.c_void_p(stream.cuda_stream)))
+        return X[: n.value].copy(), T[: n.value].copy()
+
+    def train(self, X, T, epochs=20, batch=512, lr=1e-3, seed=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        loss = np.zeros(epochs, np.float32)
+        _check(lib().occk_selector_train(self._h, X.ctypes.data, T.ctypes.data, int(X.shape[0]), int(epochs), int(batch),
+                                         float(lr), int(seed), loss.ctypes.data, ct.c_void_p(stream.cuda_stream)))
+        return loss
+
+    def grad(self, X, T, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        X = np.ascontiguousarray(X, np.float32)
+        T = np.ascontiguousarray(T, np.float32)
+        g = np.zeros(NPARAM, np.float32)
+        l = ct.c_float()
+        _check(lib().occk_selector_grad(self._h, X.ctypes.data, T.ctypes.data, int(X.shape[0]), ct.byref(l),
+                                        g.ctypes.data, ct.c_void_p(stream.cuda_stream)))
+        return float(l.value), g
+
+    def predict(self, X, lmax: int = 8, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        X = np.ascontiguousarray(X, np.float32)
+        z = np.zeros((X.shape[0], NOUT), np.float32)
+        r = np.zeros(X.shape[0], np.int32)
+        _check(lib().occk_selector_predict(self._h, X.ctypes.data, int(X.shape[0]), int(lmax), z.ctypes.data,
+                                           r.ctypes.data, ct.c_void_p(stream.cuda_stream)))
+        return z, r
+
+    def save(self, path: str):
+        _check(lib().occk_selector_save(self._h, path.encode()))
+
+    def load(self, path: str):
+        _check(lib().occk_selector_load(self._h, path.encode()))
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            _check(lib().occk_selector_free(self._h))
         self._h = None
 
     def __del__(self):

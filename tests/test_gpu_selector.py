@@ -1,0 +1,228 @@
+"""Learned rank selector: GPU training/inference kernels against the FP64 MLP
+oracle, ranked translations against the oracle's rank-truncated FMM, and
+what a trained selector gains over the fixed-rank method."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp
+from oracle.fmm import Setup, far_K as oracle_far_K
+
+from conftest import rel, with_params
+
+pytestmark = pytest.mark.gpu
+
+F, H, R = 24, 64, 8
+
+
+@pytest.fixture(scope="module")
+def occk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_05353_amd import occk as o
+    return o
+
+
+def _data(seed, n=700):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, F)).astype(np.float32)
+    T = (0.3 * np.tanh(X[:, :R]) - 0.2 * X[:, R:2 * R] ** 2).astype(np.float32)
+    return X, T
+
+
+def test_gradient_matches_oracle(occk):
+    sel = occk.Selector(seed=3)
+    X, T = _data(1)
+    loss, g = sel.grad(X, T)
+    theta = sel.weights().astype(np.float64)
+    loss_ref, g_ref = mlp.loss_and_grad(theta, X.astype(np.float64), T.astype(np.float64), F, H, R)
+    assert abs(loss - loss_ref) <= 1e-5 * abs(loss_ref)
+    assert np.abs(g - g_ref).max() <= 1e-3 * np.abs(g_ref).max()
+    sel.free()
+
+
+def test_adam_steps_match_oracle(occk):
+    """Three full-batch Adam steps on the GPU equal the oracle's (FP32 vs FP64)."""
+    sel = occk.Selector(seed=4)
+    X, T = _data(2, n=256)
+    theta = sel.weights().astype(np.float64)
+    sel.train(X, T, epochs=3, batch=256, lr=1e-3, seed=0)
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    for t in range(1, 4):
+        _, g = mlp.loss_and_grad(theta, X.astype(np.float64), T.astype(np.float64), F, H, R)
+        theta, m, v = mlp.adam_step(theta, g, m, v, t, 1e-3)
+    got = sel.weights()
+    assert np.abs(got - theta).max() <= 5e-5
+    sel.free()
+
+
+def test_bf16_inference_matches_oracle_forward(occk):
+    sel = occk.Selector(seed=5)
+    X, _ = _data(3, n=500)
+    z, r = sel.predict(X, lmax=8)
+    zr, _ = mlp.forward(sel.weights().astype(np.float64), X.astype(np.float64), F, H, R)
+    scale = np.abs(zr).max()
+    assert np.abs(z - zr).max() <= 0.03 * scale          # bf16 weights and activations
+    sel.set_rule(-6.0, 1.0)
+    z, r = sel.predict(X, lmax=8)
+    ref = mlp.rank_rule(z, (-6.0 - 1.0) / 4.0, 8)            # same decision rule on the GPU's outputs
+    assert np.array_equal(r, ref)
+    sel.free()
+
+
+def test_training_reduces_loss(occk):
+    sel = occk.Selector(seed=6)
+    X, T = _data(4, n=4000)
+    loss = sel.train(X, T, epochs=30, batch=256, lr=3e-3, seed=1)
+    assert loss[-1] < 0.2 * loss[0]
+    sel.free()
+
+
+def test_save_load_and_checksum(occk):
+    sel = occk.Selector(seed=7)
+    sel.set_rule(-5.0, 0.5)
+    w = sel.weights()
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "sel.bin")
+        sel.save(path)
+        other = occk.Selector(seed=8)
+        other.load(path)
+        assert np.array_equal(other.weights(), w)
+        raw = bytearray(open(path, "rb").read())
+        raw[100] ^= 0x5A
+        open(path, "wb").write(bytes(raw))
+        with pytest.raises(occk.OcckError):
+            other.load(path)
+        assert np.array_equal(other.weights(), w)      # unchanged after a rejected load
+        other.free()
+    sel.free()
+
+
+def _constant_rank_selector(occk, p):
+    """Outputs +10 for ranks below p and -10 from p on: the rule picks p for
+    every interaction, independent of the features."""
+    sel = occk.Selector(seed=9)
+    w = np.zeros(occk.NPARAM, np.float32)
+    b3 = 6280 - 8
+    w[b3:b3 + 8] = [10.0 if k + 1 < p else -10.0 for k in range(8)]
+    sel.set_weights(w)
+    sel.set_rule(-6.0, 1.0)
+    return sel
+
+
+@pytest.mark.parametrize("case,L,p", [("chain", 4, 2), ("chain", 6, 1), ("sheet", 3, 2), ("water", 4, 3)])
+def test_ranked_translation_matches_oracle(occk, tiny, case, L, p):
+    import torch
+    if case == "chain":
+        wl, C, _ = tiny
+        params = with_params(wl, lmax=L)
+    elif case == "sheet":
+        wl = workloads.graphene_flake(n=2, lmax=L, nocc=12, depth=3)
+        C, params = wl.orbitals(), wl.params
+    else:
+        wl = workloads.water_cluster(12, 42, lmax=L)
+        C, params = wl.orbitals(), wl.params
+    ref = oracle_far_K(Setup(wl.system, params), C, m2l_rank=p)
+    sel = _constant_rank_selector(occk, p)
+    tr = occk.Tree(wl.system, params)
+    K = torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda")
+    occk.far_K(tr, torch.from_numpy(C).cuda(), K, selector=sel, jblock=5)
+    torch.cuda.synchronize()
+    hist = tr.rank_stats()
+    nbatch = -(-C.shape[1] // 5)
+    assert hist.sum() == tr.info.n_il * nbatch and hist[p] == tr.info.n_il * nbatch
+    assert rel(K.cpu().numpy(), ref) <= 1e-8
+    tr.free()
+    sel.free()
+
+
+def test_collect_targets(occk):
+    import torch
+    wl = workloads.water_cluster(15, 43, lmax=6)
+    C = wl.orbitals()
+    tr = occk.Tree(wl.system, wl.params)
+    X, T = occk.Selector.collect(tr, torch.from_numpy(C).cuda(), (0, 8), max_samples=500, seed=1)
+    assert X.shape == (min(500, tr.info.n_il), 24) and np.all(np.isfinite(X)) and np.all(np.isfinite(T))
+    # rank L keeps everything: zero error (log10 1e-16 / 4 = -4); errors shrink with the rank
+    assert np.all(T[:, 5:] == -4.0)
+    assert np.mean(np.diff(T[:, :6], axis=1) <= 1e-6) > 0.95
+    tr.free()
+
+
+def _work_fraction(h, L=8):
+    return float(sum(h[p] * (p + 1) ** 4 for p in range(9)) / (h.sum() * (L + 1) ** 4))
+
+
+def test_trained_selector_gain(occk):
+    """Trained on method-generated targets of two training globules, with the
+    per-translation threshold calibrated on the first of them; on a third
+    globule at L = 8 the learned ranks keep K within 1e-6 of fixed L = 8
+    (FP64) while cutting the interaction-list work, and an untrained selector
+    does not achieve both."""
+    import torch
+    Xs, Ts, trains = [], [], []
+    for seed in (1000, 1001):
+        wl = workloads.protein_blob(seed=seed, scale=0.2, nocc=None)
+        tr = occk.Tree(wl.system, wl.params)
+        C = torch.from_numpy(wl.orbitals()).cuda()
+        X, T = occk.Selector.collect(tr, C, (0, 16), max_samples=40000, seed=seed)
+        Xs.append(X)
+        Ts.append(T)
+        trains.append((wl, tr, C))
+    X, T = np.vstack(Xs), np.vstack(Ts)
+    sel = occk.Selector(seed=11)
+    sel.train(X, T, epochs=25, batch=512, lr=2e-3, seed=2)
+
+    def run(tr, C, wl, s):
+        n = C.shape[1]
+        Kf = torch.zeros((wl.system.nbasis, n), dtype=torch.float64, device="cuda")
+        occk.far_K(tr, C, Kf, j_range=(0, 16))
+        Kl = torch.zeros_like(Kf)
+        occk.far_K(tr, C, Kl, j_range=(0, 16), selector=s)
+        torch.cuda.synchronize()
+        return rel(Kl.cpu().numpy(), Kf.cpu().numpy()), _work_fraction(tr.rank_stats())
+
+    # calibrate the threshold on the training globules: loosest tau whose
+    # worst error is below 1e-6 / 3
+    chosen = -10.0
+    for lt in (-3.0, -3.5, -4.0, -4.5, -5.0, -5.5, -6.0, -6.5, -7.0, -8.0):
+        sel.set_rule(lt, 0.5)
+        res = [run(tr0, C0, wl0, sel) for wl0, tr0, C0 in trains]
+        e = max(r[0] for r in res)
+        print(f"calibration log10 tau {lt}: err {e:.3e} work {max(r[1] for r in res):.3f}")
+        if e <= 1e-6 / 3:
+            chosen = lt
+            break
+    sel.set_rule(chosen, 0.5)
+    for _, tr, _ in trains:
+        tr.free()
+    wl = workloads.protein_blob(seed=2000, scale=0.2, nocc=None)
+    C = torch.from_numpy(wl.orbitals()).cuda()
+    tr = occk.Tree(wl.system, wl.params)
+    err, frac = run(tr, C, wl, sel)
+    print(f"trained (log10 tau {chosen}): err {err:.3e} M2L work fraction {frac:.3f}")
+    assert err <= 1e-6
+    # uniform truncation at one rank p for every interaction-list translation
+    best_uniform = 1.0
+    for p in (7, 6, 5, 4):
+        cs = _constant_rank_selector(occk, p)
+        eu, fu = run(tr, C, wl, cs)
+        cs.free()
+        print(f"uniform rank {p}: err {eu:.3e} M2L work fraction {fu:.3f}")
+        if eu <= 1e-6:
+            best_uniform = min(best_uniform, fu)
+    print(f"best uniform rank meeting 1e-6: work {best_uniform:.3f}; learned: {frac:.3f}")
+    assert frac < 1.0 and frac <= best_uniform
+    untrained = occk.Selector(seed=12)
+    untrained.set_rule(chosen, 0.5)
+    erru, fracu = run(tr, C, wl, untrained)
+    print(f"untrained: err {erru:.3e} M2L work fraction {fracu:.3f}")
+    assert erru > 1e-6 or fracu > frac
+    tr.free()
+    sel.free()
+    untrained.free()

@@ -255,13 +255,21 @@ def water_batch() -> list[Workload]:
     return [water_cluster(20 + int(round(80 * k / 15)), 40 + k) for k in range(16)]
 
 
-def protein_blob(seed: int = 5, lmax: int = 8, nocc: int = 1261, depth: int = 3) -> Workload:
+def protein_blob(seed: int = 5, lmax: int = 8, nocc: int | None = 1261, depth: int = 3,
+                 scale: float = 1.0) -> Workload:
     """644 sites (202 C, 317 H, 64 O, 55 N, 6 S; nbasis 6187) uniform in a sphere
-    of radius 20.36 bohr (4732 amu at 1.5 g/cm^3), minimum distance 1.9 bohr."""
+    of radius 20.36 bohr (4732 amu at 1.5 g/cm^3), minimum distance 1.9 bohr.
+
+    scale < 1 keeps the density and the composition ratios with about
+    scale * 644 sites (smaller globules for training the rank selector);
+    nocc=None then takes half the electrons."""
     rng = np.random.default_rng([seed, 0])
-    comp = ["C"] * 202 + ["H"] * 317 + ["O"] * 64 + ["N"] * 55 + ["S"] * 6
+    counts = {"C": 202, "H": 317, "O": 64, "N": 55, "S": 6}
+    if scale != 1.0:
+        counts = {k: max(1, int(round(v * scale))) for k, v in counts.items()}
+    comp = [k for k, v in counts.items() for _ in range(v)]
     comp = [comp[k] for k in rng.permutation(len(comp))]
-    radius = 20.36
+    radius = 20.36 * (len(comp) / 644.0) ** (1.0 / 3.0)
     pts: list[np.ndarray] = []
     while len(pts) < len(comp):
         p = rng.uniform(-radius, radius, 3)
@@ -270,7 +278,9 @@ def protein_blob(seed: int = 5, lmax: int = 8, nocc: int = 1261, depth: int = 3)
         if pts and np.min(np.linalg.norm(np.array(pts) - p, axis=1)) < 1.9:
             continue
         pts.append(p)
-    sysm = _build("protein_blob", np.array(pts), comp, nocc)
+    if nocc is None:
+        nocc = sum(ELECTRONS[s] for s in comp) // 2
+    sysm = _build("protein_blob" if scale == 1.0 else f"protein_blob_{len(comp)}", np.array(pts), comp, nocc)
     return Workload(sysm, TreeParams(SPLIT_XYZ, depth, 2, lmax), seed=seed)
 
 
