@@ -142,9 +142,23 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_probe(mb: int):
+    """A plain device-to-device copy of a known size, for scaling hardware
+    traffic counters (bytes the counters report per byte moved)."""
+    import torch
+    n = mb * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16"])
+    ap.add_argument("--copy-probe", type=int, default=0, help="MiB; run only a plain copy of that size")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -159,6 +173,9 @@ def main():
               "split over the output index i is described in DESIGN.md but not built.", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.workload == "batch16":
         bench_batch(args)
         return

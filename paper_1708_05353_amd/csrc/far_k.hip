@@ -268,10 +268,47 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
   ds->ws_prec = prec;
 }
 
+// Columns per thread of the small-Q vector translations: 1, 2 (default) or
+// 4, read once from OCCK_TRANSLATE_COLS (a tuning knob; results do not
+// depend on it).
+static int vec_cols() {
+  static const int nc = [] {
+    const char* s = std::getenv("OCCK_TRANSLATE_COLS");
+    const int v = s ? std::atoi(s) : 2;
+    return (v == 1 || v == 4) ? v : 2;
+  }();
+  return nc;
+}
+
 template <class T>
 void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
                       hipStream_t st, const int8_t* src_rank) {
   const int Q = t->Q, KS = ksteps_of(Q);
+  if (Q <= 9 && !src_rank) {
+    const int NC = vec_cols();
+    const int64_t nblocks = ((ncol + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
+    const int64_t grid = ((nblocks + 7) / 8) * 8;
+    if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
+#define OCCK_TV(QQ, NN)                                                                                         \
+  hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NN>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
+                     ncol, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
+#define OCCK_TVQ(QQ)                   \
+  switch (NC) {                        \
+    case 1: OCCK_TV(QQ, 1); break;     \
+    case 4: OCCK_TV(QQ, 4); break;     \
+    default: OCCK_TV(QQ, 2); break;    \
+  }
+    switch (Q) {
+      case 1: OCCK_TVQ(1); break;
+      case 4: OCCK_TVQ(4); break;
+      case 9: OCCK_TVQ(9); break;
+      default: throw std::invalid_argument("unsupported Q");
+    }
+#undef OCCK_TVQ
+#undef OCCK_TV
+    HIP_OK(hipGetLastError());
+    return;
+  }
   const int64_t nct = (ncol + 255) / 256;
   const int64_t nblocks = nct * ps.ntgt;
   const int64_t grid = ((nblocks + 7) / 8) * 8;

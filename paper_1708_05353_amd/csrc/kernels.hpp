@@ -516,6 +516,55 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
                         int(logical % ntgt), logical / ntgt, src_rank);
 }
 
+// --------------------------------------------------------------------------
+// Exact-size translations for Q <= 9 (L <= 2) on the vector ALU.  On gfx950
+// the FP64 MFMA peak equals the FP64 vector FMA peak, and a 9x9 operator
+// padded to 16x12 MFMA tiles issues 2.4x the useful products, so small
+// translations run as plain FMAs: each thread owns NC columns (lane-
+// consecutive, 512-byte wave loads per component row), the operator entries
+// are wave-uniform loads from the fragment-ordered operator (scalar cache),
+// and every product is one FMA into an FP64 (or FP32) accumulator.  Per
+// source: Q loads and Q*Q FMAs per column.  Same CSR passes, same XCD-aware
+// block order as translate_kernel; block covers 256*NC columns of one target.
+// --------------------------------------------------------------------------
+template <class T, int Q, int NC>
+__global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
+                                                            int KS, const int32_t* __restrict__ tgt_box,
+                                                            const int32_t* __restrict__ src_ptr,
+                                                            const int32_t* __restrict__ src_box,
+                                                            const int32_t* __restrict__ src_op,
+                                                            const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+  static_assert(Q <= 16, "one operator row tile");
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  const int t = int(logical % ntgt);
+  const int64_t c0 = (logical / ntgt) * (256 * NC) + threadIdx.x;
+  bool ok[NC];
+  for (int c = 0; c < NC; ++c) ok[c] = c0 + c * 256 < ncol;
+  T acc[NC][Q];
+  for (int c = 0; c < NC; ++c)
+    for (int i = 0; i < Q; ++i) acc[c][i] = T(0);
+  const int64_t opsz = int64_t(KS) * 64;
+  const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
+  for (int e = e0; e < e1; ++e) {
+    const T* X = data + int64_t(src_box[e]) * box_stride + c0;
+    const T* A = ops + int64_t(src_op[e]) * opsz;
+    T x[NC][Q];
+    for (int c = 0; c < NC; ++c)
+      for (int k = 0; k < Q; ++k) x[c][k] = ok[c] ? X[int64_t(k) * ncol + c * 256] : T(0);
+    for (int i = 0; i < Q; ++i)
+      for (int k = 0; k < Q; ++k) {
+        const T a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
+        for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, x[c][k], acc[c][i]);
+      }
+  }
+  T* Y = data + int64_t(tgt_box[t]) * box_stride + c0;
+  for (int c = 0; c < NC; ++c)
+    if (ok[c])
+      for (int i = 0; i < Q; ++i) Y[int64_t(i) * ncol + c * 256] = acc[c][i];
+}
+
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
 static __global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
                                 int64_t rows, int64_t cols) {
