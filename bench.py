@@ -29,30 +29,39 @@ PEAK_HBM = 8.0e12
 ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
 
 
-def class_costs(info, ni, nj, jb, prec):
-    """Algorithmic flops and bytes per call for each kernel class.
+def class_costs(info, n, jb, prec):
+    """Algorithmic flops and bytes per call of each kernel class, for the full
+    call (i and j over all n occupied orbitals, symmetric schedule).
 
-    GEMMs: flops of the dense contractions the method performs (half transform
-    counted over the screened pairs).  Translations: flops of the dense M2L
-    and the structurally nonzero M2M/L2L entries; compulsory bytes = every
-    source box read once, every target box written once, per j batch."""
+    Flops are the method's counts with the (i, j) symmetry of Omega and Mloc
+    used: n_c = n(n+1)/2 translated columns, F_Omega = Q n(n+1) sum_B n_B,
+    F_L2P = 2 Q n^2 sum_B n_B, F_half = 2 Q n sum_B pi_B.  Bytes are the
+    compulsory traffic of the schedule as executed: batch k (first j at
+    k*jb) carries jb*(n - k*jb) columns; every box it touches is read once
+    and written once per batch, operands of the GEMMs are read once."""
     Q = info.ncomp
-    nc = ni * nj
     s = ELEM_BYTES[prec]
     nb = info.boxes_per_level
     lmin, D = info.lmin, info.depth
-    nblk = -(-nj // jb)
-    ncol = jb * ni
+    nblk = -(-n // jb)
+    nks = [n - k * jb for k in range(nblk)]          # carried i per batch
+    nc_exec = sum(jb * nk for nk in nks)
+    nc = n * (n + 1) // 2
     up_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, D))
     down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
     z = info.m2m_nnz
+    snb, snb2, nleaf = info.sum_nb, info.sum_nb2, info.nleaf
+    half_b = (nblk * (snb2 * Q + snb * jb * (1 + Q)) + snb2 * Q + snb * n * (1 + Q)) * s
+    omega_b = sum(snb * Q * jb + snb * nk + nleaf * Q * jb * nk for nk in nks) * s
+    l2p_b = sum((nleaf * Q * jb * nk + nleaf * Q * jb * max(0, nk - jb) + snb * Q * max(0, nk - jb)) * s
+                + (snb * nk + 2 * snb * jb) * 8 for nk in nks)
     return {
-        "half": (2 * Q * info.npairs * nj, (info.sum_nb2 * Q + info.sum_nb * nj * (1 + Q)) * s),
-        "omega": (2 * Q * nj * ni * info.sum_nb, (info.sum_nb * Q * nj + info.nleaf * Q * nc) * s),
-        "up": (2 * z * nc * info.n_edges, up_boxes * Q * ncol * s * nblk),
-        "down": (2 * Q * Q * nc * info.n_il + 2 * z * nc * info.n_edges, down_boxes * Q * ncol * s * nblk),
-        "l2p": (2 * Q * nj * ni * info.sum_nb, (info.nleaf * Q * nc + info.sum_nb * Q * nj) * s),
-        "reduce": (0, (info.sum_nb * ni + info.nbasis * ni) * 8),
+        "half": (2 * Q * info.npairs * n, half_b),
+        "omega": (Q * n * (n + 1) * snb, omega_b),
+        "up": (2 * z * nc * info.n_edges, up_boxes * Q * nc_exec * s),
+        "down": (2 * Q * Q * nc * info.n_il + 2 * z * nc * info.n_edges, down_boxes * Q * nc_exec * s),
+        "l2p": (2 * Q * n * n * snb, l2p_b),
+        "reduce": (0, (snb * n + info.nbasis * n) * 8),
     }
 
 
@@ -96,7 +105,7 @@ def bench_batch(args):
         trees.append(tr)
         Cs.append(torch.from_numpy(C).cuda())
         Ks.append(torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda"))
-        flops += tr.flops(C.shape[1], C.shape[1])["total"]
+        flops += tr.flops(C.shape[1], C.shape[1], symmetric=True)["total"]
     noccs = [C.shape[1] for C in Cs]
     plan = occk.Batch(trees, noccs, prec)
     choice = plan.tune(Cs, Ks)
@@ -223,11 +232,11 @@ def main():
     prof = tree.profile_read()
     tree.profile(False)
     ms = ev0.elapsed_time(ev1) / args.steps
-    fl = tree.flops(nocc, nocc)
+    fl = tree.flops(nocc, nocc, symmetric=True)
     value = fl["total"] / (ms * 1e-3) / 1e9
     print(f"[bench] {ms:.2f} ms/step, {value:.0f} GFLOP/s", file=sys.stderr, flush=True)
 
-    costs = class_costs(tree.info, nocc, nocc, jb, args.precision)
+    costs = class_costs(tree.info, nocc, jb, args.precision)
     breakdown = {}
     for cls, (flops, nbytes) in costs.items():
         t_ms, nl = prof[cls]
@@ -266,6 +275,7 @@ def main():
         "config": {"workload": f"alkane chain (C400H802 stand-in): nbasis 9610, nocc 1601, L={args.lmax}, "
                                f"1-D tree depth 8, ws 2; all i and j",
                    "precision": args.precision, "jblock": jb, "flops_per_step": fl["total"],
+                   "flops_per_step_all_columns": tree.flops(nocc, nocc)["total"],
                    "pct_peak": round(100 * value * 1e9 / PEAK_FLOPS[args.precision], 2),
                    "tree_build_s": round(t_tree, 2), "wall_s_timed": round(wall, 3)},
         "roofline": roof,

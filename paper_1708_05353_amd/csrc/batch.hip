@@ -67,6 +67,7 @@ struct BatchPlan {
   int nsys = 0, prec = 0, L = 0, Q = 0;
   std::vector<Tree*> trees;
   std::vector<int> nocc;
+  std::vector<uint64_t> ws_gen;  // workspace generation of every tree when the tables were built
   // device tables
   DevBuf<BSys> sys;
   DevBuf<BPass> passes;
@@ -106,6 +107,9 @@ __global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ ta
       const T* Cg = MODE == kModeF64 ? reinterpret_cast<const T*>(S.Cin) : reinterpret_cast<const T*>(S.Cf);
       const int64_t ldcg = MODE == kModeF64 ? S.ldcin : int64_t(S.nocc);
       const int64_t opsz = int64_t(mtiles_of(S.Q)) * ksteps_of(S.Q) * 64;
+      GemmRun gather{};   // one j batch of all nocc columns: B gathered from C columns [0, nocc)
+      gather.blim = S.nocc;
+      const ColMap cm{S.ncol, int64_t(S.nocc), 0, S.ncol};
       switch (tk.type) {
         case kTOpgen:
           opgen_one(S.opparam[tk.a], S.ops + int64_t(tk.a) * opsz,
@@ -123,13 +127,13 @@ __global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ ta
         case kTHalf:
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = S.t_half[g];
-            gemm_tile<MODE, true, T>(S.d_half[tl.prob], tl.mt, tl.nt, Cg, ldcg, 0, S.nocc, 0, sm);
+            gemm_tile<MODE, true, T>(S.d_half[tl.prob], tl.mt, tl.nt, Cg, ldcg, gather, sm);
           }
           break;
         case kTOmega:
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = S.t_omega[g];
-            gemm_tile<MODE, false, T>(S.d_omega[tl.prob], tl.mt, tl.nt, Cg, ldcg, 0, S.nocc, 0, sm);
+            gemm_tile<MODE, false, T>(S.d_omega[tl.prob], tl.mt, tl.nt, Cg, ldcg, gather, sm);
           }
           break;
         case kTTrans: {     // pass a, logical blocks [b, b + trans_group)
@@ -137,14 +141,14 @@ __global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ ta
           const int64_t e1 = (P.nblocks < int64_t(tk.b) + trans_group) ? P.nblocks : int64_t(tk.b) + trans_group;
           const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(S.ops) : reinterpret_cast<const T*>(S.opsf);
           for (int64_t lb = tk.b; lb < e1; ++lb)
-            translate_tile<T, MT>(static_cast<T*>(S.data), S.box_stride, S.ncol, S.Q, S.KS, P.tgt_box, P.src_ptr,
+            translate_tile<T, MT>(static_cast<T*>(S.data), S.box_stride, cm, S.Q, S.KS, P.tgt_box, P.src_ptr,
                                   P.src_box, P.src_op, ops, int(lb % P.ntgt), lb / P.ntgt);
           break;
         }
         case kTL2P:
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = S.t_l2p[g];
-            gemm_tile<MODE, true, double>(S.d_l2p[tl.prob], tl.mt, tl.nt, Cg, ldcg, 0, 0, 0, sm);
+            gemm_tile<MODE, true, double>(S.d_l2p[tl.prob], tl.mt, tl.nt, Cg, ldcg, GemmRun{}, sm);
           }
           break;
         case kTReduce: {    // rows [a, b)
@@ -223,6 +227,7 @@ static void build_tasks(BatchPlan& bp) {
 static void prepare(BatchPlan& bp, hipStream_t st) {
   const bool mixed = bp.prec != OCCK_PREC_FP64;
   bp.host_sys.assign(bp.nsys, BSys{});
+  bp.ws_gen.assign(size_t(bp.nsys), 0);
   bp.host_passes.clear();
   for (int k = 0; k < bp.nsys; ++k) {
     Tree* t = bp.trees[k];
@@ -232,6 +237,7 @@ static void prepare(BatchPlan& bp, hipStream_t st) {
     const int n = bp.nocc[k];
     setup_workspace(t, n, n, bp.prec);
     if (mixed) ds->Cf.alloc(size_t(t->nbasis) * n);
+    bp.ws_gen[size_t(k)] = ds->ws_gen;
     BSys& S = bp.host_sys[k];
     S.d_half = ds->d_half.p;
     S.t_half = ds->t_half.p;
@@ -360,7 +366,7 @@ static void revalidate(BatchPlan& bp) {
   for (int k = 0; k < bp.nsys; ++k) {
     const DeviceState* ds = bp.trees[k]->dev;
     if (!ds || ds->ws_jb != bp.nocc[k] || ds->ws_ni != bp.nocc[k] || ds->ws_prec != bp.prec ||
-        ds->data.p != bp.host_sys[k].data)
+        ds->ws_gen != bp.ws_gen[size_t(k)] || (bp.prec != OCCK_PREC_FP64 && ds->Cf.p != bp.host_sys[k].Cf))
       stale = true;
   }
   if (!stale) return;

@@ -75,14 +75,19 @@ struct DeviceState {
   DevBuf<int32_t> occ_ptr, occ_row;
   int nbox = 0;                    // boxes on levels lmin..depth
   std::vector<int32_t> leaf_box;   // leaf -> box slot
-  // per workspace shape (j batch, n_i, precision)
-  int ws_jb = -1, ws_ni = -1, ws_prec = -1;
+  // per workspace shape (j batch, n_i, precision, symmetric schedule)
+  int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;
+  uint64_t ws_gen = 0;            // incremented whenever the workspace buffers are rebuilt
   DevBuf<char> H, data;           // element type of the precision (double / float)
+  DevBuf<char> HT;                // symmetric schedule: H for every column, [leaf][q][i][t]
   DevBuf<double> KB;              // per-leaf K partials, always FP64
   DevBuf<float> Cf;               // FP32 copy of C for the mixed paths
-  DevBuf<GemmDesc> d_half, d_omega, d_l2p;
-  DevBuf<GemmTile> t_half, t_omega, t_l2p;
-  int n_half = 0, n_omega = 0, n_l2p = 0;
+  DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
+  DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt;
+  int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0;
+  // omega and l2p tiles are ordered by column tile: the tiles with nt >= c
+  // start at index *_nt_start[c]
+  std::vector<int32_t> omega_nt_start, l2p_nt_start;
   size_t bytes = 0;
   // profiling: (class, start, end) event pairs recorded on the call's stream
   std::vector<hipEvent_t> ev_pool;
@@ -122,15 +127,15 @@ struct ProfScope {   // records a start/end event pair around a group of launche
 
 size_t device_cap();
 void upload_tree(Tree* t);
-void setup_workspace(Tree* t, int jb, int ni, int prec);
+void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym = false);
 void ensure_mixed_operands(Tree* t, hipStream_t st);
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st);
 template <class T>
-void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
+void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, const ColMap& cm, const T* ops,
                       hipStream_t st, const int8_t* src_rank = nullptr);
 template <class T>
-void learned_ranks(Tree* t, DeviceState* ds, const void* sel, const T* data, int64_t box_stride, int64_t ncol,
+void learned_ranks(Tree* t, DeviceState* ds, const void* sel, const T* data, int64_t box_stride, const ColMap& cm,
                    hipStream_t st);
 void run_upward_fp64(Tree* t, DeviceState* ds, const double* C, int64_t ldc, int i0, int i1, int j0, int j1,
                      hipStream_t st);

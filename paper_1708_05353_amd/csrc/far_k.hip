@@ -182,34 +182,64 @@ static void tiles_for(std::vector<GemmTile>& tiles, int prob, int M, int N) {
     for (int nt = 0; nt < (N + 63) / 64; ++nt) tiles.push_back({prob, mt, nt, 0});
 }
 
-void setup_workspace(Tree* t, int jb, int ni, int prec) {
+// Orders tiles by column tile (stable) and returns, for every column tile c,
+// the index of the first tile with nt >= c (plus the total at the end).
+static std::vector<int32_t> order_by_column_tile(std::vector<GemmTile>& tiles) {
+  std::stable_sort(tiles.begin(), tiles.end(), [](const GemmTile& x, const GemmTile& y) { return x.nt < y.nt; });
+  const int ntmax = tiles.empty() ? 0 : tiles.back().nt + 1;
+  std::vector<int32_t> start(size_t(ntmax) + 1, int32_t(tiles.size()));
+  for (int32_t k = int32_t(tiles.size()) - 1; k >= 0; --k) start[size_t(tiles[size_t(k)].nt)] = k;
+  for (int c = ntmax - 1; c >= 0; --c) start[size_t(c)] = std::min(start[size_t(c)], start[size_t(c) + 1]);
+  return start;
+}
+
+// Device bytes of one workspace shape (box data, H, HT, KB).
+static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni, size_t es, bool sym) {
+  const int64_t ncol = int64_t(jb) * ni;
+  return size_t(sum_nb) * Q * jb * es + size_t(2) * nbox * Q * size_t(ncol) * es + size_t(sum_nb) * ni * 8 +
+         (sym ? size_t(sum_nb) * Q * ni * es : 0);
+}
+
+// Buffers and GEMM descriptors of one workspace shape.  Box data of a batch:
+// Q rows x ncol = jb*ni columns per box, column (j, i) at j*ni + i.
+//   half   H^B[t][q][j] = sum_s O^B_q[t, s] C[s, jstart + j]           (ld Q*jb)
+//   omega  Omega^B[(q, j), i] = sum_t H^B[t][(q, j)] C[t, i0 + i]
+//   l2p    KB[r, i] (+)= sum_(q,j) H^B[r][(q, j)] Mloc^B[(q, j), i]
+// symmetric schedule (sym) in addition:
+//   ht     HT^B[q][i][t] = sum_s O^B_q[t, s] C[s, i0 + i]  for every column i
+//   l2pt   KB[r, jstart + j] += sum_q sum_(i >= koff) HT^B[q][i][r] Mloc^B[(q, j), i]
+void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   DeviceState* ds = t->dev;
-  if (ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec) return;
+  if (ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec && ds->ws_sym == int(sym)) return;
   const int Q = t->Q, nl = t->nleaf();
   const size_t es = prec == OCCK_PREC_FP64 ? 8 : 4;
   const int64_t sum_nb = ds->f_off[nl];
   const int64_t ncol = int64_t(jb) * ni;
-  const size_t need = size_t(sum_nb) * Q * jb * es + size_t(2) * ds->nbox * Q * size_t(ncol) * es +
-                      size_t(sum_nb) * ni * 8;
+  const size_t need = workspace_need(sum_nb, Q, ds->nbox, jb, ni, es, sym);
   if (need + ds->bytes > device_cap()) throw std::bad_alloc();
+  ++ds->ws_gen;
   ds->ws_jb = -1;   // invalid until every buffer and descriptor is in place
   ds->ws_ni = -1;
   ds->ws_prec = -1;
+  ds->ws_sym = -1;
   ds->H.free();
+  ds->HT.free();
   ds->data.free();
   ds->KB.free();
   ds->H.alloc(size_t(sum_nb) * Q * jb * es);
   ds->data.alloc(size_t(2) * ds->nbox * Q * size_t(ncol) * es);
   ds->KB.alloc(size_t(sum_nb) * ni);
+  if (sym) ds->HT.alloc(size_t(sum_nb) * Q * ni * es);
   const int64_t box_stride = int64_t(Q) * ncol;
   const char* Obase = prec == OCCK_PREC_FP64 ? reinterpret_cast<const char*>(ds->O.p)
                                              : reinterpret_cast<const char*>(ds->Of.p);
-  std::vector<GemmDesc> dh, dom, dl;
-  std::vector<GemmTile> th, tom, tl2;
+  std::vector<GemmDesc> dh, dom, dl, dht, dlt;
+  std::vector<GemmTile> th, tom, tl2, tht, tlt;
   for (int b = 0; b < nl; ++b) {
     const int nb = int(t->leaf_funcs[b].size());
     const int64_t hoff = ds->f_off[b] * Q * jb;   // H^B[t][q][j], ld Q*jb (elements)
     const int32_t* g = ds->funcs.p + ds->f_off[b];
+    const char* mloc = ds->data.p + int64_t(ds->nbox + ds->leaf_box[b]) * box_stride * es;
     for (int q = 0; q < Q; ++q) {  // H_q = O^B_q C_B[:, J]
       GemmDesc d{};
       d.A = Obase + (ds->O_off[b] + int64_t(q) * nb * nb) * es;
@@ -223,6 +253,15 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
       d.K = nb;
       tiles_for(th, int(dh.size()), d.M, d.N);
       dh.push_back(d);
+      if (sym) {   // HT_q[i][t], column-major store
+        GemmDesc e = d;
+        e.C = ds->HT.p + (ds->f_off[b] * Q * ni + int64_t(q) * ni * nb) * es;
+        e.ldc = 1;
+        e.ldcn = nb;
+        e.N = ni;
+        tiles_for(tht, int(dht.size()), e.M, e.N);
+        dht.push_back(e);
+      }
     }
     {  // Omega[(q,j), i] = sum_t H[t][(q,j)] C[f(t), i0+i]
       GemmDesc d{};
@@ -243,7 +282,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
       d.A = ds->H.p + hoff * es;
       d.sam = int64_t(Q) * jb;
       d.sak = 1;
-      d.B = ds->data.p + int64_t(ds->nbox + ds->leaf_box[b]) * box_stride * es;
+      d.B = mloc;
       d.ldb = ni;
       d.C = ds->KB.p + ds->f_off[b] * ni;
       d.ldc = ni;
@@ -253,7 +292,28 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
       tiles_for(tl2, int(dl.size()), d.M, d.N);
       dl.push_back(d);
     }
+    if (sym) {  // KB[r, jstart + j] += sum_q sum_i Mloc[(q,j), i] HT_q[i][r]: rows j, columns r
+      GemmDesc d{};
+      d.A = mloc;
+      d.sam = ni;
+      d.sak = 1;
+      d.sa_seg = ncol;
+      d.B = ds->HT.p + ds->f_off[b] * Q * ni * es;
+      d.ldb = nb;
+      d.sb_seg = int64_t(ni) * nb;
+      d.nseg = Q;
+      d.C = ds->KB.p + ds->f_off[b] * ni;
+      d.ldc = 1;
+      d.ldcn = ni;
+      d.M = jb;
+      d.N = nb;
+      d.K = ni;
+      tiles_for(tlt, int(dlt.size()), d.M, d.N);
+      dlt.push_back(d);
+    }
   }
+  ds->omega_nt_start = order_by_column_tile(tom);
+  ds->l2p_nt_start = order_by_column_tile(tl2);
   ds->d_half.upload(dh);
   ds->t_half.upload(th);
   ds->d_omega.upload(dom);
@@ -263,9 +323,23 @@ void setup_workspace(Tree* t, int jb, int ni, int prec) {
   ds->n_half = int(th.size());
   ds->n_omega = int(tom.size());
   ds->n_l2p = int(tl2.size());
+  ds->d_ht.free();
+  ds->t_ht.free();
+  ds->d_l2pt.free();
+  ds->t_l2pt.free();
+  ds->n_ht = ds->n_l2pt = 0;
+  if (sym) {
+    ds->d_ht.upload(dht);
+    ds->t_ht.upload(tht);
+    ds->d_l2pt.upload(dlt);
+    ds->t_l2pt.upload(tlt);
+    ds->n_ht = int(tht.size());
+    ds->n_l2pt = int(tlt.size());
+  }
   ds->ws_jb = jb;
   ds->ws_ni = ni;
   ds->ws_prec = prec;
+  ds->ws_sym = int(sym);
 }
 
 // Columns per thread of the small-Q vector translations: 1, 2 (default) or
@@ -281,17 +355,18 @@ static int vec_cols() {
 }
 
 template <class T>
-void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, int64_t ncol, const T* ops,
+void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, const ColMap& cm, const T* ops,
                       hipStream_t st, const int8_t* src_rank) {
   const int Q = t->Q, KS = ksteps_of(Q);
+  if (cm.nvalid <= 0 || ps.ntgt == 0) return;
   if (Q <= 9 && !src_rank) {
     const int NC = vec_cols();
-    const int64_t nblocks = ((ncol + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
+    const int64_t nblocks = ((cm.nvalid + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
     const int64_t grid = ((nblocks + 7) / 8) * 8;
     if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
 #define OCCK_TV(QQ, NN)                                                                                         \
   hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NN>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
-                     ncol, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
+                     cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
 #define OCCK_TVQ(QQ)                   \
   switch (NC) {                        \
     case 1: OCCK_TV(QQ, 1); break;     \
@@ -309,12 +384,12 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
     HIP_OK(hipGetLastError());
     return;
   }
-  const int64_t nct = (ncol + 255) / 256;
+  const int64_t nct = (cm.nvalid + 255) / 256;
   const int64_t nblocks = nct * ps.ntgt;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
 #define OCCK_TR(MT)                                                                                           \
-  hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, ncol, \
+  hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, cm, \
                      Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks, src_rank)
   switch (mtiles_of(Q)) {
     case 1: OCCK_TR(1); break;
@@ -329,10 +404,10 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
   HIP_OK(hipGetLastError());
 }
 
-template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, int64_t, const double*,
+template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, const ColMap&, const double*,
                                        hipStream_t, const int8_t*);
-template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, int64_t, const float*, hipStream_t,
-                                      const int8_t*);
+template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, const ColMap&, const float*,
+                                      hipStream_t, const int8_t*);
 
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st) {
@@ -384,7 +459,7 @@ static void free_state(DeviceState* ds) {
   delete ds;
 }
 
-static int auto_jblock(const Tree* t, int nj, int ni, size_t es) {
+static int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
   const size_t cap = device_cap();
   const int Q = t->Q;
   int64_t sum_nb = 0;
@@ -394,18 +469,28 @@ static int auto_jblock(const Tree* t, int nj, int ni, size_t es) {
   const size_t budget = std::min(cap / 2, size_t(32) << 30);
   int jb = std::min(nj, 256);
   while (jb > 1) {
-    const size_t need = size_t(sum_nb) * Q * jb * es + size_t(2) * nbox * Q * size_t(jb) * ni * es;
-    if (need <= budget) break;
+    if (workspace_need(sum_nb, Q, nbox, jb, ni, es, sym) <= budget) break;
     jb = (jb + 1) / 2;
   }
   return std::max(1, jb);
 }
 
-// One j batch: half transform, Omega, upward, downward, L2P.
+// The j batches.  Per batch J = [jstart, jstart + jb): half transform,
+// Omega, upward, downward, L2P.
+//
+// Symmetric schedule (sym: the i and j ranges coincide).  Omega^B_q and
+// hence every translated Mloc^B_q are symmetric in (i, j) (the AO multipole
+// O^{tu} is symmetric in t, u), so batch J carries only the columns (j, i)
+// with i >= jstart.  K_ri then takes two contractions per batch: l2p over the
+// carried columns, K[r, i] += sum_(q,j in J) H[r,(q,j)] Mloc[(q,j), i] for
+// i >= jstart, and the mirrored l2pt, K[r, j] += sum_q sum_(i >= jstart+jb)
+// H_q[r, i] Mloc[(q,j), i] for j in J, which supplies the pairs (i, j) whose
+// i lies in an earlier batch.  The diagonal block (i, j both in J) is
+// carried in full and counted once.
 template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
                         int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
-                        bool stop_after_up = false) {
+                        bool stop_after_up = false, bool sym = false) {
   using T = typename ModeT<MODE>::T;
   const int Q = t->Q;
   const int64_t ncol = int64_t(jb) * ni;
@@ -414,35 +499,72 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops.p) : reinterpret_cast<const T*>(ds->opsf.p);
   const int nj = j1 - j0;
   const int nblk = (nj + jb - 1) / jb;
+  if (sym) {   // HT for every column, once per call
+    ProfScope ps(ds, prof, OCCK_K_HALF, st);
+    GemmRun r{};
+    r.boff = i0;
+    r.blim = i1;
+    hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(unsigned(ds->n_ht)), dim3(256), 0, st, ds->d_ht.p,
+                       ds->t_ht.p, Cg, ldcg, r);
+  }
   for (int kb = 0; kb < nblk; ++kb) {
-    const int64_t jstart = j0 + int64_t(kb) * jb;
+    const int64_t jrel = int64_t(kb) * jb;          // first j of the batch, relative to j0
+    const int64_t jstart = j0 + jrel;
+    const int64_t istart = sym ? jrel : 0;         // first carried i (relative to i0)
+    const int jbk = int(std::min<int64_t>(jb, nj - jrel));
+    ColMap cm;
+    cm.ncol = ncol;
+    cm.ni = ni;
+    cm.istart = istart;
+    cm.nvalid = int64_t(jb) * (ni - istart);
+    const int ct0 = int(istart / 64);              // first column tile touching i >= istart
     {
       ProfScope ps(ds, prof, OCCK_K_HALF, st);
+      GemmRun r{};
+      r.boff = jstart;
+      r.blim = j1;
       hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
-                         ds->t_half.p, Cg, ldcg, jstart, int64_t(j1), 0);
+                         ds->t_half.p, Cg, ldcg, r);
     }
     {
       ProfScope ps(ds, prof, OCCK_K_OMEGA, st);
-      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(unsigned(ds->n_omega)), dim3(256), 0, st,
-                         ds->d_omega.p, ds->t_omega.p, Cg, ldcg, int64_t(i0), int64_t(i1), 0);
+      GemmRun r{};
+      r.boff = i0;
+      r.blim = i1;
+      r.tile0 = ds->omega_nt_start[size_t(ct0)];
+      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(unsigned(ds->n_omega - r.tile0)), dim3(256), 0, st,
+                         ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
     {
       ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
-      for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, ncol, ops, st);
+      for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, cm, ops, st);
     }
     if (stop_after_up) return;
     if (sel) {
       ProfScope ps(ds, prof, OCCK_K_SELECT, st, 1 + int(ds->down.size()));
-      learned_ranks<T>(t, ds, sel, data, box_stride, ncol, st);
+      learned_ranks<T>(t, ds, sel, data, box_stride, cm, st);
     }
     {
       ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
-      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, ncol, ops, st, sel ? p.rank.p : nullptr);
+      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, cm, ops, st, sel ? p.rank.p : nullptr);
     }
     {
-      ProfScope ps(ds, prof, OCCK_K_L2P, st);
-      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2p)), dim3(256), 0, st,
-                         ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, int64_t(0), int64_t(0), kb > 0 ? 1 : 0);
+      ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < ni ? 2 : 1);
+      GemmRun r{};
+      r.accumulate = kb > 0 ? 1 : 0;
+      r.nlo = int(istart);
+      r.tile0 = ds->l2p_nt_start[size_t(ct0)];
+      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2p - r.tile0)), dim3(256), 0, st,
+                         ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
+      if (sym && jrel + jb < ni) {
+        GemmRun m{};
+        m.accumulate = 1;
+        m.koff = jrel + jb;
+        m.coff = jrel;
+        m.mlim = jbk;
+        hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2pt)), dim3(256), 0, st,
+                           ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
+      }
     }
     HIP_OK(hipGetLastError());
   }
@@ -478,8 +600,9 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
     DeviceState* ds = t->dev;
     if (mixed) ensure_mixed_operands(t, st);
     const size_t es = mixed ? 4 : 8;
-    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es);
-    setup_workspace(t, jb, ni, prec);
+    const bool sym = i0 == j0 && i1 == j1;   // symmetric schedule when the i and j ranges coincide
+    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es, sym);
+    setup_workspace(t, jb, ni, prec, sym);
     const int Q = t->Q;
     const bool prof = t->profile != 0;
     {
@@ -495,13 +618,13 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
     if (prec == OCCK_PREC_FP64)
-      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel);
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
     else if (prec == OCCK_PREC_FP32)
-      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
     else if (prec == OCCK_PREC_BF16X3)
-      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
     else
-      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel);
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,

@@ -22,13 +22,40 @@ struct GemmDesc {       // element types follow the kernel's mode (output: OutT)
   const void* B;       // B(k,n) = B[k*ldb + n]                (gidx == nullptr)
   int64_t ldb;
   const int32_t* gidx; // B(k,n) = Cuser[gidx[k]*ldcu + boff + n] (gather from C)
-  void* C;             // C(m,n) = C[m*ldc + n]
-  int64_t ldc;
-  int32_t M, N, K, pad;
+  void* C;             // C(m,n) = C[m*ldc + n*ldcn]   (ldcn 0 means 1)
+  int64_t ldc, ldcn;
+  // K segments: the contraction runs over nseg (0 means 1) segments of K
+  // terms; segment s reads A + s*sa_seg and B + s*sb_seg (plain B only).
+  int64_t sa_seg, sb_seg;
+  int32_t M, N, K, nseg;
+};
+// Per-launch parameters shared by every tile of one grouped GEMM launch.
+struct GemmRun {
+  int64_t boff, blim;  // gathered B: column offset into Cuser, columns at or beyond blim read as 0
+  int64_t koff;        // every segment contracts k in [koff, K)
+  int64_t coff;        // output pointer offset (elements)
+  int32_t nlo;         // output columns below nlo are not written
+  int32_t mlim;        // output rows at or beyond mlim are not written (0: no limit)
+  int32_t accumulate;  // C += A B instead of C = A B
+  int32_t tile0;       // block b computes tile tile0 + b
 };
 struct GemmTile {
   int32_t prob, mt, nt, pad;
 };
+// Columns carried by the translations of one j batch.  Box data are Q rows
+// of ncol = jb*ni columns, column (j, i) at j*ni + i.  Only columns with
+// i >= istart are carried (the symmetric schedule starts i at the batch's
+// first j); nvalid = jb*(ni - istart) of them, numbered v = j*(ni - istart)
+// + (i - istart).
+struct ColMap {
+  int64_t ncol, ni, istart, nvalid;
+};
+__host__ __device__ inline int64_t carried_col(const ColMap& cm, int64_t v) {
+  if (cm.istart == 0) return v;
+  const int64_t nk = cm.ni - cm.istart;
+  const int64_t j = v / nk;
+  return j * cm.ni + cm.istart + (v - j * nk);
+}
 struct OpParam {
   int32_t type, weighted;
   double d[3];
@@ -265,15 +292,19 @@ struct GemmSmem {
 
 template <int MODE, bool A_KCONTIG, class OutT>
 __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
-                          int64_t ldcu, int64_t boff, int64_t blim, int accumulate, GemmSmem<MODE>& sm) {
+                          int64_t ldcu, const GemmRun& run, GemmSmem<MODE>& sm) {
   using T = typename ModeT<MODE>::T;
   using Acc = typename ModeT<MODE>::Acc;
   constexpr int KT = ModeT<MODE>::KT;
   constexpr int E = KT / 4;          // elements per thread per operand tile
   auto& As = sm.A;
   auto& Bs = sm.B;
-  const T* A = static_cast<const T*>(d.A);
+  const int64_t boff = run.boff, blim = run.blim, koff = run.koff;
   const int m0 = mt * 64, n0 = nt * 64;
+  const int64_t kseg = int64_t(d.K) - koff;                // terms per segment
+  const int nseg = d.nseg > 0 ? d.nseg : 1;
+  const int kpseg = kseg > 0 ? int((kseg + KT - 1) / KT) : 0;  // K tiles per segment
+  const int nsteps = nseg * kpseg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   Acc acc[2][2];
@@ -294,23 +325,27 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   constexpr int TPR = 64 / E;
   const int bk = tid / TPR, bn = (tid % TPR) * E;
   T ra[E], rb[E];
-  auto load = [&](int k0) {
+  // step -> (segment, first k of the tile); k indexes both operands from koff
+  auto load = [&](int step) {
+    const int seg = step / kpseg;
+    const int64_t k0 = koff + int64_t(step - seg * kpseg) * KT;
+    const T* A = static_cast<const T*>(d.A) + int64_t(seg) * d.sa_seg;
     if (A_KCONTIG) {
       const int am = tid >> 2, ak = (tid & 3) * E;
       const int gm = m0 + am;
       for (int u = 0; u < E; ++u) {
-        const int gk = k0 + ak + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
+        const int64_t gk = k0 + ak + u;
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + gk * d.sak] : T(0);
       }
     } else {
       const int ak = tid / TPR, am = (tid % TPR) * E;
-      const int gk = k0 + ak;
+      const int64_t gk = k0 + ak;
       for (int u = 0; u < E; ++u) {
         const int gm = m0 + am + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + int64_t(gk) * d.sak] : T(0);
+        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + gk * d.sak] : T(0);
       }
     }
-    const int gk = k0 + bk;
+    const int64_t gk = k0 + bk;
     if (gk < d.K) {
       if (d.gidx) {
         const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
@@ -319,7 +354,7 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
           rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
         }
       } else {
-        const T* row = static_cast<const T*>(d.B) + int64_t(gk) * d.ldb;
+        const T* row = static_cast<const T*>(d.B) + int64_t(seg) * d.sb_seg + gk * d.ldb;
         for (int u = 0; u < E; ++u) {
           const int gn = n0 + bn + u;
           rb[u] = (gn < d.N) ? row[gn] : T(0);
@@ -340,11 +375,11 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     for (int u = 0; u < E; ++u) Bs[bk][bn + u] = rb[u];
   };
 
-  load(0);
-  for (int k0 = 0; k0 < d.K; k0 += KT) {
+  if (nsteps > 0) load(0);
+  for (int step = 0; step < nsteps; ++step) {
     store();
     __syncthreads();
-    if (k0 + KT < d.K) load(k0 + KT);
+    if (step + 1 < nsteps) load(step + 1);
     if constexpr (MODE == kModeBF16x6) {
       const int kb = 8 * (lane >> 4);
       bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
@@ -413,19 +448,21 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j)
         for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
-  OutT* Cout = static_cast<OutT*>(d.C);
+  OutT* Cout = static_cast<OutT*>(d.C) + run.coff;
+  const int64_t ldcn = d.ldcn ? d.ldcn : 1;
+  const int mend = run.mlim > 0 && run.mlim < d.M ? run.mlim : d.M;
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + wn + j * 16 + (lane & 15);
-      if (col >= d.N) continue;
+      if (col >= d.N || col < run.nlo) continue;
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row >= d.M) continue;
-        OutT* c = Cout + int64_t(row) * d.ldc + col;
+        if (row >= mend) continue;
+        OutT* c = Cout + int64_t(row) * d.ldc + int64_t(col) * ldcn;
         OutT v;
         if constexpr (kFlush) v = OutT(acc64[i][j][r]);
         else v = OutT(acc[i][j][r]);
-        *c = accumulate ? *c + v : v;
+        *c = run.accumulate ? *c + v : v;
       }
     }
   __syncthreads();   // LDS is reused by the caller's next tile
@@ -435,10 +472,10 @@ template <int MODE, bool A_KCONTIG, class OutT>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTile* __restrict__ tiles,
                                                    const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
-                                                   int64_t boff, int64_t blim, int accumulate) {
+                                                   GemmRun run) {
   __shared__ GemmSmem<MODE> sm;
-  const GemmTile tl = tiles[blockIdx.x];
-  gemm_tile<MODE, A_KCONTIG, OutT>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, boff, blim, accumulate, sm);
+  const GemmTile tl = tiles[run.tile0 + int(blockIdx.x)];
+  gemm_tile<MODE, A_KCONTIG, OutT>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
 }
 
 // --------------------------------------------------------------------------
@@ -452,14 +489,22 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
 // src_rank (may be null): per CSR entry the rank p kept in that translation
 // (components l, l' <= p, i.e. the leading (p+1)^2 rows and columns).
 template <class T, int MT>
-__device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t ncol, int Q, int KS,
+__device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int Q, int KS,
                                const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
                                const T* __restrict__ ops, int t, int64_t ct,
                                const int8_t* __restrict__ src_rank = nullptr) {
   using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t colbase = ct * 256 + wave * 64;
+  const int64_t ncol = cm.ncol;
+  const int64_t vbase = ct * 256 + wave * 64;
+  int64_t cols[4];
+  bool ok[4];
+  for (int j = 0; j < 4; ++j) {
+    const int64_t v = vbase + j * 16 + (lane & 15);
+    ok[j] = v < cm.nvalid;
+    cols[j] = ok[j] ? carried_col(cm, v) : 0;
+  }
   Acc acc[MT][4];
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
@@ -477,10 +522,7 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t
     for (int ks = 0; ks < kse; ++ks) {
       const int row = ks * 4 + (lane >> 4);
       T b[4];
-      for (int j = 0; j < 4; ++j) {
-        const int64_t col = colbase + j * 16 + (lane & 15);
-        b[j] = (row < Q && col < ncol) ? X[int64_t(row) * ncol + col] : T(0);
-      }
+      for (int j = 0; j < 4; ++j) b[j] = (row < Q && ok[j]) ? X[int64_t(row) * ncol + cols[j]] : T(0);
       for (int i = 0; i < MT; ++i) {
         if (i * 16 >= nq) break;
         T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
@@ -492,17 +534,16 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, int64_t
   T* Y = data + int64_t(tgt_box[t]) * box_stride;
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 4; ++j) {
-      const int64_t col = colbase + j * 16 + (lane & 15);
-      if (col >= ncol) continue;
+      if (!ok[j]) continue;
       for (int r = 0; r < 4; ++r) {
         const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row < Q) Y[int64_t(row) * ncol + col] = T(acc[i][j][r]);
+        if (row < Q) Y[int64_t(row) * ncol + cols[j]] = T(acc[i][j][r]);
       }
     }
 }
 
 template <class T, int MT>
-__global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
+__global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
                                                         int Q, int KS, const int32_t* __restrict__ tgt_box,
                                                         const int32_t* __restrict__ src_ptr,
                                                         const int32_t* __restrict__ src_box,
@@ -512,7 +553,7 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
-  translate_tile<T, MT>(data, box_stride, ncol, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
+  translate_tile<T, MT>(data, box_stride, cm, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
                         int(logical % ntgt), logical / ntgt, src_rank);
 }
 
@@ -528,7 +569,7 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
 // block order as translate_kernel; block covers 256*NC columns of one target.
 // --------------------------------------------------------------------------
 template <class T, int Q, int NC>
-__global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, int64_t ncol,
+__global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
                                                             int KS, const int32_t* __restrict__ tgt_box,
                                                             const int32_t* __restrict__ src_ptr,
                                                             const int32_t* __restrict__ src_box,
@@ -539,30 +580,35 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
   const int t = int(logical % ntgt);
-  const int64_t c0 = (logical / ntgt) * (256 * NC) + threadIdx.x;
+  const int64_t v0 = (logical / ntgt) * (256 * NC) + threadIdx.x;
+  const int64_t ncol = cm.ncol;
   bool ok[NC];
-  for (int c = 0; c < NC; ++c) ok[c] = c0 + c * 256 < ncol;
+  int64_t col[NC];
+  for (int c = 0; c < NC; ++c) {
+    ok[c] = v0 + c * 256 < cm.nvalid;
+    col[c] = ok[c] ? carried_col(cm, v0 + c * 256) : 0;
+  }
   T acc[NC][Q];
   for (int c = 0; c < NC; ++c)
     for (int i = 0; i < Q; ++i) acc[c][i] = T(0);
   const int64_t opsz = int64_t(KS) * 64;
   const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
   for (int e = e0; e < e1; ++e) {
-    const T* X = data + int64_t(src_box[e]) * box_stride + c0;
+    const T* X = data + int64_t(src_box[e]) * box_stride;
     const T* A = ops + int64_t(src_op[e]) * opsz;
     T x[NC][Q];
     for (int c = 0; c < NC; ++c)
-      for (int k = 0; k < Q; ++k) x[c][k] = ok[c] ? X[int64_t(k) * ncol + c * 256] : T(0);
+      for (int k = 0; k < Q; ++k) x[c][k] = ok[c] ? X[int64_t(k) * ncol + col[c]] : T(0);
     for (int i = 0; i < Q; ++i)
       for (int k = 0; k < Q; ++k) {
         const T a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
         for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, x[c][k], acc[c][i]);
       }
   }
-  T* Y = data + int64_t(tgt_box[t]) * box_stride + c0;
+  T* Y = data + int64_t(tgt_box[t]) * box_stride;
   for (int c = 0; c < NC; ++c)
     if (ok[c])
-      for (int i = 0; i < Q; ++i) Y[int64_t(i) * ncol + c * 256] = acc[c][i];
+      for (int i = 0; i < Q; ++i) Y[int64_t(i) * ncol + col[c]] = acc[c][i];
 }
 
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols

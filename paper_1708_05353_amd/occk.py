@@ -245,17 +245,29 @@ class Tree:
             pass
 
     # ------------------------------------------------------------------
-    def flops(self, ni: int, nj: int) -> dict:
-        """Algorithmic flop counts of one occk_far_K call (paper-as-written,
-        all (j, i) columns carried through the translations)."""
+    def flops(self, ni: int, nj: int, symmetric: bool = False) -> dict:
+        """Algorithmic flop counts of one occk_far_K call.
+
+        symmetric=False: paper-as-written, all ni*nj (j, i) columns carried
+        through the translations.  symmetric=True (i and j over the same n
+        orbitals): Omega and the translated expansions are symmetric in
+        (i, j), so n_c = n(n+1)/2 columns and F_Omega = Q n(n+1) sum_B n_B;
+        the half transform and L2P are unchanged."""
         inf = self.info
         Q = inf.ncomp
-        nc = ni * nj
         if inf.lmin < 0:
             return dict(half=0, omega=0, m2m=0, m2l=0, l2l=0, l2p=0, total=0)
+        if symmetric:
+            if ni != nj:
+                raise ValueError("the symmetric count needs equal i and j ranges")
+            nc = ni * (ni + 1) // 2
+            omega = Q * ni * (ni + 1) * inf.sum_nb
+        else:
+            nc = ni * nj
+            omega = 2 * Q * nj * ni * inf.sum_nb
         f = dict(
             half=2 * Q * inf.npairs * nj,
-            omega=2 * Q * nj * ni * inf.sum_nb,
+            omega=omega,
             m2m=2 * inf.m2m_nnz * nc * inf.n_edges,
             m2l=2 * Q * Q * nc * inf.n_il,
             l2l=2 * inf.m2m_nnz * nc * inf.n_edges,

@@ -1,8 +1,9 @@
 """Many systems in one persistent launch (occk_batch_*).
 
 * FP64 batched K of every system matches the oracle to 1e-8 (normwise).
-* Each precision's batched K matches occk_far_K of the same precision
-  (different j batching, so only the summation order differs).
+* Each precision's batched K matches occk_far_K of the same precision:
+  FP64 to 1e-12; mixed modes to the sum of their bounds against the oracle
+  (the standalone call uses the symmetric schedule).
 * The autotuner returns a valid configuration and keeps results correct.
 * A standalone call on one of the trees (which replaces its workspace)
   before a batched run is handled: the plan rebuilds its tables.
@@ -75,7 +76,11 @@ def test_batched_equals_standalone(systems, prec):
         K1 = torch.zeros_like(Cd)
         occk.far_K(tr, Cd, K1, precision=prec, jblock=4)
         torch.cuda.synchronize()
-        tol = 1e-12 if prec == 0 else 1e-6
+        # FP64: the same arithmetic in another order.  Mixed modes: the
+        # standalone call uses the symmetric schedule (column (j, i) stands
+        # for (i, j)), the batched one all columns, so the two agree only to
+        # the sum of their stated bounds against the FP64 oracle.
+        tol = 1e-12 if prec == 0 else 2 * {1: 1e-6, 2: 5e-5, 3: 1e-6}[prec]
         assert rel(g, K1.cpu().numpy()) <= tol, prec
 
 
