@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <stdexcept>
+#include <tuple>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -177,21 +178,30 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
   ds->bytes = size_t(tot) * 8;
 }
 
+template <class S = GemmSquare>
 static void tiles_for(std::vector<GemmTile>& tiles, int prob, int M, int N) {
-  for (int mt = 0; mt < (M + 63) / 64; ++mt)
-    for (int nt = 0; nt < (N + 63) / 64; ++nt) tiles.push_back({prob, mt, nt, 0});
+  for (int mt = 0; mt < (M + S::BM - 1) / S::BM; ++mt)
+    for (int nt = 0; nt < (N + S::BN - 1) / S::BN; ++nt) tiles.push_back({prob, mt, nt, 0});
 }
 
-// Orders tiles by column tile (stable) and returns, for every column tile c,
-// the index of the first tile with nt >= c (plus the total at the end).
-static std::vector<int32_t> order_by_column_tile(std::vector<GemmTile>& tiles) {
-  std::stable_sort(tiles.begin(), tiles.end(), [](const GemmTile& x, const GemmTile& y) { return x.nt < y.nt; });
-  const int ntmax = tiles.empty() ? 0 : tiles.back().nt + 1;
-  std::vector<int32_t> start(size_t(ntmax) + 1, int32_t(tiles.size()));
-  for (int32_t k = int32_t(tiles.size()) - 1; k >= 0; --k) start[size_t(tiles[size_t(k)].nt)] = k;
-  for (int c = ntmax - 1; c >= 0; --c) start[size_t(c)] = std::min(start[size_t(c)], start[size_t(c) + 1]);
+// Orders tiles for L2 reuse and for launching a suffix of column tiles:
+// key (nt / 4, problem, nt % 4, mt).  The m tiles of one (problem, column
+// tile) are adjacent (they share the B panel), and the 4 column tiles of a
+// chunk follow each other (they share the A panels).  Returns, for every
+// chunk c of 4 column tiles, the index of its first tile (plus the total).
+static std::vector<int32_t> order_by_column_chunk(std::vector<GemmTile>& tiles) {
+  auto key = [](const GemmTile& x) { return std::make_tuple(x.nt / 4, x.prob, x.nt % 4, x.mt); };
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const GemmTile& x, const GemmTile& y) { return key(x) < key(y); });
+  const int nch = tiles.empty() ? 0 : tiles.back().nt / 4 + 1;
+  std::vector<int32_t> start(size_t(nch) + 1, int32_t(tiles.size()));
+  for (int32_t k = int32_t(tiles.size()) - 1; k >= 0; --k) start[size_t(tiles[size_t(k)].nt / 4)] = k;
+  for (int c = nch - 1; c >= 0; --c) start[size_t(c)] = std::min(start[size_t(c)], start[size_t(c) + 1]);
   return start;
 }
+
+// Launch of tiles [tile0, tile0 + n) of a grouped GEMM (grid padded to a
+// multiple of 8 for the XCD-aware order).
+static inline unsigned gemm_grid(int n) { return unsigned(((n + 7) / 8) * 8); }
 
 // Device bytes of one workspace shape (box data, H, HT, KB).
 static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni, size_t es, bool sym) {
@@ -312,8 +322,12 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       dlt.push_back(d);
     }
   }
-  ds->omega_nt_start = order_by_column_tile(tom);
-  ds->l2p_nt_start = order_by_column_tile(tl2);
+  ds->omega_nt_start = order_by_column_chunk(tom);
+  ds->l2p_nt_start = order_by_column_chunk(tl2);
+  // l2pt: the j tiles sharing one HT panel adjacent
+  std::stable_sort(tlt.begin(), tlt.end(), [](const GemmTile& x, const GemmTile& y) {
+    return std::make_tuple(x.prob, x.nt, x.mt) < std::make_tuple(y.prob, y.nt, y.mt);
+  });
   ds->d_half.upload(dh);
   ds->t_half.upload(th);
   ds->d_omega.upload(dom);
@@ -342,44 +356,25 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->ws_sym = int(sym);
 }
 
-// Columns per thread of the small-Q vector translations: 1, 2 (default) or
-// 4, read once from OCCK_TRANSLATE_COLS (a tuning knob; results do not
-// depend on it).
-static int vec_cols() {
-  static const int nc = [] {
-    const char* s = std::getenv("OCCK_TRANSLATE_COLS");
-    const int v = s ? std::atoi(s) : 2;
-    return (v == 1 || v == 4) ? v : 2;
-  }();
-  return nc;
-}
-
 template <class T>
 void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, const ColMap& cm, const T* ops,
                       hipStream_t st, const int8_t* src_rank) {
   const int Q = t->Q, KS = ksteps_of(Q);
   if (cm.nvalid <= 0 || ps.ntgt == 0) return;
   if (Q <= 9 && !src_rank) {
-    const int NC = vec_cols();
+    constexpr int NC = 2;   // columns per thread (1, 2 and 4 measured alike)
     const int64_t nblocks = ((cm.nvalid + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
     const int64_t grid = ((nblocks + 7) / 8) * 8;
     if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_TV(QQ, NN)                                                                                         \
-  hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NN>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
+#define OCCK_TV(QQ)                                                                                            \
+  hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NC>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
                      cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
-#define OCCK_TVQ(QQ)                   \
-  switch (NC) {                        \
-    case 1: OCCK_TV(QQ, 1); break;     \
-    case 4: OCCK_TV(QQ, 4); break;     \
-    default: OCCK_TV(QQ, 2); break;    \
-  }
     switch (Q) {
-      case 1: OCCK_TVQ(1); break;
-      case 4: OCCK_TVQ(4); break;
-      case 9: OCCK_TVQ(9); break;
+      case 1: OCCK_TV(1); break;
+      case 4: OCCK_TV(4); break;
+      case 9: OCCK_TV(9); break;
       default: throw std::invalid_argument("unsupported Q");
     }
-#undef OCCK_TVQ
 #undef OCCK_TV
     HIP_OK(hipGetLastError());
     return;
@@ -504,7 +499,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     GemmRun r{};
     r.boff = i0;
     r.blim = i1;
-    hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(unsigned(ds->n_ht)), dim3(256), 0, st, ds->d_ht.p,
+    r.ntiles = ds->n_ht;
+    hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_ht.p,
                        ds->t_ht.p, Cg, ldcg, r);
   }
   for (int kb = 0; kb < nblk; ++kb) {
@@ -523,7 +519,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       GemmRun r{};
       r.boff = jstart;
       r.blim = j1;
-      hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(unsigned(ds->n_half)), dim3(256), 0, st, ds->d_half.p,
+      r.ntiles = ds->n_half;
+      hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_half.p,
                          ds->t_half.p, Cg, ldcg, r);
     }
     {
@@ -531,8 +528,9 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       GemmRun r{};
       r.boff = i0;
       r.blim = i1;
-      r.tile0 = ds->omega_nt_start[size_t(ct0)];
-      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(unsigned(ds->n_omega - r.tile0)), dim3(256), 0, st,
+      r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
+      r.ntiles = ds->n_omega - r.tile0;
+      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
     {
@@ -553,8 +551,9 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       GemmRun r{};
       r.accumulate = kb > 0 ? 1 : 0;
       r.nlo = int(istart);
-      r.tile0 = ds->l2p_nt_start[size_t(ct0)];
-      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2p - r.tile0)), dim3(256), 0, st,
+      r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
+      r.ntiles = ds->n_l2p - r.tile0;
+      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       if (sym && jrel + jb < ni) {
         GemmRun m{};
@@ -562,7 +561,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
         m.koff = jrel + jb;
         m.coff = jrel;
         m.mlim = jbk;
-        hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(unsigned(ds->n_l2pt)), dim3(256), 0, st,
+        m.ntiles = ds->n_l2pt;
+        hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
                            ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
       }
     }

@@ -37,7 +37,9 @@ struct GemmRun {
   int32_t nlo;         // output columns below nlo are not written
   int32_t mlim;        // output rows at or beyond mlim are not written (0: no limit)
   int32_t accumulate;  // C += A B instead of C = A B
-  int32_t tile0;       // block b computes tile tile0 + b
+  int32_t tile0;       // the launch computes tiles [tile0, tile0 + ntiles)
+  int32_t ntiles;
+  int32_t pad;
 };
 struct GemmTile {
   int32_t prob, mt, nt, pad;
@@ -280,121 +282,140 @@ template <> __device__ inline int acc_row<d4>(int g, int r) { return g + 4 * r; 
 template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; }
 
 // --------------------------------------------------------------------------
-// grouped GEMM: C(m,n) (+)= sum_k A(m,k) B(k,n) over a list of problems;
-// 64x64 output tile per 256-thread block, each wave a 32x32 quadrant (2x2
-// MFMA tiles), K staged through LDS in steps of KT.
+// grouped GEMM: C(m,n) (+)= sum_k A(m,k) B(k,n) over a list of problems.
+// One 256-thread block computes one BM x BN output tile; the 4 waves form a
+// WGM x WGN grid, each wave TM x TN MFMA 16x16 tiles.  K is staged through
+// LDS in steps of KT with the next step's global loads in flight during the
+// current step's MFMAs.
+//   GemmSquare 64 x 64   (2 x 2 waves of 2 x 2 tiles)
+//   GemmTall   192 x 64  (4 x 1 waves of 3 x 4 tiles): all rows of a leaf
+//              (n_B <= 192) in one tile, so the wide operand is read once
+//   GemmWide   64 x 192  (1 x 4 waves of 4 x 3 tiles): the transpose case
 // --------------------------------------------------------------------------
-template <int MODE>
+template <int WGM_, int WGN_, int TM_, int TN_>
+struct GemmShape {
+  static_assert(WGM_ * WGN_ == 4, "four waves");
+  static constexpr int WGM = WGM_, WGN = WGN_, TM = TM_, TN = TN_;
+  static constexpr int BM = WGM * TM * 16, BN = WGN * TN * 16;
+};
+using GemmSquare = GemmShape<2, 2, 2, 2>;
+using GemmTall = GemmShape<4, 1, 3, 4>;
+using GemmWide = GemmShape<1, 4, 4, 3>;
+
+template <int MODE, class S = GemmSquare>
 struct GemmSmem {
-  typename ModeT<MODE>::T A[ModeT<MODE>::KT][64 + 1];
-  typename ModeT<MODE>::T B[ModeT<MODE>::KT][64 + 1];
+  typename ModeT<MODE>::T A[ModeT<MODE>::KT][S::BM + 1];
+  typename ModeT<MODE>::T B[ModeT<MODE>::KT][S::BN + 1];
 };
 
-template <int MODE, bool A_KCONTIG, class OutT>
+template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare>
 __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
-                          int64_t ldcu, const GemmRun& run, GemmSmem<MODE>& sm) {
+                          int64_t ldcu, const GemmRun& run, GemmSmem<MODE, S>& sm) {
   using T = typename ModeT<MODE>::T;
   using Acc = typename ModeT<MODE>::Acc;
   constexpr int KT = ModeT<MODE>::KT;
-  constexpr int E = KT / 4;          // elements per thread per operand tile
+  constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
+  constexpr int EA = BM * KT / 256, EB = BN * KT / 256;   // elements per thread per operand tile
   auto& As = sm.A;
   auto& Bs = sm.B;
-  const int64_t boff = run.boff, blim = run.blim, koff = run.koff;
-  const int m0 = mt * 64, n0 = nt * 64;
+  const int64_t boff = run.boff, blim = run.blim, koff = run.koff;   // koff < 2^31
+  const int m0 = mt * BM, n0 = nt * BN;
   const int64_t kseg = int64_t(d.K) - koff;                // terms per segment
   const int nseg = d.nseg > 0 ? d.nseg : 1;
   const int kpseg = kseg > 0 ? int((kseg + KT - 1) / KT) : 0;  // K tiles per segment
   const int nsteps = nseg * kpseg;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  Acc acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = Acc{};
+  const int wm = (wave % S::WGM) * TM * 16, wn = (wave / S::WGM) * TN * 16;
+  Acc acc[TM][TN];
+  for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
   // FP32 accumulators feeding an FP64 output are flushed into FP64 registers
   // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT terms.
   constexpr bool kFlush = std::is_same<OutT, double>::value && MODE != kModeF64;
   constexpr int FLUSH = 8;
-  double acc64[kFlush ? 2 : 1][kFlush ? 2 : 1][kFlush ? 4 : 1];
+  double acc64[kFlush ? TM : 1][kFlush ? TN : 1][kFlush ? 4 : 1];
   if constexpr (kFlush)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j)
         for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
   int ktile = 0;
-  // A: k-contiguous -> row am = tid/4, k = (tid%4)*E ..; m-contiguous -> k = tid/(64/E), m = (tid%(64/E))*E ..
-  // B: k = tid/(64/E), n = (tid%(64/E))*E ..
-  constexpr int TPR = 64 / E;
-  const int bk = tid / TPR, bn = (tid % TPR) * E;
-  T ra[E], rb[E];
-  // step -> (segment, first k of the tile); k indexes both operands from koff
-  auto load = [&](int step) {
-    const int seg = step / kpseg;
-    const int64_t k0 = koff + int64_t(step - seg * kpseg) * KT;
-    const T* A = static_cast<const T*>(d.A) + int64_t(seg) * d.sa_seg;
+  T ra[EA], rb[EB];
+  // Each thread loads runs of consecutive elements: A k-contiguous: EA
+  // consecutive k of row am; A m-contiguous: EA consecutive m at row ak; B:
+  // EB consecutive n at row bk.
+  constexpr int TPRA = A_KCONTIG ? KT / EA : BM / EA, TPRB = BN / EB;
+  static_assert((A_KCONTIG ? BM : KT) * TPRA == 256 && KT * TPRB == 256, "one pass per operand tile");
+  const int am = A_KCONTIG ? tid / TPRA : (tid % TPRA) * EA;
+  const int ak = A_KCONTIG ? (tid % TPRA) * EA : tid / TPRA;
+  const int bk = tid / TPRB, bn = (tid % TPRB) * EB;
+  // Per-thread operand pointers at k = koff of segment 0; a K tile advances
+  // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
+  const int kend = d.K;                       // k runs over [koff, K) in every segment
+  const int kfirst = int(koff);
+  const bool a_row_ok = A_KCONTIG ? (m0 + am < d.M) : true;
+  const T* pa = static_cast<const T*>(d.A) + int64_t(m0 + am) * d.sam + int64_t(kfirst + ak) * d.sak;
+  const T* pb = d.gidx ? nullptr : static_cast<const T*>(d.B) + int64_t(kfirst + bk) * d.ldb + (n0 + bn);
+  int kt_in_seg = 0;                          // K tile index within the current segment (next load)
+  int seg_loaded = 0;
+  auto load = [&]() {
+    const int k0 = kfirst + kt_in_seg * KT;   // first k of this K tile
+    const int64_t aoff = int64_t(seg_loaded) * d.sa_seg + int64_t(kt_in_seg) * KT * d.sak;
     if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * E;
-      const int gm = m0 + am;
-      for (int u = 0; u < E; ++u) {
-        const int64_t gk = k0 + ak + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + gk * d.sak] : T(0);
-      }
+      for (int u = 0; u < EA; ++u)
+        ra[u] = (a_row_ok && k0 + ak + u < kend) ? pa[aoff + int64_t(u) * d.sak] : T(0);
     } else {
-      const int ak = tid / TPR, am = (tid % TPR) * E;
-      const int64_t gk = k0 + ak;
-      for (int u = 0; u < E; ++u) {
-        const int gm = m0 + am + u;
-        ra[u] = (gm < d.M && gk < d.K) ? A[int64_t(gm) * d.sam + gk * d.sak] : T(0);
-      }
+      const bool kok = k0 + ak < kend;
+      for (int u = 0; u < EA; ++u)
+        ra[u] = (kok && m0 + am + u < d.M) ? pa[aoff + int64_t(u) * d.sam] : T(0);
     }
-    const int64_t gk = k0 + bk;
-    if (gk < d.K) {
+    const int gk = k0 + bk;
+    if (gk < kend) {
       if (d.gidx) {
         const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
-        for (int u = 0; u < E; ++u) {
+        for (int u = 0; u < EB; ++u) {
           const int gn = n0 + bn + u;
           rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
         }
       } else {
-        const T* row = static_cast<const T*>(d.B) + int64_t(seg) * d.sb_seg + gk * d.ldb;
-        for (int u = 0; u < E; ++u) {
-          const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N) ? row[gn] : T(0);
-        }
+        const T* row = pb + int64_t(seg_loaded) * d.sb_seg + int64_t(kt_in_seg) * KT * d.ldb;
+        for (int u = 0; u < EB; ++u) rb[u] = (n0 + bn + u < d.N) ? row[u] : T(0);
       }
     } else {
-      for (int u = 0; u < E; ++u) rb[u] = T(0);
+      for (int u = 0; u < EB; ++u) rb[u] = T(0);
+    }
+    if (++kt_in_seg == kpseg) {
+      kt_in_seg = 0;
+      ++seg_loaded;
     }
   };
   auto store = [&]() {
-    if (A_KCONTIG) {
-      const int am = tid >> 2, ak = (tid & 3) * E;
-      for (int u = 0; u < E; ++u) As[ak + u][am] = ra[u];
-    } else {
-      const int ak = tid / TPR, am = (tid % TPR) * E;
-      for (int u = 0; u < E; ++u) As[ak][am + u] = ra[u];
-    }
-    for (int u = 0; u < E; ++u) Bs[bk][bn + u] = rb[u];
+    if (A_KCONTIG)
+      for (int u = 0; u < EA; ++u) As[ak + u][am] = ra[u];
+    else
+      for (int u = 0; u < EA; ++u) As[ak][am + u] = ra[u];
+    for (int u = 0; u < EB; ++u) Bs[bk][bn + u] = rb[u];
   };
 
-  if (nsteps > 0) load(0);
+  if (nsteps > 0) load();
   for (int step = 0; step < nsteps; ++step) {
     store();
     __syncthreads();
-    if (step + 1 < nsteps) load(step + 1);
+    if (step + 1 < nsteps) load();
     if constexpr (MODE == kModeBF16x6) {
       const int kb = 8 * (lane >> 4);
-      bf16x8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
-      for (int i = 0; i < 2; ++i) {
+      bf16x8 ah[TM], am[TM], al[TM], bh[TN], bm[TN], bl[TN];
+      for (int i = 0; i < TM; ++i) {
         float x[8];
         for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
         split8x3(x, ah[i], am[i], al[i]);
       }
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < TN; ++j) {
         float x[8];
         for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
         split8x3(x, bh[j], bm[j], bl[j]);
       }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {   // smallest terms first
+      for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < TN; ++j) {   // smallest terms first
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
@@ -404,19 +425,19 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
         }
     } else if constexpr (MODE == kModeBF16x3) {
       const int kb = 8 * (lane >> 4);
-      bf16x8 ah[2], al[2], bh[2], bl[2];
-      for (int i = 0; i < 2; ++i) {
+      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
+      for (int i = 0; i < TM; ++i) {
         float x[8];
         for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
         split8(x, ah[i], al[i]);
       }
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < TN; ++j) {
         float x[8];
         for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
         split8(x, bh[j], bl[j]);
       }
-      for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) {
+      for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < TN; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
@@ -425,19 +446,19 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         const int kr = kk + (lane >> 4);
-        T a[2], b[2];
-        for (int i = 0; i < 2; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
-        for (int j = 0; j < 2; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
+        T a[TM], b[TN];
+        for (int i = 0; i < TM; ++i) a[i] = As[kr][wm + i * 16 + (lane & 15)];
+        for (int j = 0; j < TN; ++j) b[j] = Bs[kr][wn + j * 16 + (lane & 15)];
+        for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
       }
     }
     __syncthreads();
     if constexpr (kFlush) {
       if (++ktile == FLUSH) {
         ktile = 0;
-        for (int i = 0; i < 2; ++i)
-          for (int j = 0; j < 2; ++j) {
+        for (int i = 0; i < TM; ++i)
+          for (int j = 0; j < TN; ++j) {
             for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
             acc[i][j] = Acc{};
           }
@@ -445,14 +466,14 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     }
   }
   if constexpr (kFlush)
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < TM; ++i)
+      for (int j = 0; j < TN; ++j)
         for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
   OutT* Cout = static_cast<OutT*>(d.C) + run.coff;
   const int64_t ldcn = d.ldcn ? d.ldcn : 1;
   const int mend = run.mlim > 0 && run.mlim < d.M ? run.mlim : d.M;
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) {
+  for (int i = 0; i < TM; ++i)
+    for (int j = 0; j < TN; ++j) {
       const int col = n0 + wn + j * 16 + (lane & 15);
       if (col >= d.N || col < run.nlo) continue;
       for (int r = 0; r < 4; ++r) {
@@ -468,14 +489,21 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   __syncthreads();   // LDS is reused by the caller's next tile
 }
 
-template <int MODE, bool A_KCONTIG, class OutT>
+template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
                                                    const GemmTile* __restrict__ tiles,
                                                    const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
                                                    GemmRun run) {
-  __shared__ GemmSmem<MODE> sm;
-  const GemmTile tl = tiles[run.tile0 + int(blockIdx.x)];
-  gemm_tile<MODE, A_KCONTIG, OutT>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
+  __shared__ GemmSmem<MODE, S> sm;
+  // XCD-aware order: the grid is a multiple of 8 and hardware block b runs on
+  // XCD b % 8, so XCD x walks the contiguous tile range [x*per, (x+1)*per).
+  // Tiles that share an operand panel are adjacent in the list and hence
+  // share one L2.
+  const int per = int(gridDim.x / 8);
+  const int logical = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
+  if (logical >= run.ntiles) return;
+  const GemmTile tl = tiles[run.tile0 + logical];
+  gemm_tile<MODE, A_KCONTIG, OutT, S>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
 }
 
 // --------------------------------------------------------------------------
