@@ -192,15 +192,17 @@ int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes);
 /* ---- many systems in one persistent launch ---- */
 
 /* Plan for evaluating K^ff of nsys independent systems (all i, all j of
- * each, one j batch per system) in one persistent (cooperative) kernel
- * launch: the same steps as occk_far_K (Eqs. 15-18, operator generation and
- * operand conversion included) become tasks grouped by stage; the blocks
- * share the tasks of a stage and meet at a grid barrier between stages.  trees: live handles with a far field and a common lmax;
+ * each) in one persistent (cooperative) kernel launch: the same steps as
+ * occk_far_K (Eqs. 15-18, operator generation and operand conversion
+ * included, the symmetric schedule over j batches) become tasks grouped by
+ * stage; the blocks share the tasks of a stage and meet at a grid barrier
+ * between stages.  trees: live handles with a far field and a common lmax;
  * the plan keeps pointers to them (free the plan first).  nocc[k]: occupied
  * count of system k.  opts: precision (any OCCK_PREC_*); rank_mode must be
- * FIXED; jblock and accumulate are ignored (K is overwritten).  Uploads the
- * trees and allocates every workspace (synchronous).  Errors: EINVAL,
- * EHANDLE, ENOMEM, EHIP. */
+ * FIXED; jblock: j batch width of every system (0: chosen per system as in
+ * occk_far_K; capped at nocc); accumulate is ignored (K is overwritten).
+ * Uploads the trees and allocates every workspace (synchronous).  Errors:
+ * EINVAL, EHANDLE, ENOMEM, EHIP. */
 int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* nocc, const occk_far_opts* opts,
                           occk_batch** out);
 
@@ -215,8 +217,9 @@ int32_t occk_batch_run(occk_batch* plan, const double* const* C, const int64_t* 
                        const int64_t* ldk, void* hip_stream);
 
 /* Autotuner: runs the batch once per candidate configuration (blocks per
- * compute unit 1/2/4, GEMM tiles per task 1/2, translation column tiles per
- * task 1/4) after a warm-up, keeps the fastest and reports it in
+ * compute unit 2/4/all co-resident (untuned default: all), GEMM tiles per
+ * task 1/2, translation column tiles per task 1/4) after a warm-up, keeps
+ * the fastest and reports it in
  * choice[3] = {blocks per CU, GEMM tiles per task, translation tiles per
  * task} (may be NULL).  Writes K like occk_batch_run.  Synchronous. */
 int32_t occk_batch_tune(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
@@ -229,6 +232,17 @@ int32_t occk_batch_shape(const occk_batch* plan, int32_t* nsys, int32_t* nocc, i
  * task, number of tasks, number of stages, resident-block limit per CU} of
  * the plan's current configuration. */
 int32_t occk_batch_config(const occk_batch* plan, int32_t* config);
+
+/* Diagnostics of the last occk_batch_run/tune launch (synchronises the
+ * device): for stages s < min(cap, nstage), ms[s] = wall-clock duration of
+ * stage s up to and including its grid barrier, type[s] = task type of the
+ * stage (0 opgen, 1 convert, 2 half transform of all columns, 3 half
+ * transform of a j batch, 4 Omega, 5 translation pass, 6 L2P, 7 mirrored
+ * L2P, 8 reduce; the first system that has the stage decides).  Either
+ * array may be NULL; *nstage (may be NULL) receives the stage count.
+ * Before the first launch only *nstage is written.  Errors: EHANDLE,
+ * EINVAL, EHIP. */
+int32_t occk_batch_stage_times(occk_batch* plan, double* ms, int32_t* type, int32_t cap, int32_t* nstage);
 
 /* Frees the plan (after a device synchronisation); NULL is accepted. */
 int32_t occk_batch_free(occk_batch* plan);

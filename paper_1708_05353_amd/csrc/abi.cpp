@@ -320,6 +320,10 @@ int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* 
     set_error("occk_batch_create: only fixed ranks are batched");
     return OCCK_EINVAL;
   }
+  if (o.jblock < 0) {
+    set_error("occk_batch_create: jblock must be >= 0");
+    return OCCK_EINVAL;
+  }
   std::vector<Tree*> ts(nsys);
   for (int k = 0; k < nsys; ++k) {
     Tree* t = reinterpret_cast<Tree*>(trees[k]);
@@ -349,7 +353,7 @@ int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* 
   void* plan = nullptr;
   int32_t rc = OCCK_OK;
   OCCK_GUARD_BEGIN
-  rc = batch_create(nsys, ts.data(), nocc, o.precision, &plan);
+  rc = batch_create(nsys, ts.data(), nocc, o.precision, o.jblock, &plan);
   OCCK_GUARD_END
   if (rc != OCCK_OK) return rc;
   {
@@ -378,6 +382,18 @@ int32_t occk_batch_config(const occk_batch* plan, int32_t* config) {
     return OCCK_EINVAL;
   }
   return batch_shape(plan, nullptr, nullptr, 0, config);
+}
+
+int32_t occk_batch_stage_times(occk_batch* plan, double* ms, int32_t* type, int32_t cap, int32_t* nstage) {
+  if (!plan_live(plan)) {
+    set_error("occk_batch_stage_times: plan is not live");
+    return OCCK_EHANDLE;
+  }
+  if (cap < 0 || (cap > 0 && !ms && !type)) {
+    set_error("occk_batch_stage_times: cap must be >= 0, with ms or type non-NULL when cap > 0");
+    return OCCK_EINVAL;
+  }
+  return batch_stage_times(plan, ms, type, cap, nstage);
 }
 
 static int32_t check_io(int nsys, const double* const* C, const int64_t* ldc, double* const* K, const int64_t* ldk) {

@@ -128,6 +128,8 @@ struct ProfScope {   // records a start/end event pair around a group of launche
 size_t device_cap();
 void upload_tree(Tree* t);
 void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym = false);
+// largest j batch width (<= 256) whose workspace fits min(cap/2, 32 GiB)
+int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym);
 void ensure_mixed_operands(Tree* t, hipStream_t st);
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st);

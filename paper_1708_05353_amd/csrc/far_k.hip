@@ -454,7 +454,7 @@ static void free_state(DeviceState* ds) {
   delete ds;
 }
 
-static int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
+int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
   const size_t cap = device_cap();
   const int Q = t->Q;
   int64_t sum_nb = 0;

@@ -13,6 +13,36 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace occk {
 
+// Global-memory view of a pointer.  Pointers read from device tables (the
+// persistent batched kernel) are generic to the compiler, which then emits
+// flat loads and stores; the tile routines below access every operand
+// through this view so that they compile to global loads and stores.
+template <class T>
+using gbl = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ gbl<T>* as_global(T* p) {
+  return (gbl<T>*)p;
+}
+// Read-only view for tables and operators that no kernel writes while the
+// reading kernel runs (CSR lists, descriptors, operators): wave-uniform
+// loads through it compile to scalar loads.
+template <class T>
+using cst = __attribute__((address_space(4))) T;
+template <class T>
+__device__ __forceinline__ const cst<T>* as_const(const T* p) {
+  return (const cst<T>*)p;
+}
+// Copy of a table entry (a descriptor struct) read through the read-only view.
+template <class S>
+__device__ __forceinline__ S load_const(const S* p) {
+  static_assert(sizeof(S) % 4 == 0, "whole dwords");
+  S out;
+  const cst<uint32_t>* src = (const cst<uint32_t>*)p;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+  for (int i = 0; i < int(sizeof(S) / 4); ++i) dst[i] = src[i];
+  return out;
+}
+
 // --------------------------------------------------------------------------
 // device-side descriptors
 // --------------------------------------------------------------------------
@@ -198,8 +228,8 @@ static __device__ void opgen_one(const OpParam& p, double* out, float* outf, int
       v = real_entry(p.type, tab, row, col);
       if (p.weighted) v *= l2p_weight(row);
     }
-    if (out) out[e] = v;
-    if (outf) outf[e] = float(v);
+    if (out) as_global(out)[e] = v;
+    if (outf) as_global(outf)[e] = float(v);
   }
   __syncthreads();
 }
@@ -353,8 +383,12 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   const int kend = d.K;                       // k runs over [koff, K) in every segment
   const int kfirst = int(koff);
   const bool a_row_ok = A_KCONTIG ? (m0 + am < d.M) : true;
-  const T* pa = static_cast<const T*>(d.A) + int64_t(m0 + am) * d.sam + int64_t(kfirst + ak) * d.sak;
-  const T* pb = d.gidx ? nullptr : static_cast<const T*>(d.B) + int64_t(kfirst + bk) * d.ldb + (n0 + bn);
+  const gbl<const T>* pa = as_global(static_cast<const T*>(d.A)) + int64_t(m0 + am) * d.sam +
+                           int64_t(kfirst + ak) * d.sak;
+  const gbl<const T>* pb =
+      d.gidx ? nullptr : as_global(static_cast<const T*>(d.B)) + int64_t(kfirst + bk) * d.ldb + (n0 + bn);
+  const gbl<const T>* cu = as_global(Cuser);
+  const gbl<const int32_t>* gidx = as_global(d.gidx);
   int kt_in_seg = 0;                          // K tile index within the current segment (next load)
   int seg_loaded = 0;
   auto load = [&]() {
@@ -371,13 +405,13 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     const int gk = k0 + bk;
     if (gk < kend) {
       if (d.gidx) {
-        const T* row = Cuser + int64_t(d.gidx[gk]) * ldcu + boff;
+        const gbl<const T>* row = cu + int64_t(gidx[gk]) * ldcu + boff;
         for (int u = 0; u < EB; ++u) {
           const int gn = n0 + bn + u;
           rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
         }
       } else {
-        const T* row = pb + int64_t(seg_loaded) * d.sb_seg + int64_t(kt_in_seg) * KT * d.ldb;
+        const gbl<const T>* row = pb + int64_t(seg_loaded) * d.sb_seg + int64_t(kt_in_seg) * KT * d.ldb;
         for (int u = 0; u < EB; ++u) rb[u] = (n0 + bn + u < d.N) ? row[u] : T(0);
       }
     } else {
@@ -469,7 +503,7 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     for (int i = 0; i < TM; ++i)
       for (int j = 0; j < TN; ++j)
         for (int r = 0; r < 4; ++r) acc64[i][j][r] += double(acc[i][j][r]);
-  OutT* Cout = static_cast<OutT*>(d.C) + run.coff;
+  gbl<OutT>* Cout = as_global(static_cast<OutT*>(d.C)) + run.coff;
   const int64_t ldcn = d.ldcn ? d.ldcn : 1;
   const int mend = run.mlim > 0 && run.mlim < d.M ? run.mlim : d.M;
   for (int i = 0; i < TM; ++i)
@@ -479,7 +513,7 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
         if (row >= mend) continue;
-        OutT* c = Cout + int64_t(row) * d.ldc + int64_t(col) * ldcn;
+        gbl<OutT>* c = Cout + int64_t(row) * d.ldc + int64_t(col) * ldcn;
         OutT v;
         if constexpr (kFlush) v = OutT(acc64[i][j][r]);
         else v = OutT(acc[i][j][r]);
@@ -537,13 +571,15 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 4; ++j) acc[i][j] = Acc{};
   const int64_t opsz = int64_t(MT) * KS * 64;
-  const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
+  const cst<int32_t>* sbox = as_const(src_box);
+  const cst<int32_t>* sop = as_const(src_op);
+  const int e0 = as_const(src_ptr)[t], e1 = as_const(src_ptr)[t + 1];
   for (int e = e0; e < e1; ++e) {
-    const T* X = data + int64_t(src_box[e]) * box_stride;
-    const T* Tm = ops + int64_t(src_op[e]) * opsz;
+    const gbl<const T>* X = as_global(static_cast<const T*>(data)) + int64_t(sbox[e]) * box_stride;
+    const gbl<const T>* Tm = as_global(ops) + int64_t(sop[e]) * opsz;
     int nq = Q, kse = KS;
     if (src_rank) {
-      const int p = src_rank[e];
+      const int p = as_global(src_rank)[e];
       nq = (p + 1) * (p + 1);
       kse = (nq + 3) / 4;
     }
@@ -559,7 +595,7 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
       }
     }
   }
-  T* Y = data + int64_t(tgt_box[t]) * box_stride;
+  gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
   for (int i = 0; i < MT; ++i)
     for (int j = 0; j < 4; ++j) {
       if (!ok[j]) continue;
@@ -597,18 +633,12 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
 // block order as translate_kernel; block covers 256*NC columns of one target.
 // --------------------------------------------------------------------------
 template <class T, int Q, int NC>
-__global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
-                                                            int KS, const int32_t* __restrict__ tgt_box,
-                                                            const int32_t* __restrict__ src_ptr,
-                                                            const int32_t* __restrict__ src_box,
-                                                            const int32_t* __restrict__ src_op,
-                                                            const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+__device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int KS,
+                                   const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
+                                   const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
+                                   const T* __restrict__ ops, int t, int64_t ct) {
   static_assert(Q <= 16, "one operator row tile");
-  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
-  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (logical >= nblocks) return;
-  const int t = int(logical % ntgt);
-  const int64_t v0 = (logical / ntgt) * (256 * NC) + threadIdx.x;
+  const int64_t v0 = ct * (256 * NC) + threadIdx.x;
   const int64_t ncol = cm.ncol;
   bool ok[NC];
   int64_t col[NC];
@@ -620,10 +650,12 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
   for (int c = 0; c < NC; ++c)
     for (int i = 0; i < Q; ++i) acc[c][i] = T(0);
   const int64_t opsz = int64_t(KS) * 64;
-  const int e0 = src_ptr[t], e1 = src_ptr[t + 1];
+  const cst<int32_t>* sbox = as_const(src_box);
+  const cst<int32_t>* sop = as_const(src_op);
+  const int e0 = as_const(src_ptr)[t], e1 = as_const(src_ptr)[t + 1];
   for (int e = e0; e < e1; ++e) {
-    const T* X = data + int64_t(src_box[e]) * box_stride;
-    const T* A = ops + int64_t(src_op[e]) * opsz;
+    const gbl<const T>* X = as_global(static_cast<const T*>(data)) + int64_t(sbox[e]) * box_stride;
+    const cst<T>* A = as_const(ops) + int64_t(sop[e]) * opsz;
     T x[NC][Q];
     for (int c = 0; c < NC; ++c)
       for (int k = 0; k < Q; ++k) x[c][k] = ok[c] ? X[int64_t(k) * ncol + col[c]] : T(0);
@@ -633,10 +665,24 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
         for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, x[c][k], acc[c][i]);
       }
   }
-  T* Y = data + int64_t(tgt_box[t]) * box_stride;
+  gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
   for (int c = 0; c < NC; ++c)
     if (ok[c])
       for (int i = 0; i < Q; ++i) Y[int64_t(i) * ncol + col[c]] = acc[c][i];
+}
+
+template <class T, int Q, int NC>
+__global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
+                                                            int KS, const int32_t* __restrict__ tgt_box,
+                                                            const int32_t* __restrict__ src_ptr,
+                                                            const int32_t* __restrict__ src_box,
+                                                            const int32_t* __restrict__ src_op,
+                                                            const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  translate_vec_tile<T, Q, NC>(data, box_stride, cm, KS, tgt_box, src_ptr, src_box, src_op, ops,
+                               int(logical % ntgt), logical / ntgt);
 }
 
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
@@ -654,8 +700,11 @@ __device__ inline void reduce_elem(const double* __restrict__ KB, int64_t ni, co
                                    const int32_t* __restrict__ occ_row, double* __restrict__ K, int64_t ldk, int i0,
                                    int accumulate, int r, int64_t i) {
   double s = 0.0;
-  for (int e = occ_ptr[r]; e < occ_ptr[r + 1]; ++e) s += KB[int64_t(occ_row[e]) * ni + i];
-  double* k = K + int64_t(r) * ldk + i0 + i;
+  const gbl<const int32_t>* op = as_global(occ_ptr);
+  const gbl<const int32_t>* orow = as_global(occ_row);
+  const gbl<const double>* kb = as_global(KB);
+  for (int e = op[r]; e < op[r + 1]; ++e) s += kb[int64_t(orow[e]) * ni + i];
+  gbl<double>* k = as_global(K) + int64_t(r) * ldk + i0 + i;
   *k = accumulate ? *k + s : s;
 }
 

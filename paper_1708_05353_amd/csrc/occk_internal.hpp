@@ -97,12 +97,13 @@ int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);
 int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);
 int32_t profile_read(Tree* t, double* ms, int64_t* launches);
 int32_t workspace_info(Tree* t, int32_t* jblock, int64_t* bytes);
-int32_t batch_create(int nsys, Tree* const* trees, const int32_t* nocc, int prec, void** out);
+int32_t batch_create(int nsys, Tree* const* trees, const int32_t* nocc, int prec, int jblock, void** out);
 int32_t batch_run(void* plan, const double* const* C, const int64_t* ldc, double* const* K, const int64_t* ldk,
                   void* stream);
 int32_t batch_tune(void* plan, const double* const* C, const int64_t* ldc, double* const* K, const int64_t* ldk,
                    void* stream, int32_t* choice);
 int32_t batch_free(void* plan);
+int32_t batch_stage_times(void* plan, double* ms, int32_t* type, int cap, int32_t* nstage);
 int32_t batch_shape(const void* plan, int32_t* nsys, int32_t* nocc, int cap, int32_t* tuned);
 int32_t selector_create(int32_t seed, void** out);
 int32_t selector_free(void* sel);

@@ -73,6 +73,8 @@ EXPORTS = {
                                      ct.c_void_p]),
     "occk_batch_shape": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_void_p, ct.c_int32]),
     "occk_batch_config": (ct.c_int32, [ct.c_void_p, ct.c_void_p]),
+    "occk_batch_stage_times": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int32,
+                                            ct.POINTER(ct.c_int32)]),
     "occk_batch_free": (ct.c_int32, [ct.c_void_p]),
     "occk_selector_create": (ct.c_int32, [ct.c_int32, ct.POINTER(ct.c_void_p)]),
     "occk_selector_free": (ct.c_int32, [ct.c_void_p]),
@@ -309,11 +311,11 @@ def debug_mfma_probe(kind: int, ia: int, ka: int, jb: int) -> np.ndarray:
 class Batch:
     """Many systems in one persistent launch (occk_batch_*)."""
 
-    def __init__(self, trees, noccs, precision: int = PREC_FP32):
+    def __init__(self, trees, noccs, precision: int = PREC_FP32, jblock: int = 0):
         self.trees = list(trees)
         arr = (ct.c_void_p * len(self.trees))(*[t.handle.value for t in self.trees])
         no = np.ascontiguousarray(noccs, dtype=np.int32)
-        opts = _Opts(int(precision), RANK_FIXED, None, 0, 0)
+        opts = _Opts(int(precision), RANK_FIXED, None, int(jblock), 0)
         h = ct.c_void_p()
         _check(lib().occk_batch_create(len(self.trees), ct.cast(arr, ct.c_void_p), no.ctypes.data, ct.byref(opts),
                                        ct.byref(h)))
@@ -330,6 +332,15 @@ class Batch:
         )
         a, b, c, d = self._keep
         return ct.cast(a, ct.c_void_p), b.ctypes.data, ct.cast(c, ct.c_void_p), d.ctypes.data
+
+    def stage_times(self):
+        """(ms per stage, task type per stage) of the last launch."""
+        n = ct.c_int32()
+        _check(lib().occk_batch_stage_times(self._h, None, None, 0, ct.byref(n)))
+        ms = np.zeros(max(1, n.value), np.float64)
+        ty = np.zeros(max(1, n.value), np.int32)
+        _check(lib().occk_batch_stage_times(self._h, ms.ctypes.data, ty.ctypes.data, n.value, ct.byref(n)))
+        return ms[:n.value], ty[:n.value]
 
     def run(self, Cs, Ks, stream=None):
         import torch

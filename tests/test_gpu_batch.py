@@ -4,6 +4,7 @@
 * Each precision's batched K matches occk_far_K of the same precision:
   FP64 to 1e-12; mixed modes to the sum of their bounds against the oracle
   (the standalone call uses the symmetric schedule).
+* Several j batches per system (explicit jblock) match the oracle.
 * The autotuner returns a valid configuration and keeps results correct.
 * A standalone call on one of the trees (which replaces its workspace)
   before a batched run is handled: the plan rebuilds its tables.
@@ -84,13 +85,32 @@ def test_batched_equals_standalone(systems, prec):
         assert rel(g, K1.cpu().numpy()) <= tol, prec
 
 
+@pytest.mark.parametrize("prec,jblock,tol", [(0, 16, 1e-8), (1, 7, 1e-6), (0, 64, 1e-8)],
+                         ids=["fp64-jb16", "fp32-jb7", "fp64-jb64"])
+def test_batched_j_batches_match_oracle(systems, prec, jblock, tol):
+    """Several j batches per system (symmetric schedule inside the
+    persistent launch): first carried column inside 64-column GEMM tiles,
+    ragged last batches, systems with one batch beside systems with many."""
+    import torch
+    from paper_1708_05353_amd import occk
+    Cs, Ks = _io(systems)
+    b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], prec, jblock=jblock)
+    print(f"[batch] prec {prec} jblock {jblock}", flush=True)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    for (wl, C, tr), K in zip(systems, Ks):
+        ref = oracle_far_K(Setup(wl.system, wl.params), C)
+        assert rel(K.cpu().numpy(), ref) <= tol
+    b.free()
+
+
 def test_autotune_then_run(systems):
     import torch
     from paper_1708_05353_amd import occk
     Cs, Ks = _io(systems)
     b = occk.Batch([tr for _, _, tr in systems], [C.shape[1] for _, C, _ in systems], occk.PREC_FP32)
     choice = b.tune(Cs, Ks)
-    assert choice[0] in (1, 2, 4) and choice[1] in (1, 2) and choice[2] in (1, 4)
+    assert 1 <= choice[0] <= 8 and choice[1] in (1, 2) and choice[2] in (1, 4)
     cfg = b.config()
     assert (cfg["blocks_per_cu"], cfg["gemm_group"], cfg["trans_group"]) == choice
     for K in Ks:
@@ -117,3 +137,17 @@ def test_plan_survives_standalone_call(systems):
     assert rel(Ks[1].cpu().numpy(), ref) <= 1e-6
     assert rel(K1.cpu().numpy(), ref) <= 1e-6
     b.free()
+
+
+def test_spilling_persistent_kernel_is_refused():
+    """lmax = 4 needs a persistent kernel that spills registers; the plan is
+    refused at creation (before any launch) with an error."""
+    import torch
+    from paper_1708_05353_amd import occk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = workloads.water_cluster(6, 40, lmax=4, depth=3)
+    tr = occk.Tree(wl.system, wl.params)
+    with pytest.raises(occk.OcckError, match="spill"):
+        occk.Batch([tr], [wl.system.nocc], occk.PREC_FP64)
+    tr.free()
