@@ -164,10 +164,136 @@ def copy_probe(mb: int):
     print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8}), flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "alkane_L2_fp64_hbm_traffic.md")
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the library's device and host sources: counters taken
+    with other sources do not describe the current kernels."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1708_05353_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls: str):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None when it is missing or was taken on other sources."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if line.startswith("<!-- traffic "):
+                    rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                    if rec["digest"] != kernel_source_digest():
+                        return None
+                    return rec["per_launch_bytes"].get(cls)
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
+def _pmc_rows(d, counter):
+    import csv
+    import glob
+    import re
+    rows = {}
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                rows[int(r["Dispatch_Id"])] = (re.sub(r"\(.*", "", r["Kernel_Name"]), float(r["Counter_Value"]))
+    return rows
+
+
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, cmds):
+    """Per-class HBM traffic of the last occk_far_K call recorded by two
+    rocprofv3 --pmc runs of 'bench.py --steps 1 --warmup 0' (FETCH_SIZE,
+    WRITE_SIZE; KiB per dispatch), scaled by what the same counters read for
+    a plain copy of copy_mib MiB; prints a markdown summary."""
+    import workloads
+    from paper_1708_05353_amd import occk
+    cf = _pmc_rows(copy_fetch_dir, "FETCH_SIZE")
+    cw = _pmc_rows(copy_write_dir, "WRITE_SIZE")
+    nbytes = copy_mib * (1 << 20)
+    fk = [v for k, v in cf.values() if "copyBuffer" in k]
+    wk = [v for k, v in cw.values() if "copyBuffer" in k]
+    fetch_scale = nbytes / (fk[0] * 1024)
+    write_scale = nbytes / (wk[0] * 1024)
+    F = _pmc_rows(fetch_dir, "FETCH_SIZE")
+    W = _pmc_rows(write_dir, "WRITE_SIZE")
+    wl = workloads.alkane_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    info = tr.info
+    n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
+    ids = sorted(i for i in F if "occk::" in F[i][0])
+    start = max(i for i in ids if "opgen" in F[i][0])      # the last call
+    seq = [i for i in ids if i >= start]
+    cls_of, state, ntr = {}, "ht", 0
+    for i in seq:
+        k = F[i][0]
+        if "opgen" in k:
+            c = "opgen"
+        elif "reduce" in k:
+            c = "reduce"
+        elif "gemm_kernel<0, false" in k:
+            c, ntr = "omega", 0
+        elif "translate" in k:
+            ntr += 1
+            c = "up" if ntr <= n_up else "down"
+            if ntr == n_up + n_down:
+                state = "l2p"
+        elif "gemm_kernel<0, true" in k:
+            c = {"ht": "half", "half": "half", "l2p": "l2p", "l2pt": "l2p"}[state]
+            state = {"ht": "half", "half": "half", "l2p": "l2pt", "l2pt": "half"}[state]
+        else:
+            raise SystemExit(f"unexpected kernel in the sequence: {k}")
+        cls_of[i] = c
+    tot = {}
+    for i, c in cls_of.items():
+        n, fb, wb = tot.get(c, (0, 0.0, 0.0))
+        tot[c] = (n + 1, fb + F[i][1] * 1024 * fetch_scale, wb + W.get(i, ("", 0.0))[1] * 1024 * write_scale)
+    jb = 256
+    costs = class_costs(info, wl.system.nocc, jb, "fp64")
+    print("# HBM traffic per kernel class: alkane chain, L = 2, FP64 (one occk_far_K call)\n")
+    print("Commands (repository root, one MI355X, `export TMPDIR=/tmp`):\n\n```")
+    for c in cmds:
+        print(c)
+    print("```\n")
+    print(f"Scale factors from the {copy_mib} MiB copy: FETCH_SIZE x{fetch_scale:.3f}, WRITE_SIZE x{write_scale:.3f} "
+          "(bytes moved per byte the counter reports).  Algorithmic bytes: the compulsory traffic of the schedule "
+          "as executed (`class_costs` in bench.py).  The half class includes the all-column HT transform, l2p "
+          "both L2P contractions.\n")
+    print("| class | launches | HBM read GB | HBM write GB | HBM total GB | algorithmic GB | ratio | bytes per launch |")
+    print("|---|---|---|---|---|---|---|---|")
+    per_launch = {}
+    for c in ["half", "omega", "up", "down", "l2p", "reduce"]:
+        if c not in tot:
+            continue
+        n, fb, wb = tot[c]
+        alg = costs[c][1]
+        per_launch[c] = (fb + wb) / n
+        print(f"| {c} | {n} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {(fb + wb) / 1e9:.2f} | {alg / 1e9:.2f} | "
+              f"{(fb + wb) / alg:.2f} | {per_launch[c]:.4g} |")
+    print()
+    print("<!-- traffic " + json.dumps({"digest": kernel_source_digest(), "fetch_scale": round(fetch_scale, 4),
+                                        "write_scale": round(write_scale, 4),
+                                        "per_launch_bytes": {k: round(v) for k, v in per_launch.items()}}) + " -->")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16"])
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; run only a plain copy of that size")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (CPU only)")
+    ap.add_argument("--pmc-copy-mib", type=int, default=1024)
+    ap.add_argument("--pmc-commands", nargs="*", default=[])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
@@ -184,6 +310,9 @@ def main():
 
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary, args.pmc_copy_mib, args.pmc_commands)
         return
     if args.workload == "batch16":
         bench_batch(args)
@@ -259,6 +388,11 @@ def main():
         pk = PEAK_FLOPS[args.precision] / 1e12
         roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(pk, 1), "unit": "TFLOP/s",
                 "frac": round(ach / pk, 4), "traffic": None, "kernel": dom}
+    nl_dom = breakdown[dom]["launches_per_step"]
+    roof["alg_bytes_per_launch"] = round(nbytes / max(1, nl_dom))
+    roof["alg_flops_per_launch"] = round(flops / max(1, nl_dom))
+    if args.precision == "fp64" and args.lmax == 2 and args.jblock in (0, 256):
+        roof["traffic"] = measured_traffic(dom)   # HBM bytes per launch from the counter summary, if current
     out = {
         "metric": "far-field K_ri GFLOP/s",
         "value": round(value, 1),
