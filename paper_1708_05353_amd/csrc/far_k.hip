@@ -500,7 +500,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     r.boff = i0;
     r.blim = i1;
     r.ntiles = ds->n_ht;
-    hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_ht.p,
+    hipLaunchKernelGGL((half_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_ht.p,
                        ds->t_ht.p, Cg, ldcg, r);
   }
   for (int kb = 0; kb < nblk; ++kb) {
@@ -520,7 +520,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.boff = jstart;
       r.blim = j1;
       r.ntiles = ds->n_half;
-      hipLaunchKernelGGL((gemm_kernel<MODE, true, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_half.p,
+      hipLaunchKernelGGL((half_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_half.p,
                          ds->t_half.p, Cg, ldcg, r);
     }
     {
@@ -530,7 +530,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.blim = i1;
       r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
       r.ntiles = ds->n_omega - r.tile0;
-      hipLaunchKernelGGL((gemm_kernel<MODE, false, T>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+      hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
     {
@@ -553,7 +553,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.nlo = int(istart);
       r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
       r.ntiles = ds->n_l2p - r.tile0;
-      hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+      hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       if (sym && jrel + jb < ni) {
         GemmRun m{};
@@ -562,7 +562,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
         m.coff = jrel;
         m.mlim = jbk;
         m.ntiles = ds->n_l2pt;
-        hipLaunchKernelGGL((gemm_kernel<MODE, true, double>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
+        hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
                            ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
       }
     }

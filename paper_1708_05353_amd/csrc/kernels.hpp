@@ -332,22 +332,22 @@ using GemmSquare = GemmShape<2, 2, 2, 2>;
 using GemmTall = GemmShape<4, 1, 3, 4>;
 using GemmWide = GemmShape<1, 4, 4, 3>;
 
-template <int MODE, class S = GemmSquare>
+// NB = 2: double-buffered operand tiles (one barrier per K tile); NB = 1:
+// single buffer (two barriers per K tile, half the LDS).
+template <int MODE, class S = GemmSquare, int NB = 1>
 struct GemmSmem {
-  typename ModeT<MODE>::T A[ModeT<MODE>::KT][S::BM + 1];
-  typename ModeT<MODE>::T B[ModeT<MODE>::KT][S::BN + 1];
+  typename ModeT<MODE>::T A[NB][ModeT<MODE>::KT][S::BM + 1];
+  typename ModeT<MODE>::T B[NB][ModeT<MODE>::KT][S::BN + 1];
 };
 
-template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare>
+template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare, int NB = 1>
 __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
-                          int64_t ldcu, const GemmRun& run, GemmSmem<MODE, S>& sm) {
+                          int64_t ldcu, const GemmRun& run, GemmSmem<MODE, S, NB>& sm) {
   using T = typename ModeT<MODE>::T;
   using Acc = typename ModeT<MODE>::Acc;
   constexpr int KT = ModeT<MODE>::KT;
   constexpr int BM = S::BM, BN = S::BN, TM = S::TM, TN = S::TN;
   constexpr int EA = BM * KT / 256, EB = BN * KT / 256;   // elements per thread per operand tile
-  auto& As = sm.A;
-  auto& Bs = sm.B;
   const int64_t boff = run.boff, blim = run.blim, koff = run.koff;   // koff < 2^31
   const int m0 = mt * BM, n0 = nt * BN;
   const int64_t kseg = int64_t(d.K) - koff;                // terms per segment
@@ -422,19 +422,32 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       ++seg_loaded;
     }
   };
-  auto store = [&]() {
+  auto store = [&](int buf) {
+    auto& Aw = sm.A[buf];
+    auto& Bw = sm.B[buf];
     if (A_KCONTIG)
-      for (int u = 0; u < EA; ++u) As[ak + u][am] = ra[u];
+      for (int u = 0; u < EA; ++u) Aw[ak + u][am] = ra[u];
     else
-      for (int u = 0; u < EA; ++u) As[ak][am + u] = ra[u];
-    for (int u = 0; u < EB; ++u) Bs[bk][bn + u] = rb[u];
+      for (int u = 0; u < EA; ++u) Aw[ak][am + u] = ra[u];
+    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = rb[u];
   };
 
-  if (nsteps > 0) load();
+  if (nsteps > 0) {
+    load();
+    if constexpr (NB == 2) {
+      store(0);
+      __syncthreads();
+    }
+  }
   for (int step = 0; step < nsteps; ++step) {
-    store();
-    __syncthreads();
+    const int cur = NB == 2 ? (step & 1) : 0;
+    if constexpr (NB == 1) {
+      store(0);
+      __syncthreads();
+    }
     if (step + 1 < nsteps) load();
+    auto& As = sm.A[cur];
+    auto& Bs = sm.B[cur];
     if constexpr (MODE == kModeBF16x6) {
       const int kb = 8 * (lane >> 4);
       bf16x8 ah[TM], am[TM], al[TM], bh[TN], bm[TN], bl[TN];
@@ -487,6 +500,10 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
           for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
       }
     }
+    // NB = 2: the next tile goes to the other buffer, whose last readers
+    // passed the previous barrier; one barrier publishes it.
+    if constexpr (NB == 2)
+      if (step + 1 < nsteps) store(cur ^ 1);
     __syncthreads();
     if constexpr (kFlush) {
       if (++ktile == FLUSH) {
@@ -524,11 +541,10 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
 }
 
 template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ descs,
-                                                   const GemmTile* __restrict__ tiles,
-                                                   const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
-                                                   GemmRun run) {
-  __shared__ GemmSmem<MODE, S> sm;
+__device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
+                                             const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
+                                             const GemmRun& run) {
+  __shared__ GemmSmem<MODE, S, 2> sm;
   // XCD-aware order: the grid is a multiple of 8 and hardware block b runs on
   // XCD b % 8, so XCD x walks the contiguous tile range [x*per, (x+1)*per).
   // Tiles that share an operand panel are adjacent in the list and hence
@@ -537,8 +553,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmDesc* __restrict__ 
   const int logical = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
   if (logical >= run.ntiles) return;
   const GemmTile tl = tiles[run.tile0 + logical];
-  gemm_tile<MODE, A_KCONTIG, OutT, S>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
+  gemm_tile<MODE, A_KCONTIG, OutT, S, 2>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
 }
+
+// One kernel per contraction, so that profiles name the step:
+//   half_kernel   H = O C (Eq. 15a), per j batch and for all columns (HT)
+//   omega_kernel  Omega = H^T C (Eq. 15b)
+//   l2p_kernel    K partials from the carried columns (Eq. 18)
+//   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
+#define OCCK_GEMM_KERNEL(NAME, AK, OUT)                                                                        \
+  template <int MODE>                                                                                          \
+  __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
+                                              const GemmTile* __restrict__ tiles,                              \
+                                              const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu, \
+                                              GemmRun run) {                                                   \
+    gemm_grouped<MODE, AK, OUT>(descs, tiles, Cuser, ldcu, run);                                               \
+  }
+OCCK_GEMM_KERNEL(half_kernel, true, typename ModeT<MODE>::T)
+OCCK_GEMM_KERNEL(omega_kernel, false, typename ModeT<MODE>::T)
+OCCK_GEMM_KERNEL(l2p_kernel, true, double)
+OCCK_GEMM_KERNEL(l2pt_kernel, true, double)
+#undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
 // translation: out[t] = sum_{e in CSR(t)} T[op_e] * data[src_e]   (overwrite)
