@@ -191,8 +191,9 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
               translate_vec_tile<T, QV, kVecCols>(static_cast<T*>(S.data), S.box_stride, cm, S.KS, P.tgt_box,
                                                   P.src_ptr, P.src_box, P.src_op, ops, int(lb % P.ntgt), lb / P.ntgt);
             else
-              translate_tile<T, MT>(static_cast<T*>(S.data), S.box_stride, cm, S.Q, S.KS, P.tgt_box, P.src_ptr,
-                                    P.src_box, P.src_op, ops, int(lb % P.ntgt), lb / P.ntgt);
+              translate_tile<T, MT, (sizeof(GemmSmem<MODE>) >= sizeof(T) * MT * 4 * MT * 64)>(
+                  static_cast<T*>(S.data), S.box_stride, cm, S.Q, S.KS, P.tgt_box, P.src_ptr, P.src_box, P.src_op,
+                  ops, int(lb % P.ntgt), lb / P.ntgt, nullptr, reinterpret_cast<T*>(&sm));
           }
           break;
         }

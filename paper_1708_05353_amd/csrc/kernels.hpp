@@ -585,12 +585,17 @@ OCCK_GEMM_KERNEL(l2pt_kernel, true, double)
 // --------------------------------------------------------------------------
 // src_rank (may be null): per CSR entry the rank p kept in that translation
 // (components l, l' <= p, i.e. the leading (p+1)^2 rows and columns).
-template <class T, int MT>
+// USE_LDS: op_lds is a block-shared staging area of at least MT*KS*64
+// elements; the 256 threads copy each source's operator into it once and the
+// four waves read their A fragments from LDS (one global read of the
+// operator per block instead of one per wave).  The block then must call
+// this routine with all its threads.
+template <class T, int MT, bool USE_LDS>
 __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int Q, int KS,
                                const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
-                               const T* __restrict__ ops, int t, int64_t ct,
-                               const int8_t* __restrict__ src_rank = nullptr) {
+                               const T* __restrict__ ops, int t, int64_t ct, const int8_t* __restrict__ src_rank,
+                               T* __restrict__ op_lds) {
   using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t ncol = cm.ncol;
@@ -618,16 +623,50 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
       nq = (p + 1) * (p + 1);
       kse = (nq + 3) / 4;
     }
-    for (int ks = 0; ks < kse; ++ks) {
-      const int row = ks * 4 + (lane >> 4);
-      T b[4];
-      for (int j = 0; j < 4; ++j) b[j] = (row < Q && ok[j]) ? X[int64_t(row) * ncol + cols[j]] : T(0);
-      for (int i = 0; i < MT; ++i) {
-        if (i * 16 >= nq) break;
-        T a = Tm[(int64_t(i) * KS + ks) * 64 + lane];
-        if (nq < Q && (i * 16 + (lane & 15) >= nq || row >= nq)) a = T(0);
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a, b[j], acc[i][j]);
+    const int nfi = (nq + 15) / 16;   // row tiles in use (<= MT)
+    if constexpr (USE_LDS) {
+      __syncthreads();   // every wave is done with the previous operator
+      for (int idx = threadIdx.x; idx < MT * KS * 64; idx += 256) {
+        const int frag = idx >> 6, i = frag / KS, ks = frag - i * KS;
+        if (i < nfi && ks < kse) op_lds[idx] = Tm[idx];
       }
+      __syncthreads();
+    }
+    // Branch-free operand loads: every address is in bounds (rows clamped to
+    // Q - 1, invalid columns read column 0) and invalid values are replaced
+    // by zero afterwards.  The next k step's B fragments are in flight
+    // during this step's MFMAs.
+    T bn[4];   // raw values of the next k step (masked when used)
+    auto loadb = [&](int ks, T (&b)[4]) {
+      const int row = ks * 4 + (lane >> 4);
+      const int rc = row < Q ? row : Q - 1;
+      for (int j = 0; j < 4; ++j) b[j] = X[int64_t(rc) * ncol + cols[j]];
+    };
+    if (kse > 0) loadb(0, bn);
+    for (int ks = 0; ks < kse; ++ks) {
+      const bool row_ok = ks * 4 + (lane >> 4) < Q;
+      T b[4];
+      for (int j = 0; j < 4; ++j) b[j] = (row_ok && ok[j]) ? bn[j] : T(0);
+      if (ks + 1 < kse) loadb(ks + 1, bn);
+      T a[MT];
+#pragma unroll
+      for (int i = 0; i < MT; ++i) {
+        const int64_t fi = (int64_t(i) * KS + ks) * 64 + lane;
+        if constexpr (USE_LDS)
+          a[i] = op_lds[fi];
+        else
+          a[i] = T(Tm[fi]);
+      }
+      if (nq < Q) {   // truncated rank: entries with l or l' above p are zero
+        const int row = ks * 4 + (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+          if (i * 16 + (lane & 15) >= nq || row >= nq) a[i] = T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < MT; ++i)   // row tiles beyond the rank are skipped
+        if (i < nfi)
+          for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
     }
   }
   gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
@@ -649,11 +688,12 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
                                                         const int32_t* __restrict__ src_op,
                                                         const T* __restrict__ ops, int ntgt, int64_t nblocks,
                                                         const int8_t* __restrict__ src_rank) {
+  __shared__ T op_lds[MT * 4 * MT * 64];   // KS <= 4 MT
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (logical >= nblocks) return;
-  translate_tile<T, MT>(data, box_stride, cm, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
-                        int(logical % ntgt), logical / ntgt, src_rank);
+  if (logical >= nblocks) return;   // block-uniform
+  translate_tile<T, MT, true>(data, box_stride, cm, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
+                              int(logical % ntgt), logical / ntgt, src_rank, op_lds);
 }
 
 // --------------------------------------------------------------------------
