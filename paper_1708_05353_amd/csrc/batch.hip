@@ -108,6 +108,14 @@ __host__ __device__ static inline int trans_block_cols(int Q) { return Q <= 9 ? 
 // --------------------------------------------------------------------------
 // device side
 // --------------------------------------------------------------------------
+// Shared memory of the persistent kernel: one task at a time uses it.
+template <int MODE>
+union BatchSmem {
+  GemmSmem<MODE, GemmSquare> sq;
+  GemmSmem<MODE, GemmRows48> rows;
+  GemmSmem<MODE, GemmCols48> cols;
+};
+
 // QV > 0: translations as exact-size vector FMAs for Q = QV (L <= 2);
 // QV == 0: MFMA translation tiles with MT row tiles.
 template <int MODE, int MT, int QV>
@@ -115,7 +123,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
                                            int nstage, const BSys* __restrict__ sys,
                                            const BPass* __restrict__ passes, int gemm_group, int trans_group,
                                            uint64_t* __restrict__ stage_clk, int* __restrict__ claim,
-                                           GemmSmem<MODE>& sm) {
+                                           BatchSmem<MODE>& sm) {
   using T = typename ModeT<MODE>::T;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   const bool clock_block = stage_clk && blockIdx.x == 0 && threadIdx.x == 0;
@@ -161,7 +169,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_ht + g);
-            gemm_tile<MODE, true, T>(load_const(S.d_ht + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm);
+            gemm_tile<MODE, true, T, GemmRows48>(load_const(S.d_ht + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTHalf:
@@ -169,14 +177,14 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_half + g);
-            gemm_tile<MODE, true, T>(load_const(S.d_half + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm);
+            gemm_tile<MODE, true, T, GemmRows48>(load_const(S.d_half + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTOmega:
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_omega + g);
-            gemm_tile<MODE, false, T>(load_const(S.d_omega + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm);
+            gemm_tile<MODE, false, T>(load_const(S.d_omega + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.sq);
           }
           break;
         case kTTrans: {     // pass a, logical blocks [b, b + trans_group)
@@ -191,7 +199,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
               translate_vec_tile<T, QV, kVecCols>(static_cast<T*>(S.data), S.box_stride, cm, S.KS, P.tgt_box,
                                                   P.src_ptr, P.src_box, P.src_op, ops, int(lb % P.ntgt), lb / P.ntgt);
             else
-              translate_tile<T, MT, (sizeof(GemmSmem<MODE>) >= sizeof(T) * MT * 4 * MT * 64)>(
+              translate_tile<T, MT, (sizeof(BatchSmem<MODE>) >= sizeof(T) * MT * 4 * MT * 64)>(
                   static_cast<T*>(S.data), S.box_stride, cm, S.Q, S.KS, P.tgt_box, P.src_ptr, P.src_box, P.src_op,
                   ops, int(lb % P.ntgt), lb / P.ntgt, nullptr, reinterpret_cast<T*>(&sm));
           }
@@ -202,7 +210,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.nlo = jrel;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_l2p + g);
-            gemm_tile<MODE, true, double>(load_const(S.d_l2p + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm);
+            gemm_tile<MODE, true, double, GemmRows48>(load_const(S.d_l2p + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTL2PT:
@@ -212,7 +220,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.mlim = (n - jrel < jb) ? n - jrel : jb;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_l2pt + g);
-            gemm_tile<MODE, true, double>(load_const(S.d_l2pt + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm);
+            gemm_tile<MODE, true, double, GemmCols48>(load_const(S.d_l2pt + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.cols);
           }
           break;
         case kTReduce: {    // rows [a, b)
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
     const BTask* __restrict__ tasks, const int32_t* __restrict__ stage_ptr, int nstage, const BSys* __restrict__ sys,
     const BPass* __restrict__ passes, int gemm_group, int trans_group, uint64_t* __restrict__ stage_clk,
     int* __restrict__ claim) {
-  __shared__ GemmSmem<MODE> sm;
+  __shared__ BatchSmem<MODE> sm;
   batch_body<MODE, MT, QV>(tasks, stage_ptr, nstage, sys, passes, gemm_group, trans_group, stage_clk, claim, sm);
 }
 
@@ -250,7 +258,7 @@ __global__ __launch_bounds__(256) void batch_kernel(const BTask* __restrict__ ta
                                                     const BSys* __restrict__ sys, const BPass* __restrict__ passes,
                                                     int gemm_group, int trans_group,
                                                     uint64_t* __restrict__ stage_clk, int* __restrict__ claim) {
-  __shared__ GemmSmem<MODE> sm;
+  __shared__ BatchSmem<MODE> sm;
   batch_body<MODE, MT, QV>(tasks, stage_ptr, nstage, sys, passes, gemm_group, trans_group, stage_clk, claim, sm);
 }
 

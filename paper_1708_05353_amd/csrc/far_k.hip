@@ -261,7 +261,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.M = nb;
       d.N = jb;
       d.K = nb;
-      tiles_for(th, int(dh.size()), d.M, d.N);
+      tiles_for<GemmRows48>(th, int(dh.size()), d.M, d.N);
       dh.push_back(d);
       if (sym) {   // HT_q[i][t], column-major store
         GemmDesc e = d;
@@ -269,7 +269,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
         e.ldc = 1;
         e.ldcn = nb;
         e.N = ni;
-        tiles_for(tht, int(dht.size()), e.M, e.N);
+        tiles_for<GemmRows48>(tht, int(dht.size()), e.M, e.N);
         dht.push_back(e);
       }
     }
@@ -299,7 +299,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.M = nb;
       d.N = ni;
       d.K = Q * jb;
-      tiles_for(tl2, int(dl.size()), d.M, d.N);
+      tiles_for<GemmRows48>(tl2, int(dl.size()), d.M, d.N);
       dl.push_back(d);
     }
     if (sym) {  // KB[r, jstart + j] += sum_q sum_i Mloc[(q,j), i] HT_q[i][r]: rows j, columns r
@@ -318,7 +318,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.M = jb;
       d.N = nb;
       d.K = ni;
-      tiles_for(tlt, int(dlt.size()), d.M, d.N);
+      tiles_for<GemmCols48>(tlt, int(dlt.size()), d.M, d.N);
       dlt.push_back(d);
     }
   }

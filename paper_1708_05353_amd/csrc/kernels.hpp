@@ -317,10 +317,10 @@ template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; 
 // WGM x WGN grid, each wave TM x TN MFMA 16x16 tiles.  K is staged through
 // LDS in steps of KT with the next step's global loads in flight during the
 // current step's MFMAs.
-//   GemmSquare 64 x 64   (2 x 2 waves of 2 x 2 tiles)
-//   GemmTall   192 x 64  (4 x 1 waves of 3 x 4 tiles): all rows of a leaf
-//              (n_B <= 192) in one tile, so the wide operand is read once
-//   GemmWide   64 x 192  (1 x 4 waves of 4 x 3 tiles): the transpose case
+//   GemmSquare 64 x 64  (2 x 2 waves of 2 x 2 tiles)
+//   GemmRows48 48 x 64  (1 x 4 waves of 3 x 1 tiles): a leaf's n_B rows
+//              (typically 80..144) padded to a multiple of 48, not 64
+//   GemmCols48 64 x 48  (4 x 1 waves of 1 x 3 tiles): the transpose case
 // --------------------------------------------------------------------------
 template <int WGM_, int WGN_, int TM_, int TN_>
 struct GemmShape {
@@ -329,8 +329,8 @@ struct GemmShape {
   static constexpr int BM = WGM * TM * 16, BN = WGN * TN * 16;
 };
 using GemmSquare = GemmShape<2, 2, 2, 2>;
-using GemmTall = GemmShape<4, 1, 3, 4>;
-using GemmWide = GemmShape<1, 4, 4, 3>;
+using GemmRows48 = GemmShape<1, 4, 3, 1>;   // 48 x 64: the n_B rows of a leaf in tiles of 48
+using GemmCols48 = GemmShape<4, 1, 1, 3>;   // 64 x 48: the transpose case
 
 // NB = 2: double-buffered operand tiles (one barrier per K tile); NB = 1:
 // single buffer (two barriers per K tile, half the LDS).
@@ -373,10 +373,16 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // Each thread loads runs of consecutive elements: A k-contiguous: EA
   // consecutive k of row am; A m-contiguous: EA consecutive m at row ak; B:
   // EB consecutive n at row bk.
-  constexpr int TPRA = A_KCONTIG ? KT / EA : BM / EA, TPRB = BN / EB;
-  static_assert((A_KCONTIG ? BM : KT) * TPRA == 256 && KT * TPRB == 256, "one pass per operand tile");
-  const int am = A_KCONTIG ? tid / TPRA : (tid % TPRA) * EA;
-  const int ak = A_KCONTIG ? (tid % TPRA) * EA : tid / TPRA;
+  // A k-contiguous with KT not a multiple of EA (tiles of 48 rows): thread
+  // takes column ak = tid % KT of rows am + u * (256 / KT) instead.
+  constexpr bool A_ROWS = A_KCONTIG && (KT % EA != 0);
+  constexpr int TPRA = A_ROWS ? KT : (A_KCONTIG ? KT / EA : BM / EA), TPRB = BN / EB;
+  constexpr int ARS = 256 / KT;   // row stride of the A_ROWS mapping
+  static_assert(A_ROWS ? (256 % KT == 0 && BM == EA * ARS)
+                       : ((A_KCONTIG ? BM : KT) * TPRA == 256), "one pass over the A tile");
+  static_assert(KT * TPRB == 256, "one pass over the B tile");
+  const int am = A_ROWS ? tid / KT : (A_KCONTIG ? tid / TPRA : (tid % TPRA) * EA);
+  const int ak = A_ROWS ? tid % KT : (A_KCONTIG ? (tid % TPRA) * EA : tid / TPRA);
   const int bk = tid / TPRB, bn = (tid % TPRB) * EB;
   // Per-thread operand pointers at k = koff of segment 0; a K tile advances
   // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
@@ -394,7 +400,11 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   auto load = [&]() {
     const int k0 = kfirst + kt_in_seg * KT;   // first k of this K tile
     const int64_t aoff = int64_t(seg_loaded) * d.sa_seg + int64_t(kt_in_seg) * KT * d.sak;
-    if (A_KCONTIG) {
+    if (A_ROWS) {
+      const bool kok = k0 + ak < kend;
+      for (int u = 0; u < EA; ++u)
+        ra[u] = (kok && m0 + am + u * ARS < d.M) ? pa[aoff + int64_t(u) * ARS * d.sam] : T(0);
+    } else if (A_KCONTIG) {
       for (int u = 0; u < EA; ++u)
         ra[u] = (a_row_ok && k0 + ak + u < kend) ? pa[aoff + int64_t(u) * d.sak] : T(0);
     } else {
@@ -425,7 +435,9 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   auto store = [&](int buf) {
     auto& Aw = sm.A[buf];
     auto& Bw = sm.B[buf];
-    if (A_KCONTIG)
+    if (A_ROWS)
+      for (int u = 0; u < EA; ++u) Aw[ak][am + u * ARS] = ra[u];
+    else if (A_KCONTIG)
       for (int u = 0; u < EA; ++u) Aw[ak + u][am] = ra[u];
     else
       for (int u = 0; u < EA; ++u) Aw[ak][am + u] = ra[u];
@@ -561,18 +573,18 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   omega_kernel  Omega = H^T C (Eq. 15b)
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
-#define OCCK_GEMM_KERNEL(NAME, AK, OUT)                                                                        \
+#define OCCK_GEMM_KERNEL(NAME, AK, OUT, SHAPE)                                                                 \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
                                               const GemmTile* __restrict__ tiles,                              \
                                               const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu, \
                                               GemmRun run) {                                                   \
-    gemm_grouped<MODE, AK, OUT>(descs, tiles, Cuser, ldcu, run);                                               \
+    gemm_grouped<MODE, AK, OUT, SHAPE>(descs, tiles, Cuser, ldcu, run);                                        \
   }
-OCCK_GEMM_KERNEL(half_kernel, true, typename ModeT<MODE>::T)
-OCCK_GEMM_KERNEL(omega_kernel, false, typename ModeT<MODE>::T)
-OCCK_GEMM_KERNEL(l2p_kernel, true, double)
-OCCK_GEMM_KERNEL(l2pt_kernel, true, double)
+OCCK_GEMM_KERNEL(half_kernel, true, typename ModeT<MODE>::T, GemmRows48)
+OCCK_GEMM_KERNEL(omega_kernel, false, typename ModeT<MODE>::T, GemmSquare)
+OCCK_GEMM_KERNEL(l2p_kernel, true, double, GemmRows48)
+OCCK_GEMM_KERNEL(l2pt_kernel, true, double, GemmCols48)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
