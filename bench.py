@@ -333,26 +333,20 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
     ids = sorted(i for i in F if "occk::" in F[i][0])
     start = max(i for i in ids if "opgen" in F[i][0])      # the last call
     seq = [i for i in ids if i >= start]
-    cls_of, state, ntr = {}, "ht", 0
-    for i in seq:
+    cls_of, ntr = {}, 0
+    for i in seq:          # translations: n_up upward then n_down downward launches per j batch
         k = F[i][0]
-        if "opgen" in k:
-            c = "opgen"
-        elif "reduce" in k:
-            c = "reduce"
-        elif "gemm_kernel<0, false" in k:
-            c, ntr = "omega", 0
-        elif "translate" in k:
+        if "translate" in k:
             ntr += 1
-            c = "up" if ntr <= n_up else "down"
-            if ntr == n_up + n_down:
-                state = "l2p"
-        elif "gemm_kernel<0, true" in k:
-            c = {"ht": "half", "half": "half", "l2p": "l2p", "l2pt": "l2p"}[state]
-            state = {"ht": "half", "half": "half", "l2p": "l2pt", "l2pt": "half"}[state]
+            cls_of[i] = "up" if (ntr - 1) % (n_up + n_down) < n_up else "down"
+            continue
+        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("half_kernel", "half"),
+                       ("omega_kernel", "omega"), ("l2pt_kernel", "l2p"), ("l2p_kernel", "l2p")):
+            if key in k:
+                cls_of[i] = c
+                break
         else:
             raise SystemExit(f"unexpected kernel in the sequence: {k}")
-        cls_of[i] = c
     tot = {}
     for i, c in cls_of.items():
         n, fb, wb = tot.get(c, (0, 0.0, 0.0))
