@@ -8,7 +8,8 @@ depth 8, ws 2, L = 2), inputs resident in HBM.  Prints one JSON line.
 
 value = algorithmic flops of one call / measured time (GFLOP/s).  The
 roofline object reports the dominant kernel class, timed with HIP events on
-the library's stream inside the timed region.  cpu_baseline times the FP64
+the library's stream inside the timed region.  The "mixed" object times the
+FP32 path on the same inputs and gives its error against the FP64 result.  cpu_baseline times the FP64
 oracle on a bounded j sample of the same workload and scales it linearly in
 the number of j columns.
 """
@@ -395,6 +396,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--jblock", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 mixed-path comparison")
     ap.add_argument("--cpu-sample-j", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -512,6 +514,29 @@ def main():
         "roofline": roof,
         "breakdown": breakdown,
     }
+    if args.precision == "fp64" and not args.no_mixed:
+        # the mixed path on the same inputs: FP32 contractions and translations,
+        # FP64 operators and K accumulation; error against this FP64 result
+        K64 = K.clone()
+        Km = torch.zeros_like(K)
+        mcall = lambda: occk.far_K(tree, Cd, Km, precision=occk.PREC_FP32, jblock=args.jblock, stream=stream)
+        mcall()
+        for _ in range(args.warmup):
+            mcall()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            mcall()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_m = e0.elapsed_time(e1) / args.steps
+        err = float((Km - K64).abs().max() / K64.abs().max())
+        out["mixed"] = {"precision": "fp32", "ms_per_step": round(ms_m, 3),
+                        "value": round(fl["total"] / (ms_m * 1e-3) / 1e9, 1),
+                        "speedup_vs_fp64": round(ms / ms_m, 3), "rel_err_vs_fp64": err, "bound": 1e-6}
+        print(f"[bench] mixed fp32 {ms_m:.2f} ms/step, x{ms / ms_m:.2f}, rel err {err:.2e}", file=sys.stderr,
+              flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, C, fl["total"], nocc, args.cpu_sample_j)
