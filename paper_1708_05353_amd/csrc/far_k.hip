@@ -362,7 +362,7 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
   const int Q = t->Q, KS = ksteps_of(Q);
   if (cm.nvalid <= 0 || ps.ntgt == 0) return;
   if (Q <= 9 && !src_rank) {
-    constexpr int NC = 2;   // columns per thread (1, 2 and 4 measured alike)
+    constexpr int NC = 1;   // columns per thread
     const int64_t nblocks = ((cm.nvalid + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
     const int64_t grid = ((nblocks + 7) / 8) * 8;
     if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");

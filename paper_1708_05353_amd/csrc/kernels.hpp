@@ -719,7 +719,9 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
 // source: Q loads and Q*Q FMAs per column.  Same CSR passes, same XCD-aware
 // block order as translate_kernel; block covers 256*NC columns of one target.
 // --------------------------------------------------------------------------
-template <class T, int Q, int NC>
+// PIPE: the next source's column values are loaded while the current one's
+// products are formed (two register sets); without it, one source at a time.
+template <class T, int Q, int NC, bool PIPE = true>
 __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int KS,
                                    const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                    const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
@@ -740,17 +742,39 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
   const cst<int32_t>* sbox = as_const(src_box);
   const cst<int32_t>* sop = as_const(src_op);
   const int e0 = as_const(src_ptr)[t], e1 = as_const(src_ptr)[t + 1];
-  for (int e = e0; e < e1; ++e) {
-    const gbl<const T>* X = as_global(static_cast<const T*>(data)) + int64_t(sbox[e]) * box_stride;
-    const cst<T>* A = as_const(ops) + int64_t(sop[e]) * opsz;
-    T x[NC][Q];
+  // Raw column values of the next source are in flight while the current
+  // source's products are formed (two register sets, used alternately).
+  // Addresses are always in bounds (invalid columns read column 0); the
+  // values of invalid columns are never stored.
+  const gbl<const T>* base = as_global(static_cast<const T*>(data));
+  T xa[NC][Q], xb[NC][Q];
+  auto fetch = [&](T (&x)[NC][Q], int e) {
+    const gbl<const T>* X = base + int64_t(sbox[e]) * box_stride;
     for (int c = 0; c < NC; ++c)
-      for (int k = 0; k < Q; ++k) x[c][k] = ok[c] ? X[int64_t(k) * ncol + col[c]] : T(0);
+      for (int k = 0; k < Q; ++k) x[c][k] = X[int64_t(k) * ncol + col[c]];
+  };
+  auto apply = [&](const T (&x)[NC][Q], int e) {
+    const cst<T>* A = as_const(ops) + int64_t(sop[e]) * opsz;
     for (int i = 0; i < Q; ++i)
       for (int k = 0; k < Q; ++k) {
         const T a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
         for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, x[c][k], acc[c][i]);
       }
+  };
+  if constexpr (PIPE) {
+    if (e0 < e1) fetch(xa, e0);
+    for (int e = e0; e < e1; e += 2) {
+      if (e + 1 < e1) fetch(xb, e + 1);
+      apply(xa, e);
+      if (e + 1 >= e1) break;
+      if (e + 2 < e1) fetch(xa, e + 2);
+      apply(xb, e + 1);
+    }
+  } else {
+    for (int e = e0; e < e1; ++e) {
+      fetch(xa, e);
+      apply(xa, e);
+    }
   }
   gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
   for (int c = 0; c < NC; ++c)
