@@ -251,6 +251,71 @@ def bench_protein(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_graphene(args):
+    """Graphene-shaped sheet C150H30 (nbasis 2250, nocc 480, quadtree depth 4,
+    ws 2), rank sweep L = 2..8 in FP64, FP32, BF16x3 and BF16x6: time per
+    call, GFLOP/s, the error of each mixed result against the FP64 result at
+    the same L (precision), and the error of the FP64 result at L against
+    FP64 at L = 8 (truncation)."""
+    import torch
+
+    import workloads
+    from paper_1708_05353_amd import occk
+
+    precs = [("fp64", occk.PREC_FP64), ("fp32", occk.PREC_FP32), ("bf16x3", occk.PREC_BF16X3),
+             ("bf16x6", occk.PREC_BF16X6)]
+
+    def timeit(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    def rel(a, b):
+        return float((a - b).abs().max() / b.abs().max())
+
+    rows, K8 = [], None
+    for L in (8, 7, 6, 5, 4, 3, 2):
+        wl = workloads.graphene_flake(lmax=L)
+        tree = occk.Tree(wl.system, wl.params)
+        n = wl.system.nocc
+        Cd = torch.from_numpy(wl.orbitals()).cuda()
+        fl = tree.flops(n, n, symmetric=True)["total"]
+        row = {"lmax": L, "flops_per_call": fl}
+        K64 = None
+        for name, code in precs:
+            K = torch.zeros((wl.system.nbasis, n), dtype=torch.float64, device="cuda")
+            ms = timeit(lambda: occk.far_K(tree, Cd, K, precision=code))
+            row[name] = {"ms": round(ms, 3), "GFLOP/s": round(fl / (ms * 1e-3) / 1e9, 1)}
+            if name == "fp64":
+                K64 = K.clone()
+                if K8 is None:
+                    K8 = K64
+                row["fp64"]["rel_err_vs_L8"] = rel(K64, K8)
+            else:
+                row[name]["rel_err_vs_fp64"] = rel(K, K64)
+                row[name]["speedup_vs_fp64"] = round(row["fp64"]["ms"] / ms, 3)
+        tree.free()
+        rows.append(row)
+        print(f"[bench] L={L}: " + ", ".join(f"{k} {row[k]['ms']:.1f} ms" for k, _ in precs), file=sys.stderr,
+              flush=True)
+    top = rows[0]
+    out = {"metric": "far-field K_ri GFLOP/s (graphene sheet, L=8 FP64; sweep L=2..8 x precision beside it)",
+           "value": top["fp64"]["GFLOP/s"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": top["fp64"]["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "graphene-shaped sheet C150H30 (nbasis 2250, nocc 480), quadtree depth 4, ws 2; "
+                                  "all i and j"},
+           "sweep": sorted(rows, key=lambda r: r["lmax"])}
+    print(json.dumps(out), flush=True)
+
+
 def copy_probe(mb: int):
     """A plain device-to-device copy of a known size, for scaling hardware
     traffic counters (bytes the counters report per byte moved)."""
@@ -382,7 +447,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16", "protein-learned"])
+    ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16", "protein-learned", "graphene-sweep"])
     ap.add_argument("--protein-j", type=int, default=32, help="j sample of the protein-learned workload")
     ap.add_argument("--copy-probe", type=int, default=0, help="MiB; run only a plain copy of that size")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -415,6 +480,9 @@ def main():
         return
     if args.workload == "protein-learned":
         bench_protein(args)
+        return
+    if args.workload == "graphene-sweep":
+        bench_graphene(args)
         return
 
     import torch

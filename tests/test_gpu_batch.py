@@ -151,3 +151,28 @@ def test_spilling_persistent_kernel_is_refused():
     with pytest.raises(occk.OcckError, match="spill"):
         occk.Batch([tr], [wl.system.nocc], occk.PREC_FP64)
     tr.free()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)], ids=["fp64", "fp32"])
+def test_batched_L3_mfma_translations(prec, tol):
+    """lmax = 3 (Q = 16): the persistent kernel's MFMA translation tiles with
+    the operator staged in its shared memory; three uneven systems, two j
+    batches for the larger ones."""
+    import torch
+    from paper_1708_05353_amd import occk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    sysl = [workloads.water_cluster(n, s, lmax=3, depth=3) for n, s in [(6, 40), (9, 41), (12, 42)]]
+    trees = [occk.Tree(wl.system, wl.params) for wl in sysl]
+    Cs = [torch.from_numpy(wl.orbitals()).cuda() for wl in sysl]
+    Ks = [torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda") for wl, C in zip(sysl, Cs)]
+    b = occk.Batch(trees, [C.shape[1] for C in Cs], prec, jblock=32)
+    print(f"[batch] L3 prec {prec}", flush=True)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    for wl, C, K in zip(sysl, Cs, Ks):
+        ref = oracle_far_K(Setup(wl.system, wl.params), C.cpu().numpy())
+        assert rel(K.cpu().numpy(), ref) <= tol
+    b.free()
+    for t in trees:
+        t.free()
