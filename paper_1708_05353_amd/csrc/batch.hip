@@ -169,7 +169,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_ht + g);
-            gemm_tile<MODE, true, T, GemmRows48>(load_const(S.d_ht + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
+            gemm_tile<MODE, true, true, T, GemmRows48>(load_const(S.d_ht + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTHalf:
@@ -177,14 +177,14 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_half + g);
-            gemm_tile<MODE, true, T, GemmRows48>(load_const(S.d_half + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
+            gemm_tile<MODE, true, true, T, GemmRows48>(load_const(S.d_half + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTOmega:
           run.blim = n;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_omega + g);
-            gemm_tile<MODE, false, T>(load_const(S.d_omega + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.sq);
+            gemm_tile<MODE, false, true, T>(load_const(S.d_omega + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.sq);
           }
           break;
         case kTTrans: {     // pass a, logical blocks [b, b + trans_group)
@@ -210,7 +210,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.nlo = jrel;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_l2p + g);
-            gemm_tile<MODE, true, double, GemmRows48>(load_const(S.d_l2p + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
+            gemm_tile<MODE, true, false, double, GemmRows48>(load_const(S.d_l2p + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.rows);
           }
           break;
         case kTL2PT:
@@ -220,7 +220,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           run.mlim = (n - jrel < jb) ? n - jrel : jb;
           for (int g = tk.a; g < tk.b; ++g) {
             const GemmTile tl = load_const(S.t_l2pt + g);
-            gemm_tile<MODE, true, double, GemmCols48>(load_const(S.d_l2pt + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.cols);
+            gemm_tile<MODE, true, false, double, GemmCols48>(load_const(S.d_l2pt + tl.prob), tl.mt, tl.nt, Cg, ldcg, run, sm.cols);
           }
           break;
         case kTReduce: {    // rows [a, b)
@@ -303,7 +303,7 @@ static void build_tasks(BatchPlan& bp) {
       const int jrel = kb * jb;
       const int ch = (jrel / 64) / 4;             // first chunk of 4 column tiles touching i >= jrel
       gemm_stage(kTHalf, 0, ds->n_half, kb);
-      gemm_stage(kTOmega, ds->omega_nt_start[size_t(ch)], ds->n_omega, kb);
+      gemm_stage(kTOmega, ds->omega_nt_start[size_t(ch)], ds->omega_nt_start[size_t(ch) + 1], kb);
       const int64_t nct = (int64_t(jb) * (n - jrel) + tbc - 1) / tbc;
       for (int p = 0; p < np; ++p) {
         const BPass& P = bp.host_passes[size_t(S.pass0 + p)];
@@ -313,7 +313,7 @@ static void build_tasks(BatchPlan& bp) {
           s.t.push_back({kTTrans, sk, p, int32_t(lb), kb, 0});
         v.push_back(s);
       }
-      gemm_stage(kTL2P, ds->l2p_nt_start[size_t(ch)], ds->n_l2p, kb);
+      gemm_stage(kTL2P, ds->l2p_nt_start[size_t(ch)], ds->l2p_nt_start[size_t(ch) + 1], kb);
       if (jrel + jb < n) gemm_stage(kTL2PT, 0, ds->n_l2pt, kb);
     }
     Stage red;

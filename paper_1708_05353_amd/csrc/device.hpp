@@ -85,8 +85,9 @@ struct DeviceState {
   DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
   DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt;
   int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0;
-  // omega and l2p tiles are ordered by chunks of 4 column tiles: the tiles
-  // with nt >= 4c start at index *_nt_start[c]
+  // omega and l2p: one tile list per chunk c of 4 column tiles, holding the
+  // tiles with nt >= 4c, stored one after another; list c is
+  // [*_nt_start[c], *_nt_start[c + 1]) and list 0 holds every tile
   std::vector<int32_t> omega_nt_start, l2p_nt_start;
   size_t bytes = 0;
   // profiling: (class, start, end) event pairs recorded on the call's stream

@@ -184,18 +184,27 @@ static void tiles_for(std::vector<GemmTile>& tiles, int prob, int M, int N) {
     for (int nt = 0; nt < (N + S::BN - 1) / S::BN; ++nt) tiles.push_back({prob, mt, nt, 0});
 }
 
-// Orders tiles for L2 reuse and for launching a suffix of column tiles:
-// key (nt / 4, problem, nt % 4, mt).  The m tiles of one (problem, column
-// tile) are adjacent (they share the B panel), and the 4 column tiles of a
-// chunk follow each other (they share the A panels).  Returns, for every
-// chunk c of 4 column tiles, the index of its first tile (plus the total).
-static std::vector<int32_t> order_by_column_chunk(std::vector<GemmTile>& tiles) {
-  auto key = [](const GemmTile& x) { return std::make_tuple(x.nt / 4, x.prob, x.nt % 4, x.mt); };
+// Tile lists for launching the column tiles nt >= 4c of every problem
+// (c = 0 .. nch-1; the symmetric schedule skips the columns below the first
+// carried one).  List c holds those tiles in the order `key`, problem first,
+// so that a problem's tiles are adjacent in the launch and its operand panels
+// stay in L2 while they run; the lists are stored one after another and list
+// c is [start[c], start[c + 1]).
+template <class Key>
+static std::vector<int32_t> chunked_tile_lists(std::vector<GemmTile>& tiles, Key key) {
   std::stable_sort(tiles.begin(), tiles.end(), [&](const GemmTile& x, const GemmTile& y) { return key(x) < key(y); });
-  const int nch = tiles.empty() ? 0 : tiles.back().nt / 4 + 1;
-  std::vector<int32_t> start(size_t(nch) + 1, int32_t(tiles.size()));
-  for (int32_t k = int32_t(tiles.size()) - 1; k >= 0; --k) start[size_t(tiles[size_t(k)].nt / 4)] = k;
-  for (int c = nch - 1; c >= 0; --c) start[size_t(c)] = std::min(start[size_t(c)], start[size_t(c) + 1]);
+  int nch = 1;
+  for (const GemmTile& x : tiles) nch = std::max(nch, x.nt / 4 + 1);
+  std::vector<int32_t> start;
+  std::vector<GemmTile> out;
+  for (int c = 0; c < nch; ++c) {
+    start.push_back(int32_t(out.size()));
+    for (const GemmTile& x : tiles)
+      if (x.nt >= 4 * c) out.push_back(x);
+    if (out.size() > size_t(INT32_MAX)) throw std::invalid_argument("far_K: too many GEMM tiles");
+  }
+  start.push_back(int32_t(out.size()));
+  tiles.swap(out);
   return start;
 }
 
@@ -322,8 +331,12 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       dlt.push_back(d);
     }
   }
-  ds->omega_nt_start = order_by_column_chunk(tom);
-  ds->l2p_nt_start = order_by_column_chunk(tl2);
+  // omega: the column tiles of one row tile adjacent (they share its panel of
+  // H), a box's gathered rows of C reused from L2 by all its row tiles;
+  // l2p: the row tiles of one column tile adjacent (they share its panel of
+  // Mloc), H of the box reused from L2 by all its column tiles
+  ds->omega_nt_start = chunked_tile_lists(tom, [](const GemmTile& x) { return std::make_tuple(x.prob, x.mt, x.nt); });
+  ds->l2p_nt_start = chunked_tile_lists(tl2, [](const GemmTile& x) { return std::make_tuple(x.prob, x.nt, x.mt); });
   // l2pt: the j tiles sharing one HT panel adjacent
   std::stable_sort(tlt.begin(), tlt.end(), [](const GemmTile& x, const GemmTile& y) {
     return std::make_tuple(x.prob, x.nt, x.mt) < std::make_tuple(y.prob, y.nt, y.mt);
@@ -335,8 +348,8 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->d_l2p.upload(dl);
   ds->t_l2p.upload(tl2);
   ds->n_half = int(th.size());
-  ds->n_omega = int(tom.size());
-  ds->n_l2p = int(tl2.size());
+  ds->n_omega = ds->omega_nt_start.size() > 1 ? ds->omega_nt_start[1] : 0;   // list 0: every tile
+  ds->n_l2p = ds->l2p_nt_start.size() > 1 ? ds->l2p_nt_start[1] : 0;
   ds->d_ht.free();
   ds->t_ht.free();
   ds->d_l2pt.free();
@@ -529,7 +542,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.boff = i0;
       r.blim = i1;
       r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
-      r.ntiles = ds->n_omega - r.tile0;
+      r.ntiles = ds->omega_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
       hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
@@ -552,7 +565,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.accumulate = kb > 0 ? 1 : 0;
       r.nlo = int(istart);
       r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
-      r.ntiles = ds->n_l2p - r.tile0;
+      r.ntiles = ds->l2p_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
       hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                          ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       if (sym && jrel + jb < ni) {

@@ -340,7 +340,7 @@ struct GemmSmem {
   typename ModeT<MODE>::T B[NB][ModeT<MODE>::KT][S::BN + 1];
 };
 
-template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare, int NB = 1>
+template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S = GemmSquare, int NB = 1>
 __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
                           int64_t ldcu, const GemmRun& run, GemmSmem<MODE, S, NB>& sm) {
   using T = typename ModeT<MODE>::T;
@@ -388,85 +388,88 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
   const int kend = d.K;                       // k runs over [koff, K) in every segment
   const int kfirst = int(koff);
-  const bool a_row_ok = A_KCONTIG ? (m0 + am < d.M) : true;
-  const gbl<const T>* pa = as_global(static_cast<const T*>(d.A)) + int64_t(m0 + am) * d.sam +
-                           int64_t(kfirst + ak) * d.sak;
-  const gbl<const T>* pb =
-      d.gidx ? nullptr : as_global(static_cast<const T*>(d.B)) + int64_t(kfirst + bk) * d.ldb + (n0 + bn);
+  const int M = d.M, N = d.N;
+  const int64_t sam = d.sam, sak = d.sak, sa_seg = d.sa_seg, ldb = d.ldb, sb_seg = d.sb_seg;
+  const bool a_row_ok = A_KCONTIG ? (m0 + am < M) : true;
+  const gbl<const T>* A0 = as_global(static_cast<const T*>(d.A));
+  const gbl<const T>* pa = A0 + int64_t(m0 + am) * sam + int64_t(kfirst + ak) * sak;
   const gbl<const T>* cu = as_global(Cuser);
+  const gbl<const T>* B0 = GATHER ? cu : as_global(static_cast<const T*>(d.B));
+  const gbl<const T>* pb = GATHER ? cu : B0 + int64_t(kfirst + bk) * ldb + (n0 + bn);
   const gbl<const int32_t>* gidx = as_global(d.gidx);
   int kt_in_seg = 0;                          // K tile index within the current segment (next load)
   int seg_loaded = 0;
+  // Gathered B: the row of C for the next load's k, fetched one load ahead
+  // so that the operand loads never wait on the index load.
+  int grow = 0;
+  if constexpr (GATHER) {
+    const int gk = kfirst + bk;
+    grow = nsteps > 0 ? gidx[gk < kend ? gk : kfirst] : 0;
+  }
+  // Loads carry no branches: an element outside its operand reads the
+  // operand's first element (present whenever the tile has K work) and is
+  // replaced by zero when it is stored to LDS, so that the MFMAs of the
+  // current K tile do not wait for the loads in flight.
+  bool oka[EA], okb[EB];
   auto load = [&]() {
     const int k0 = kfirst + kt_in_seg * KT;   // first k of this K tile
-    const int64_t aoff = int64_t(seg_loaded) * d.sa_seg + int64_t(kt_in_seg) * KT * d.sak;
-    if (A_ROWS) {
-      const bool kok = k0 + ak < kend;
-      for (int u = 0; u < EA; ++u)
-        ra[u] = (kok && m0 + am + u * ARS < d.M) ? pa[aoff + int64_t(u) * ARS * d.sam] : T(0);
-    } else if (A_KCONTIG) {
-      for (int u = 0; u < EA; ++u)
-        ra[u] = (a_row_ok && k0 + ak + u < kend) ? pa[aoff + int64_t(u) * d.sak] : T(0);
-    } else {
-      const bool kok = k0 + ak < kend;
-      for (int u = 0; u < EA; ++u)
-        ra[u] = (kok && m0 + am + u < d.M) ? pa[aoff + int64_t(u) * d.sam] : T(0);
-    }
-    const int gk = k0 + bk;
-    if (gk < kend) {
-      if (d.gidx) {
-        const gbl<const T>* row = cu + int64_t(gidx[gk]) * ldcu + boff;
-        for (int u = 0; u < EB; ++u) {
-          const int gn = n0 + bn + u;
-          rb[u] = (gn < d.N && boff + gn < blim) ? row[gn] : T(0);
-        }
+    const int64_t aoff = int64_t(seg_loaded) * sa_seg + int64_t(kt_in_seg) * KT * sak;
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      int64_t off;
+      if (A_ROWS) {
+        oka[u] = k0 + ak < kend && m0 + am + u * ARS < M;
+        off = aoff + int64_t(u) * ARS * sam;
+      } else if (A_KCONTIG) {
+        oka[u] = a_row_ok && k0 + ak + u < kend;
+        off = aoff + int64_t(u) * sak;
       } else {
-        const gbl<const T>* row = pb + int64_t(seg_loaded) * d.sb_seg + int64_t(kt_in_seg) * KT * d.ldb;
-        for (int u = 0; u < EB; ++u) rb[u] = (n0 + bn + u < d.N) ? row[u] : T(0);
+        oka[u] = k0 + ak < kend && m0 + am + u < M;
+        off = aoff + int64_t(u) * sam;
       }
-    } else {
-      for (int u = 0; u < EB; ++u) rb[u] = T(0);
+      ra[u] = *(oka[u] ? pa + off : A0);
+    }
+    const bool bkok = k0 + bk < kend;
+    const gbl<const T>* brow = GATHER ? cu + int64_t(grow) * ldcu + boff + (n0 + bn)
+                                      : pb + int64_t(seg_loaded) * sb_seg + int64_t(kt_in_seg) * KT * ldb;
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int gn = n0 + bn + u;
+      okb[u] = bkok && gn < N && (!GATHER || boff + gn < blim);
+      rb[u] = *(okb[u] ? brow + u : B0);
     }
     if (++kt_in_seg == kpseg) {
       kt_in_seg = 0;
       ++seg_loaded;
     }
+    if constexpr (GATHER) {
+      const int gk = kfirst + kt_in_seg * KT + bk;
+      grow = gidx[gk < kend ? gk : kfirst];
+    }
   };
   auto store = [&](int buf) {
     auto& Aw = sm.A[buf];
     auto& Bw = sm.B[buf];
-    if (A_ROWS)
-      for (int u = 0; u < EA; ++u) Aw[ak][am + u * ARS] = ra[u];
-    else if (A_KCONTIG)
-      for (int u = 0; u < EA; ++u) Aw[ak + u][am] = ra[u];
-    else
-      for (int u = 0; u < EA; ++u) Aw[ak][am + u] = ra[u];
-    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = rb[u];
+#pragma unroll
+    for (int u = 0; u < EA; ++u) {
+      const T v = oka[u] ? ra[u] : T(0);
+      if (A_ROWS) Aw[ak][am + u * ARS] = v;
+      else if (A_KCONTIG) Aw[ak + u][am] = v;
+      else Aw[ak][am + u] = v;
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = okb[u] ? rb[u] : T(0);
   };
-
-  if (nsteps > 0) {
-    load();
-    if constexpr (NB == 2) {
-      store(0);
-      __syncthreads();
-    }
-  }
-  for (int step = 0; step < nsteps; ++step) {
-    const int cur = NB == 2 ? (step & 1) : 0;
-    if constexpr (NB == 1) {
-      store(0);
-      __syncthreads();
-    }
-    if (step + 1 < nsteps) load();
+  auto compute = [&](int cur) {
     auto& As = sm.A[cur];
     auto& Bs = sm.B[cur];
     if constexpr (MODE == kModeBF16x6) {
       const int kb = 8 * (lane >> 4);
-      bf16x8 ah[TM], am[TM], al[TM], bh[TN], bm[TN], bl[TN];
+      bf16x8 ah[TM], am_[TM], al[TM], bh[TN], bm[TN], bl[TN];
       for (int i = 0; i < TM; ++i) {
         float x[8];
         for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
-        split8x3(x, ah[i], am[i], al[i]);
+        split8x3(x, ah[i], am_[i], al[i]);
       }
       for (int j = 0; j < TN; ++j) {
         float x[8];
@@ -475,10 +478,10 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       }
       for (int i = 0; i < TM; ++i)
         for (int j = 0; j < TN; ++j) {   // smallest terms first
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am_[i], bm[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am_[i], bh[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
         }
@@ -512,11 +515,8 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
           for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
       }
     }
-    // NB = 2: the next tile goes to the other buffer, whose last readers
-    // passed the previous barrier; one barrier publishes it.
-    if constexpr (NB == 2)
-      if (step + 1 < nsteps) store(cur ^ 1);
-    __syncthreads();
+  };
+  auto flush = [&]() {
     if constexpr (kFlush) {
       if (++ktile == FLUSH) {
         ktile = 0;
@@ -526,6 +526,45 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
             acc[i][j] = Acc{};
           }
       }
+    }
+  };
+
+  // The last K tile is peeled off, so that the main loop has no branch
+  // besides its back edge: every step loads the next tile, computes the
+  // current one and stores the next one.
+  if (nsteps > 0) load();
+  if constexpr (NB == 2) {
+    if (nsteps > 0) {
+      store(0);
+      __syncthreads();
+    }
+    for (int step = 0; step + 1 < nsteps; ++step) {
+      const int cur = step & 1;
+      load();
+      compute(cur);
+      // the other buffer's last readers passed the previous barrier
+      store(cur ^ 1);
+      __syncthreads();
+      flush();
+    }
+    if (nsteps > 0) {
+      compute((nsteps - 1) & 1);
+      flush();
+    }
+  } else {
+    for (int step = 0; step + 1 < nsteps; ++step) {
+      store(0);
+      __syncthreads();
+      load();
+      compute(0);
+      __syncthreads();
+      flush();
+    }
+    if (nsteps > 0) {
+      store(0);
+      __syncthreads();
+      compute(0);
+      flush();
     }
   }
   if constexpr (kFlush)
@@ -552,7 +591,7 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   __syncthreads();   // LDS is reused by the caller's next tile
 }
 
-template <int MODE, bool A_KCONTIG, class OutT, class S = GemmSquare>
+template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S = GemmSquare>
 __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
                                              const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
                                              const GemmRun& run) {
@@ -565,7 +604,7 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
   const int logical = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
   if (logical >= run.ntiles) return;
   const GemmTile tl = tiles[run.tile0 + logical];
-  gemm_tile<MODE, A_KCONTIG, OutT, S, 2>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
+  gemm_tile<MODE, A_KCONTIG, GATHER, OutT, S, 2>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
 }
 
 // One kernel per contraction, so that profiles name the step:
@@ -573,18 +612,18 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   omega_kernel  Omega = H^T C (Eq. 15b)
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
-#define OCCK_GEMM_KERNEL(NAME, AK, OUT, SHAPE)                                                                 \
+#define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE)                                                                \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
                                               const GemmTile* __restrict__ tiles,                              \
                                               const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu, \
                                               GemmRun run) {                                                   \
-    gemm_grouped<MODE, AK, OUT, SHAPE>(descs, tiles, Cuser, ldcu, run);                                        \
+    gemm_grouped<MODE, AK, GA, OUT, SHAPE>(descs, tiles, Cuser, ldcu, run);                                       \
   }
-OCCK_GEMM_KERNEL(half_kernel, true, typename ModeT<MODE>::T, GemmRows48)
-OCCK_GEMM_KERNEL(omega_kernel, false, typename ModeT<MODE>::T, GemmSquare)
-OCCK_GEMM_KERNEL(l2p_kernel, true, double, GemmRows48)
-OCCK_GEMM_KERNEL(l2pt_kernel, true, double, GemmCols48)
+OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48)
+OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare)
+OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48)
+OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
