@@ -340,7 +340,11 @@ struct GemmSmem {
   typename ModeT<MODE>::T B[NB][ModeT<MODE>::KT][S::BN + 1];
 };
 
-template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S = GemmSquare, int NB = 1>
+// Read in place of operand elements outside their matrix: the GEMM operand
+// loads take no branch and their values need no masking afterwards.
+__device__ const double gemm_zero[2] = {0.0, 0.0};
+
+template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S = GemmSquare, int NB = 1, int DEPTH = 1>
 __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename ModeT<MODE>::T* __restrict__ Cuser,
                           int64_t ldcu, const GemmRun& run, GemmSmem<MODE, S, NB>& sm) {
   using T = typename ModeT<MODE>::T;
@@ -369,7 +373,11 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       for (int j = 0; j < TN; ++j)
         for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
   int ktile = 0;
-  T ra[EA], rb[EB];
+  // DEPTH = 2 (with NB = 2): two register sets, the loads run two K tiles
+  // ahead of the MFMAs
+  static_assert(DEPTH == 1 || (DEPTH == 2 && NB == 2), "two-deep loads need two LDS buffers");
+  constexpr int NR = DEPTH;
+  T ra[NR][EA], rb[NR][EB];
   // Each thread loads runs of consecutive elements: A k-contiguous: EA
   // consecutive k of row am; A m-contiguous: EA consecutive m at row ak; B:
   // EB consecutive n at row bk.
@@ -406,28 +414,30 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     const int gk = kfirst + bk;
     grow = nsteps > 0 ? gidx[gk < kend ? gk : kfirst] : 0;
   }
-  // Loads carry no branches: an element outside its operand reads the
-  // operand's first element (present whenever the tile has K work) and is
-  // replaced by zero when it is stored to LDS, so that the MFMAs of the
-  // current K tile do not wait for the loads in flight.
-  bool oka[EA], okb[EB];
-  auto load = [&]() {
+  // An element outside its operand is read from gemm_zero: no branch, and
+  // no select after the load that could make the MFMAs of the current K
+  // tile wait for the loads in flight.
+  const gbl<const T>* zero = as_global(reinterpret_cast<const T*>(gemm_zero));
+  int ld_step = 0;   // index of the next K tile to load; tiles past the last read as zero
+  auto load = [&](int set) {
+    const bool live = ld_step++ < nsteps;
     const int k0 = kfirst + kt_in_seg * KT;   // first k of this K tile
     const int64_t aoff = int64_t(seg_loaded) * sa_seg + int64_t(kt_in_seg) * KT * sak;
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       int64_t off;
+      bool ok;
       if (A_ROWS) {
-        oka[u] = k0 + ak < kend && m0 + am + u * ARS < M;
+        ok = live && k0 + ak < kend && m0 + am + u * ARS < M;
         off = aoff + int64_t(u) * ARS * sam;
       } else if (A_KCONTIG) {
-        oka[u] = a_row_ok && k0 + ak + u < kend;
+        ok = live && a_row_ok && k0 + ak + u < kend;
         off = aoff + int64_t(u) * sak;
       } else {
-        oka[u] = k0 + ak < kend && m0 + am + u < M;
+        ok = live && k0 + ak < kend && m0 + am + u < M;
         off = aoff + int64_t(u) * sam;
       }
-      ra[u] = *(oka[u] ? pa + off : A0);
+      ra[set][u] = *(ok ? pa + off : zero);
     }
     const bool bkok = k0 + bk < kend;
     const gbl<const T>* brow = GATHER ? cu + int64_t(grow) * ldcu + boff + (n0 + bn)
@@ -435,8 +445,8 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int gn = n0 + bn + u;
-      okb[u] = bkok && gn < N && (!GATHER || boff + gn < blim);
-      rb[u] = *(okb[u] ? brow + u : B0);
+      const bool ok = live && bkok && gn < N && (!GATHER || boff + gn < blim);
+      rb[set][u] = *(ok ? brow + u : zero);
     }
     if (++kt_in_seg == kpseg) {
       kt_in_seg = 0;
@@ -447,18 +457,18 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       grow = gidx[gk < kend ? gk : kfirst];
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int set, int buf) {
     auto& Aw = sm.A[buf];
     auto& Bw = sm.B[buf];
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
-      const T v = oka[u] ? ra[u] : T(0);
+      const T v = ra[set][u];
       if (A_ROWS) Aw[ak][am + u * ARS] = v;
       else if (A_KCONTIG) Aw[ak + u][am] = v;
       else Aw[ak][am + u] = v;
     }
 #pragma unroll
-    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = okb[u] ? rb[u] : T(0);
+    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = rb[set][u];
   };
   auto compute = [&](int cur) {
     auto& As = sm.A[cur];
@@ -529,39 +539,62 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
     }
   };
 
-  // The last K tile is peeled off, so that the main loop has no branch
-  // besides its back edge: every step loads the next tile, computes the
-  // current one and stores the next one.
-  if (nsteps > 0) load();
-  if constexpr (NB == 2) {
-    if (nsteps > 0) {
-      store(0);
+  // DEPTH = 2: tile s is computed from LDS buffer s & 1 while tile s + 1
+  // waits in one register set and tiles s + 2, s + 3 are loaded; the loop
+  // runs two K tiles per iteration so that register sets and buffers are
+  // fixed.  DEPTH = 1, NB = 2: loads one tile ahead, one barrier per tile.
+  // NB = 1: one buffer, loads one tile ahead, two barriers per tile.
+  // Stores and loads past the last tile move zeros and keep the loops free
+  // of branches.
+  if (nsteps > 0) {
+    if constexpr (DEPTH == 2) {
+      load(0);
+      store(0, 0);
       __syncthreads();
-    }
-    for (int step = 0; step + 1 < nsteps; ++step) {
-      const int cur = step & 1;
-      load();
-      compute(cur);
-      // the other buffer's last readers passed the previous barrier
-      store(cur ^ 1);
+      load(1);
+      load(0);
+      int step = 0;
+      for (; step + 2 <= nsteps; step += 2) {
+        compute(0);
+        store(1, 1);   // buffer 1's last readers passed the previous barrier
+        load(1);
+        __syncthreads();
+        flush();
+        compute(1);
+        store(0, 0);
+        load(0);
+        __syncthreads();
+        flush();
+      }
+      if (step < nsteps) {
+        compute(0);
+        flush();
+      }
+    } else if constexpr (NB == 2) {
+      load(0);
+      store(0, 0);
       __syncthreads();
-      flush();
-    }
-    if (nsteps > 0) {
+      for (int step = 0; step + 1 < nsteps; ++step) {
+        const int cur = step & 1;
+        load(0);
+        compute(cur);
+        store(0, cur ^ 1);   // the other buffer's last readers passed the previous barrier
+        __syncthreads();
+        flush();
+      }
       compute((nsteps - 1) & 1);
       flush();
-    }
-  } else {
-    for (int step = 0; step + 1 < nsteps; ++step) {
-      store(0);
-      __syncthreads();
-      load();
-      compute(0);
-      __syncthreads();
-      flush();
-    }
-    if (nsteps > 0) {
-      store(0);
+    } else {
+      load(0);
+      for (int step = 0; step + 1 < nsteps; ++step) {
+        store(0, 0);
+        __syncthreads();
+        load(0);
+        compute(0);
+        __syncthreads();
+        flush();
+      }
+      store(0, 0);
       __syncthreads();
       compute(0);
       flush();
@@ -591,11 +624,11 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   __syncthreads();   // LDS is reused by the caller's next tile
 }
 
-template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S = GemmSquare>
+template <int MODE, bool A_KCONTIG, bool GATHER, class OutT, class S, int NB, int DEPTH>
 __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs, const GemmTile* __restrict__ tiles,
                                              const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu,
                                              const GemmRun& run) {
-  __shared__ GemmSmem<MODE, S, 2> sm;
+  __shared__ GemmSmem<MODE, S, NB> sm;
   // XCD-aware order: the grid is a multiple of 8 and hardware block b runs on
   // XCD b % 8, so XCD x walks the contiguous tile range [x*per, (x+1)*per).
   // Tiles that share an operand panel are adjacent in the list and hence
@@ -604,7 +637,7 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
   const int logical = int(blockIdx.x % 8) * per + int(blockIdx.x / 8);
   if (logical >= run.ntiles) return;
   const GemmTile tl = tiles[run.tile0 + logical];
-  gemm_tile<MODE, A_KCONTIG, GATHER, OutT, S, 2>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
+  gemm_tile<MODE, A_KCONTIG, GATHER, OutT, S, NB, DEPTH>(descs[tl.prob], tl.mt, tl.nt, Cuser, ldcu, run, sm);
 }
 
 // One kernel per contraction, so that profiles name the step:
@@ -612,18 +645,22 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   omega_kernel  Omega = H^T C (Eq. 15b)
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
-#define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE)                                                                \
+#define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE, NB, DEPTH)                                                  \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
                                               const GemmTile* __restrict__ tiles,                              \
                                               const typename ModeT<MODE>::T* __restrict__ Cuser, int64_t ldcu, \
                                               GemmRun run) {                                                   \
-    gemm_grouped<MODE, AK, GA, OUT, SHAPE>(descs, tiles, Cuser, ldcu, run);                                       \
+    gemm_grouped<MODE, AK, GA, OUT, SHAPE, NB, DEPTH>(descs, tiles, Cuser, ldcu, run);                           \
   }
-OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48)
-OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare)
-OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48)
-OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48)
+// Loads two K tiles ahead only in l2p (a long K loop over the (q, j) rows of
+// Mloc); half and omega contract over the n_B functions of a leaf (a few K
+// tiles), and in l2pt the deeper loads cost more in L2 misses (the tiles of
+// one leaf drift apart) than they gain in latency.
+OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48, 2, 1)
+OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
+OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48, 2, 2)
+OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48, 2, 1)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
