@@ -23,6 +23,12 @@ template <class T>
 __device__ __forceinline__ gbl<T>* as_global(T* p) {
   return (gbl<T>*)p;
 }
+// Streaming store (non-temporal): for results that the next pass reads
+// long after the L2 has cycled through other data.
+template <class T>
+__device__ __forceinline__ void store_stream(gbl<T>* p, T v) {
+  __builtin_nontemporal_store(v, p);
+}
 // Read-only view for tables and operators that no kernel writes while the
 // reading kernel runs (CSR lists, descriptors, operators): wave-uniform
 // loads through it compile to scalar loads.
@@ -618,7 +624,8 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
         OutT v;
         if constexpr (kFlush) v = OutT(acc64[i][j][r]);
         else v = OutT(acc[i][j][r]);
-        *c = run.accumulate ? *c + v : v;
+        if (run.accumulate) *c = *c + v;
+        else store_stream(c, v);
       }
     }
   __syncthreads();   // LDS is reused by the caller's next tile
@@ -763,7 +770,7 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
       if (!ok[j]) continue;
       for (int r = 0; r < 4; ++r) {
         const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row < Q) Y[int64_t(row) * ncol + cols[j]] = T(acc[i][j][r]);
+        if (row < Q) store_stream(Y + int64_t(row) * ncol + cols[j], T(acc[i][j][r]));
       }
     }
 }
@@ -855,7 +862,7 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
   gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
   for (int c = 0; c < NC; ++c)
     if (ok[c])
-      for (int i = 0; i < Q; ++i) Y[int64_t(i) * ncol + col[c]] = acc[c][i];
+      for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col[c], acc[c][i]);
 }
 
 template <class T, int Q, int NC>
