@@ -384,20 +384,29 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   static_assert(DEPTH == 1 || (DEPTH == 2 && NB == 2), "two-deep loads need two LDS buffers");
   constexpr int NR = DEPTH;
   T ra[NR][EA], rb[NR][EB];
-  // Each thread loads runs of consecutive elements: A k-contiguous: EA
-  // consecutive k of row am; A m-contiguous: EA consecutive m at row ak; B:
-  // EB consecutive n at row bk.
-  // A k-contiguous with KT not a multiple of EA (tiles of 48 rows): thread
-  // takes column ak = tid % KT of rows am + u * (256 / KT) instead.
+  // Thread -> element maps of the operand tiles (element u of the thread):
+  //   A k-contiguous: EA consecutive k of row am;
+  //   A k-contiguous, KT not a multiple of EA (tiles of 48 rows, A_ROWS):
+  //     column ak = tid % KT of rows am + u * (256 / KT);
+  //   A m-contiguous, 64-wide tile (A_MW): element am = tid % 64 of k rows
+  //     ak + u * 4, so that a wave loads and stores whole 64-element rows
+  //     (coalesced loads, LDS stores without bank conflicts);
+  //   A m-contiguous otherwise: EA consecutive m at k row ak;
+  //   B, 64-wide tile (B_W): element bn = tid % 64 of k rows bk + u * 4;
+  //   B otherwise: EB consecutive n at k row bk.
   constexpr bool A_ROWS = A_KCONTIG && (KT % EA != 0);
+  constexpr bool A_MW = !A_KCONTIG && BM == 64;
+  constexpr bool B_W = BN == 64;
+  constexpr int ARW = 256 / 64;   // k rows per pass of the A_MW and B_W maps
   constexpr int TPRA = A_ROWS ? KT : (A_KCONTIG ? KT / EA : BM / EA), TPRB = BN / EB;
   constexpr int ARS = 256 / KT;   // row stride of the A_ROWS mapping
   static_assert(A_ROWS ? (256 % KT == 0 && BM == EA * ARS)
-                       : ((A_KCONTIG ? BM : KT) * TPRA == 256), "one pass over the A tile");
-  static_assert(KT * TPRB == 256, "one pass over the B tile");
-  const int am = A_ROWS ? tid / KT : (A_KCONTIG ? tid / TPRA : (tid % TPRA) * EA);
-  const int ak = A_ROWS ? tid % KT : (A_KCONTIG ? (tid % TPRA) * EA : tid / TPRA);
-  const int bk = tid / TPRB, bn = (tid % TPRB) * EB;
+                       : A_MW ? (EA * ARW == KT)
+                              : ((A_KCONTIG ? BM : KT) * TPRA == 256), "one pass over the A tile");
+  static_assert(B_W ? (EB * ARW == KT) : (KT * TPRB == 256), "one pass over the B tile");
+  const int am = A_ROWS ? tid / KT : A_MW ? tid % 64 : (A_KCONTIG ? tid / TPRA : (tid % TPRA) * EA);
+  const int ak = A_ROWS ? tid % KT : A_MW ? tid / 64 : (A_KCONTIG ? (tid % TPRA) * EA : tid / TPRA);
+  const int bk = B_W ? tid / 64 : tid / TPRB, bn = B_W ? tid % 64 : (tid % TPRB) * EB;
   // Per-thread operand pointers at k = koff of segment 0; a K tile advances
   // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
   const int kend = d.K;                       // k runs over [koff, K) in every segment
@@ -410,15 +419,24 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   const gbl<const T>* cu = as_global(Cuser);
   const gbl<const T>* B0 = GATHER ? cu : as_global(static_cast<const T*>(d.B));
   const gbl<const T>* pb = GATHER ? cu : B0 + int64_t(kfirst + bk) * ldb + (n0 + bn);
-  const gbl<const int32_t>* gidx = as_global(d.gidx);
   int kt_in_seg = 0;                          // K tile index within the current segment (next load)
   int seg_loaded = 0;
-  // Gathered B: the row of C for the next load's k, fetched one load ahead
-  // so that the operand loads never wait on the index load.
-  int grow = 0;
+  // Gathered B: the rows of C for the next load's k rows, fetched one load
+  // ahead so that the operand loads never wait on the index loads.  A
+  // wave's k rows are uniform (B_W map), so the indices are scalar loads.
+  static_assert(!GATHER || B_W, "gathered B uses the 64-wide row map");
+  constexpr int NG = B_W ? EB : 1;   // k rows of B per thread
+  int grow[NG];
+  const cst<int32_t>* gidx_c = as_const(d.gidx);
+  auto fetch_rows = [&](int kt) {
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+      const int gk = __builtin_amdgcn_readfirstlane(kfirst + kt * KT + bk + u * ARW);
+      grow[u] = gidx_c[gk < kend ? gk : kfirst];
+    }
+  };
   if constexpr (GATHER) {
-    const int gk = kfirst + bk;
-    grow = nsteps > 0 ? gidx[gk < kend ? gk : kfirst] : 0;
+    if (nsteps > 0) fetch_rows(0);
   }
   // An element outside its operand is read from gemm_zero: no branch, and
   // no select after the load that could make the MFMAs of the current K
@@ -439,29 +457,40 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       } else if (A_KCONTIG) {
         ok = live && a_row_ok && k0 + ak + u < kend;
         off = aoff + int64_t(u) * sak;
+      } else if (A_MW) {
+        ok = live && k0 + ak + u * ARW < kend && m0 + am < M;
+        off = aoff + int64_t(u) * ARW * sak;
       } else {
         ok = live && k0 + ak < kend && m0 + am + u < M;
         off = aoff + int64_t(u) * sam;
       }
       ra[set][u] = *(ok ? pa + off : zero);
     }
-    const bool bkok = k0 + bk < kend;
-    const gbl<const T>* brow = GATHER ? cu + int64_t(grow) * ldcu + boff + (n0 + bn)
-                                      : pb + int64_t(seg_loaded) * sb_seg + int64_t(kt_in_seg) * KT * ldb;
+    const gbl<const T>* bplain = pb + int64_t(seg_loaded) * sb_seg + int64_t(kt_in_seg) * KT * ldb;
+    // Gathered rows: offsets formed once per wave (readfirstlane is
+    // convergent, so the compiler cannot sink them under the per-lane
+    // bounds test and branch around the loads).
+    int64_t roff[NG];
+#pragma unroll
+    for (int u = 0; u < NG; ++u) {
+      const int64_t r = GATHER ? int64_t(grow[u]) * ldcu + boff : 0;
+      const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(r));
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(r) >> 32));
+      roff[u] = int64_t((uint64_t(hi) << 32) | lo);
+    }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
-      const int gn = n0 + bn + u;
-      const bool ok = live && bkok && gn < N && (!GATHER || boff + gn < blim);
-      rb[set][u] = *(ok ? brow + u : zero);
+      const int kk = B_W ? bk + u * ARW : bk, gn = n0 + (B_W ? bn : bn + u);
+      const bool ok = live & (k0 + kk < kend) & (gn < N) & (!GATHER | (boff + gn < blim));
+      const gbl<const T>* p = GATHER ? cu + roff[B_W ? u : 0] + gn
+                                     : bplain + (B_W ? int64_t(u) * ARW * ldb : int64_t(u));
+      rb[set][u] = *(ok ? p : zero);
     }
     if (++kt_in_seg == kpseg) {
       kt_in_seg = 0;
       ++seg_loaded;
     }
-    if constexpr (GATHER) {
-      const int gk = kfirst + kt_in_seg * KT + bk;
-      grow = gidx[gk < kend ? gk : kfirst];
-    }
+    if constexpr (GATHER) fetch_rows(kt_in_seg);
   };
   auto store = [&](int set, int buf) {
     auto& Aw = sm.A[buf];
@@ -471,10 +500,14 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       const T v = ra[set][u];
       if (A_ROWS) Aw[ak][am + u * ARS] = v;
       else if (A_KCONTIG) Aw[ak + u][am] = v;
+      else if (A_MW) Aw[ak + u * ARW][am] = v;
       else Aw[ak][am + u] = v;
     }
 #pragma unroll
-    for (int u = 0; u < EB; ++u) Bw[bk][bn + u] = rb[set][u];
+    for (int u = 0; u < EB; ++u) {
+      if (B_W) Bw[bk + u * ARW][bn] = rb[set][u];
+      else Bw[bk][bn + u] = rb[set][u];
+    }
   };
   auto compute = [&](int cur) {
     auto& As = sm.A[cur];
