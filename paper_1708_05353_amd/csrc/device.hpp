@@ -85,6 +85,11 @@ struct DeviceState {
   DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
   DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt;
   int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0;
+  // mirrored L2P in 64 x 144 tiles (a whole leaf per tile), built when they
+  // pad the leaves no more than the 64 x 48 tiles; the persistent batch
+  // kernel uses the 64 x 48 list
+  DevBuf<GemmTile> t_l2ptw;
+  int n_l2ptw = 0;
   // omega and l2p: one tile list per chunk c of 4 column tiles, holding the
   // tiles with nt >= 4c, stored one after another; list c is
   // [*_nt_start[c], *_nt_start[c + 1]) and list 0 holds every tile

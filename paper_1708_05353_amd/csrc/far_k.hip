@@ -253,7 +253,8 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   const char* Obase = prec == OCCK_PREC_FP64 ? reinterpret_cast<const char*>(ds->O.p)
                                              : reinterpret_cast<const char*>(ds->Of.p);
   std::vector<GemmDesc> dh, dom, dl, dht, dlt;
-  std::vector<GemmTile> th, tom, tl2, tht, tlt;
+  std::vector<GemmTile> th, tom, tl2, tht, tlt, tltw;
+  int64_t pad48 = 0, pad144 = 0;   // leaf columns of the mirrored L2P as padded by either tile
   for (int b = 0; b < nl; ++b) {
     const int nb = int(t->leaf_funcs[b].size());
     const int64_t hoff = ds->f_off[b] * Q * jb;   // H^B[t][q][j], ld Q*jb (elements)
@@ -328,6 +329,9 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.N = nb;
       d.K = ni;
       tiles_for<GemmCols48>(tlt, int(dlt.size()), d.M, d.N);
+      tiles_for<GemmCols144>(tltw, int(dlt.size()), d.M, d.N);
+      pad48 += (nb + 47) / 48 * 48;
+      pad144 += (nb + 143) / 144 * 144;
       dlt.push_back(d);
     }
   }
@@ -338,9 +342,11 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->omega_nt_start = chunked_tile_lists(tom, [](const GemmTile& x) { return std::make_tuple(x.prob, x.mt, x.nt); });
   ds->l2p_nt_start = chunked_tile_lists(tl2, [](const GemmTile& x) { return std::make_tuple(x.prob, x.nt, x.mt); });
   // l2pt: the j tiles sharing one HT panel adjacent
-  std::stable_sort(tlt.begin(), tlt.end(), [](const GemmTile& x, const GemmTile& y) {
+  auto by_leaf = [](const GemmTile& x, const GemmTile& y) {
     return std::make_tuple(x.prob, x.nt, x.mt) < std::make_tuple(y.prob, y.nt, y.mt);
-  });
+  };
+  std::stable_sort(tlt.begin(), tlt.end(), by_leaf);
+  std::stable_sort(tltw.begin(), tltw.end(), by_leaf);
   ds->d_half.upload(dh);
   ds->t_half.upload(th);
   ds->d_omega.upload(dom);
@@ -354,7 +360,8 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->t_ht.free();
   ds->d_l2pt.free();
   ds->t_l2pt.free();
-  ds->n_ht = ds->n_l2pt = 0;
+  ds->t_l2ptw.free();
+  ds->n_ht = ds->n_l2pt = ds->n_l2ptw = 0;
   if (sym) {
     ds->d_ht.upload(dht);
     ds->t_ht.upload(tht);
@@ -362,6 +369,12 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
     ds->t_l2pt.upload(tlt);
     ds->n_ht = int(tht.size());
     ds->n_l2pt = int(tlt.size());
+    // a whole leaf per tile reads each Mloc panel once; used when it pads
+    // the leaves' columns by at most a tenth more than the 64 x 48 tiles
+    if (10 * pad144 <= 11 * pad48) {
+      ds->t_l2ptw.upload(tltw);
+      ds->n_l2ptw = int(tltw.size());
+    }
   }
   ds->ws_jb = jb;
   ds->ws_ni = ni;
@@ -574,9 +587,15 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
         m.koff = jrel + jb;
         m.coff = jrel;
         m.mlim = jbk;
-        m.ntiles = ds->n_l2pt;
-        hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
-                           ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
+        if (MODE <= kModeF32 && ds->n_l2ptw > 0) {   // the split-BF16 modes would need 256+ VGPRs
+          m.ntiles = ds->n_l2ptw;
+          hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
+                             ds->d_l2pt.p, ds->t_l2ptw.p, Cg, ldcg, m);
+        } else {
+          m.ntiles = ds->n_l2pt;
+          hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
+                             ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
+        }
       }
     }
     HIP_OK(hipGetLastError());

@@ -327,6 +327,8 @@ template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; 
 //   GemmRows48 48 x 64  (1 x 4 waves of 3 x 1 tiles): a leaf's n_B rows
 //              (typically 80..144) padded to a multiple of 48, not 64
 //   GemmCols48 64 x 48  (4 x 1 waves of 1 x 3 tiles): the transpose case
+//   GemmCols144 64 x 144 (4 x 1 waves of 1 x 9 tiles): the transpose case
+//              with the n_B <= 144 columns of a leaf in one tile
 // --------------------------------------------------------------------------
 template <int WGM_, int WGN_, int TM_, int TN_>
 struct GemmShape {
@@ -337,6 +339,7 @@ struct GemmShape {
 using GemmSquare = GemmShape<2, 2, 2, 2>;
 using GemmRows48 = GemmShape<1, 4, 3, 1>;   // 48 x 64: the n_B rows of a leaf in tiles of 48
 using GemmCols48 = GemmShape<4, 1, 1, 3>;   // 64 x 48: the transpose case
+using GemmCols144 = GemmShape<4, 1, 1, 9>;  // 64 x 144: the transpose case, a whole leaf per tile
 
 // NB = 2: double-buffered operand tiles (one barrier per K tile); NB = 1:
 // single buffer (two barriers per K tile, half the LDS).
@@ -685,6 +688,7 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   omega_kernel  Omega = H^T C (Eq. 15b)
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
+//   l2pt_wide_kernel  the same with a whole leaf per tile
 #define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE, NB, DEPTH)                                                  \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
@@ -701,6 +705,7 @@ OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48, 2
 OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
 OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48, 2, 2)
 OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48, 2, 1)
+OCCK_GEMM_KERNEL(l2pt_wide_kernel, true, false, double, GemmCols144, 2, 1)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------

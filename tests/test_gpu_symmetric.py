@@ -96,3 +96,19 @@ def test_symmetric_K_ij_is_symmetric(torch_cuda, water75):
     tr.free()
     Kij = C.T @ got
     assert np.abs(Kij - Kij.T).max() <= 1e-10 * np.abs(Kij).max()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)], ids=["fp64", "fp32"])
+def test_symmetric_whole_leaf_mirrored_tiles(torch_cuda, prec, tol):
+    """Alkane chain whose leaves hold at most 144 functions (mean 131): the
+    mirrored L2P runs in 64 x 144 tiles, one per leaf, with ragged leaves."""
+    wl = workloads.alkane_chain(n_carbon=100, depth=6)
+    C = wl.orbitals()
+    ref = oracle_far_K(Setup(wl.system, wl.params), C)
+    from paper_1708_05353_amd import occk
+    tr = occk.Tree(wl.system, wl.params)
+    assert tr.info.max_nb <= 144
+    print(f"[sym] alkane C100 L2 prec {prec}", flush=True)
+    got = _run(torch_cuda, tr, torch_cuda.from_numpy(C).cuda(), C.shape[1], jblock=64, precision=prec)
+    tr.free()
+    assert rel(got, ref) <= tol
