@@ -408,7 +408,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
             continue
         for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("half_kernel", "half"),
                        ("omega_kernel", "omega"), ("l2pt_kernel", "l2p"), ("l2pt_wide_kernel", "l2p"),
-                       ("l2p_kernel", "l2p")):
+                       ("l2p_kernel", "l2p"), ("l2p_wide_kernel", "l2p")):
             if key in k:
                 cls_of[i] = c
                 break

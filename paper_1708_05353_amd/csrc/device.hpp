@@ -28,6 +28,25 @@ template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  // owns its allocation: freed on destruction, moved but never copied
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      free();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf() { free(); }
   void free() {
     if (p) (void)hipFree(p);
     p = nullptr;
@@ -86,10 +105,14 @@ struct DeviceState {
   DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt;
   int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0;
   // mirrored L2P in 64 x 144 tiles (a whole leaf per tile), built when they
-  // pad the leaves no more than the 64 x 48 tiles; the persistent batch
-  // kernel uses the 64 x 48 list
+  // pad the leaves by at most a tenth more than 48-wide tiles; the
+  // persistent batch kernel uses the 64 x 48 list
   DevBuf<GemmTile> t_l2ptw;
   int n_l2ptw = 0;
+  // direct L2P in 144 x 64 tiles under the same rule, in chunked lists like
+  // l2p_nt_start (empty when not built)
+  DevBuf<GemmTile> t_l2pw;
+  std::vector<int32_t> l2pw_nt_start;
   // omega and l2p: one tile list per chunk c of 4 column tiles, holding the
   // tiles with nt >= 4c, stored one after another; list c is
   // [*_nt_start[c], *_nt_start[c + 1]) and list 0 holds every tile

@@ -253,10 +253,12 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   const char* Obase = prec == OCCK_PREC_FP64 ? reinterpret_cast<const char*>(ds->O.p)
                                              : reinterpret_cast<const char*>(ds->Of.p);
   std::vector<GemmDesc> dh, dom, dl, dht, dlt;
-  std::vector<GemmTile> th, tom, tl2, tht, tlt, tltw;
-  int64_t pad48 = 0, pad144 = 0;   // leaf columns of the mirrored L2P as padded by either tile
+  std::vector<GemmTile> th, tom, tl2, tht, tlt, tltw, tl2w;
+  int64_t pad48 = 0, pad144 = 0;   // leaf functions as padded by 48- and 144-wide tiles
   for (int b = 0; b < nl; ++b) {
     const int nb = int(t->leaf_funcs[b].size());
+    pad48 += (nb + 47) / 48 * 48;
+    pad144 += (nb + 143) / 144 * 144;
     const int64_t hoff = ds->f_off[b] * Q * jb;   // H^B[t][q][j], ld Q*jb (elements)
     const int32_t* g = ds->funcs.p + ds->f_off[b];
     const char* mloc = ds->data.p + int64_t(ds->nbox + ds->leaf_box[b]) * box_stride * es;
@@ -310,6 +312,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.N = ni;
       d.K = Q * jb;
       tiles_for<GemmRows48>(tl2, int(dl.size()), d.M, d.N);
+      tiles_for<GemmRows144>(tl2w, int(dl.size()), d.M, d.N);
       dl.push_back(d);
     }
     if (sym) {  // KB[r, jstart + j] += sum_q sum_i Mloc[(q,j), i] HT_q[i][r]: rows j, columns r
@@ -330,8 +333,6 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
       d.K = ni;
       tiles_for<GemmCols48>(tlt, int(dlt.size()), d.M, d.N);
       tiles_for<GemmCols144>(tltw, int(dlt.size()), d.M, d.N);
-      pad48 += (nb + 47) / 48 * 48;
-      pad144 += (nb + 143) / 144 * 144;
       dlt.push_back(d);
     }
   }
@@ -341,6 +342,16 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   // Mloc), H of the box reused from L2 by all its column tiles
   ds->omega_nt_start = chunked_tile_lists(tom, [](const GemmTile& x) { return std::make_tuple(x.prob, x.mt, x.nt); });
   ds->l2p_nt_start = chunked_tile_lists(tl2, [](const GemmTile& x) { return std::make_tuple(x.prob, x.nt, x.mt); });
+  // whole-leaf tiles (a leaf's n_B rows in one tile, each Mloc panel read
+  // once) when they pad the leaves by at most a tenth more than 48-row tiles
+  // (the persistent batch kernel uses the 48-row lists)
+  const bool wide = 10 * pad144 <= 11 * pad48;
+  ds->l2pw_nt_start.clear();
+  ds->t_l2pw.free();
+  if (wide) {
+    ds->l2pw_nt_start = chunked_tile_lists(tl2w, [](const GemmTile& x) { return std::make_tuple(x.prob, x.nt, x.mt); });
+    ds->t_l2pw.upload(tl2w);
+  }
   // l2pt: the j tiles sharing one HT panel adjacent
   auto by_leaf = [](const GemmTile& x, const GemmTile& y) {
     return std::make_tuple(x.prob, x.nt, x.mt) < std::make_tuple(y.prob, y.nt, y.mt);
@@ -369,9 +380,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
     ds->t_l2pt.upload(tlt);
     ds->n_ht = int(tht.size());
     ds->n_l2pt = int(tlt.size());
-    // a whole leaf per tile reads each Mloc panel once; used when it pads
-    // the leaves' columns by at most a tenth more than the 64 x 48 tiles
-    if (10 * pad144 <= 11 * pad48) {
+    if (wide) {   // a whole leaf per tile: each Mloc panel is read once
       ds->t_l2ptw.upload(tltw);
       ds->n_l2ptw = int(tltw.size());
     }
@@ -473,10 +482,13 @@ static void free_state(DeviceState* ds) {
   ds->occ_ptr.free();
   ds->occ_row.free();
   ds->H.free();
+  ds->HT.free();
   ds->data.free();
   ds->KB.free();
-  ds->d_half.free(); ds->d_omega.free(); ds->d_l2p.free();
-  ds->t_half.free(); ds->t_omega.free(); ds->t_l2p.free();
+  ds->d_half.free(); ds->d_omega.free(); ds->d_l2p.free(); ds->d_ht.free(); ds->d_l2pt.free();
+  ds->t_half.free(); ds->t_omega.free(); ds->t_l2p.free(); ds->t_ht.free(); ds->t_l2pt.free();
+  ds->t_l2ptw.free();
+  ds->t_l2pw.free();
   delete ds;
 }
 
@@ -577,10 +589,17 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       GemmRun r{};
       r.accumulate = kb > 0 ? 1 : 0;
       r.nlo = int(istart);
-      r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
-      r.ntiles = ds->l2p_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-      hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                         ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
+      if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
+        r.tile0 = ds->l2pw_nt_start[size_t(ct0 / 4)];
+        r.ntiles = ds->l2pw_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
+        hipLaunchKernelGGL((l2p_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+                           ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
+      } else {
+        r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
+        r.ntiles = ds->l2p_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
+        hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+                           ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
+      }
       if (sym && jrel + jb < ni) {
         GemmRun m{};
         m.accumulate = 1;

@@ -329,6 +329,8 @@ template <> __device__ inline int acc_row<f4>(int g, int r) { return 4 * g + r; 
 //   GemmCols48 64 x 48  (4 x 1 waves of 1 x 3 tiles): the transpose case
 //   GemmCols144 64 x 144 (4 x 1 waves of 1 x 9 tiles): the transpose case
 //              with the n_B <= 144 columns of a leaf in one tile
+//   GemmRows144 144 x 64 (1 x 4 waves of 9 x 1 tiles): the n_B <= 144 rows
+//              of a leaf in one tile
 // --------------------------------------------------------------------------
 template <int WGM_, int WGN_, int TM_, int TN_>
 struct GemmShape {
@@ -340,6 +342,7 @@ using GemmSquare = GemmShape<2, 2, 2, 2>;
 using GemmRows48 = GemmShape<1, 4, 3, 1>;   // 48 x 64: the n_B rows of a leaf in tiles of 48
 using GemmCols48 = GemmShape<4, 1, 1, 3>;   // 64 x 48: the transpose case
 using GemmCols144 = GemmShape<4, 1, 1, 9>;  // 64 x 144: the transpose case, a whole leaf per tile
+using GemmRows144 = GemmShape<1, 4, 9, 1>;  // 144 x 64: a whole leaf per tile
 
 // NB = 2: double-buffered operand tiles (one barrier per K tile); NB = 1:
 // single buffer (two barriers per K tile, half the LDS).
@@ -688,7 +691,7 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   omega_kernel  Omega = H^T C (Eq. 15b)
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
-//   l2pt_wide_kernel  the same with a whole leaf per tile
+//   l2p_wide_kernel, l2pt_wide_kernel  the same with a whole leaf per tile
 #define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE, NB, DEPTH)                                                  \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
@@ -699,13 +702,15 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
   }
 // Loads two K tiles ahead only in l2p (a long K loop over the (q, j) rows of
 // Mloc); half and omega contract over the n_B functions of a leaf (a few K
-// tiles), and in l2pt the deeper loads cost more in L2 misses (the tiles of
-// one leaf drift apart) than they gain in latency.
+// tiles), in l2pt the deeper loads cost more in L2 misses (the tiles of one
+// leaf drift apart) than they gain in latency, and the whole-leaf tiles
+// would drop to 2 waves per SIMD.
 OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48, 2, 1)
 OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
 OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48, 2, 2)
 OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48, 2, 1)
 OCCK_GEMM_KERNEL(l2pt_wide_kernel, true, false, double, GemmCols144, 2, 1)
+OCCK_GEMM_KERNEL(l2p_wide_kernel, true, false, double, GemmRows144, 2, 1)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
