@@ -376,6 +376,66 @@ def _pmc_rows(d, counter):
     return rows
 
 
+def _classify_last_call(names, info):
+    """Kernel class of every dispatch of the last occk_far_K call in a
+    profile of 'bench.py --no-mixed' (dispatch id -> kernel name): each call
+    starts with the operator generation; the translations of a j batch are
+    n_up upward then n_down downward launches."""
+    n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
+    ids = sorted(i for i in names if "occk::" in names[i])
+    start = max(i for i in ids if "opgen" in names[i])      # the last call
+    cls_of, ntr = {}, 0
+    for i in ids:
+        if i < start:
+            continue
+        k = names[i]
+        if "translate" in k:
+            ntr += 1
+            cls_of[i] = "up" if (ntr - 1) % (n_up + n_down) < n_up else "down"
+            continue
+        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("half_kernel", "half"),
+                       ("omega_kernel", "omega"), ("l2pt_kernel", "l2p"), ("l2pt_wide_kernel", "l2p"),
+                       ("l2p_kernel", "l2p"), ("l2p_wide_kernel", "l2p")):
+            if key in k:
+                cls_of[i] = c
+                break
+        else:
+            raise SystemExit(f"unexpected kernel in the sequence: {k}")
+    return cls_of
+
+
+def trace_summary(trace_dir):
+    """Per-class launch times of the last occk_far_K call recorded by
+    'rocprofv3 --kernel-trace' of 'bench.py --no-mixed' (the same classes
+    and launch averages as the bench line's breakdown); prints markdown."""
+    import csv
+    import glob
+    import re
+    import workloads
+    from paper_1708_05353_amd import occk
+    names, dur = {}, {}
+    for f in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                i = int(r["Dispatch_Id"])
+                names[i] = re.sub(r"\(.*", "", r["Kernel_Name"])
+                dur[i] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    wl = workloads.alkane_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    cls_of = _classify_last_call(names, tr.info)
+    tot = {}
+    for i, c in cls_of.items():
+        n, t = tot.get(c, (0, 0.0))
+        tot[c] = (n + 1, t + dur[i])
+    print("Per kernel class, last call of the run (the bench line's classes; `python3 bench.py --trace-summary "
+          f"{trace_dir}`):\n")
+    print("| class | launches | ms | average launch, us |\n|---|---|---|---|")
+    for c in ["half", "omega", "up", "down", "l2p", "reduce"]:
+        if c in tot:
+            n, t = tot[c]
+            print(f"| {c} | {n} | {t * 1e3:.2f} | {t / n * 1e6:.1f} |")
+
+
 def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, cmds):
     """Per-class HBM traffic of the last occk_far_K call recorded by two
     rocprofv3 --pmc runs of 'bench.py --steps 1 --warmup 0' (FETCH_SIZE,
@@ -395,25 +455,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
     wl = workloads.alkane_chain()
     tr = occk.Tree(wl.system, wl.params)
     info = tr.info
-    n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
-    ids = sorted(i for i in F if "occk::" in F[i][0])
-    start = max(i for i in ids if "opgen" in F[i][0])      # the last call
-    seq = [i for i in ids if i >= start]
-    cls_of, ntr = {}, 0
-    for i in seq:          # translations: n_up upward then n_down downward launches per j batch
-        k = F[i][0]
-        if "translate" in k:
-            ntr += 1
-            cls_of[i] = "up" if (ntr - 1) % (n_up + n_down) < n_up else "down"
-            continue
-        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("half_kernel", "half"),
-                       ("omega_kernel", "omega"), ("l2pt_kernel", "l2p"), ("l2pt_wide_kernel", "l2p"),
-                       ("l2p_kernel", "l2p"), ("l2p_wide_kernel", "l2p")):
-            if key in k:
-                cls_of[i] = c
-                break
-        else:
-            raise SystemExit(f"unexpected kernel in the sequence: {k}")
+    cls_of = _classify_last_call({i: F[i][0] for i in F}, info)
     tot = {}
     for i, c in cls_of.items():
         n, fb, wb = tot.get(c, (0, 0.0, 0.0))
@@ -454,6 +496,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (CPU only)")
     ap.add_argument("--pmc-copy-mib", type=int, default=1024)
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="print per-class launch times of a rocprofv3 --kernel-trace run of this bench (--no-mixed)")
     ap.add_argument("--pmc-commands", nargs="*", default=[])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
@@ -475,6 +519,9 @@ def main():
         return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary, args.pmc_copy_mib, args.pmc_commands)
+        return
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
         return
     if args.workload == "batch16":
         bench_batch(args)
