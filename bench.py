@@ -39,7 +39,8 @@ def class_costs(info, n, jb, prec):
     F_L2P = 2 Q n^2 sum_B n_B, F_half = 2 Q n sum_B pi_B.  Bytes are the
     compulsory traffic of the schedule as executed: batch k (first j at
     k*jb) carries jb*(n - k*jb) columns; every box it touches is read once
-    and written once per batch, operands of the GEMMs are read once."""
+    and written once per batch (the upward walk reads the leaves and writes
+    the other boxes), operands of the GEMMs are read once."""
     Q = info.ncomp
     s = ELEM_BYTES[prec]
     nb = info.boxes_per_level
@@ -48,7 +49,10 @@ def class_costs(info, n, jb, prec):
     nks = [n - k * jb for k in range(nblk)]          # carried i per batch
     nc_exec = sum(jb * nk for nk in nks)
     nc = n * (n + 1) // 2
-    up_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, D))
+    if Q <= 9 and 1 <= D - lmin <= 6:   # the upward walk: leaves read once, every other box written once
+        up_boxes = nb[D] + sum(nb[l] for l in range(lmin, D))
+    else:                              # level by level: children read, parent written per level
+        up_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, D))
     down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
     z = info.m2m_nnz
     snb, snb2, nleaf = info.sum_nb, info.sum_nb2, info.nleaf
@@ -380,15 +384,21 @@ def _classify_last_call(names, info):
     """Kernel class of every dispatch of the last occk_far_K call in a
     profile of 'bench.py --no-mixed' (dispatch id -> kernel name): each call
     starts with the operator generation; the translations of a j batch are
-    n_up upward then n_down downward launches."""
+    n_up upward then n_down downward launches (or one upward walk, then the
+    downward launches)."""
     n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
     ids = sorted(i for i in names if "occk::" in names[i])
     start = max(i for i in ids if "opgen" in names[i])      # the last call
+    if any("up_walk" in names[i] for i in ids if i >= start):
+        n_up = 0        # the upward pass ran as one walk per batch
     cls_of, ntr = {}, 0
     for i in ids:
         if i < start:
             continue
         k = names[i]
+        if "up_walk" in k:
+            cls_of[i] = "up"
+            continue
         if "translate" in k:
             ntr += 1
             cls_of[i] = "up" if (ntr - 1) % (n_up + n_down) < n_up else "down"

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <functional>
 #include <stdexcept>
 #include <tuple>
 #include <string>
@@ -129,6 +130,40 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.src_box.upload(sb);
     ps.src_op.upload(so);
     ds->up.push_back(std::move(ps));
+  }
+  // the upward walk: post-order program of every subtree below a level-lmin
+  // box, children in the order of the upward passes' source lists
+  if (Q <= 9 && D - lmin >= 1 && D - lmin <= kUpWalkLevels) {
+    std::vector<std::vector<std::vector<std::pair<int32_t, int32_t>>>> kids(static_cast<size_t>(D));
+    for (int lev = lmin; lev < D; ++lev) {
+      kids[size_t(lev)].resize(t->boxes[lev].size());
+      for (int32_t c = 0; c < int32_t(t->boxes[lev + 1].size()); ++c) {
+        const auto& cc = t->boxes[lev + 1][c];
+        const int oct = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
+        kids[size_t(lev)][size_t(t->parent(lev + 1, c))].push_back({c, t->op_up[(lev + 1) * 8 + oct]});
+      }
+    }
+    std::vector<UpInstr> prog;
+    std::vector<int32_t> pptr{0};
+    std::function<void(int, int32_t)> emit = [&](int lev, int32_t p) {
+      for (const auto& kc : kids[size_t(lev)][size_t(p)]) {
+        if (lev + 1 == D) {
+          prog.push_back({UP_LEAF, lev - lmin, slot0[D] + kc.first, kc.second});
+        } else {
+          emit(lev + 1, kc.first);
+          prog.push_back({UP_CLOSE, lev + 1 - lmin, slot0[lev + 1] + kc.first, kc.second});
+        }
+      }
+    };
+    for (int32_t r = 0; r < int32_t(t->boxes[lmin].size()); ++r) {
+      emit(lmin, r);
+      prog.push_back({UP_CLOSE, 0, slot0[lmin] + r, -1});
+      pptr.push_back(int32_t(prog.size()));
+    }
+    ds->upw_prog.upload(prog);
+    ds->upw_ptr.upload(pptr);
+    ds->upw_nroots = int(t->boxes[lmin].size());
+    ds->upw_nlv = D - lmin;
   }
   // downward passes: Mloc targets at lev; sources = parent Mloc (L2L) + IL Omega (M2L)
   for (int lev = lmin; lev <= D; ++lev) {
@@ -434,6 +469,39 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
   HIP_OK(hipGetLastError());
 }
 
+// the upward walk over every subtree below level lmin (setup built the programs)
+template <class T>
+void launch_up_walk(const Tree* t, const DeviceState* ds, T* data, int64_t box_stride, const ColMap& cm,
+                    const T* ops, hipStream_t st) {
+  if (cm.nvalid <= 0 || ds->upw_nroots == 0) return;
+  const int Q = t->Q, KS = ksteps_of(Q);
+  const int64_t nblocks = ((cm.nvalid + 255) / 256) * ds->upw_nroots;
+  const int64_t grid = ((nblocks + 7) / 8) * 8;
+  if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
+#define OCCK_UW(QQ, NL)                                                                                       \
+  hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, cm, \
+                     KS, ds->upw_ptr.p, ds->upw_prog.p, ops, ds->upw_nroots, nblocks)
+#define OCCK_UWQ(QQ)                                    \
+  switch (ds->upw_nlv) {                                \
+    case 1: OCCK_UW(QQ, 1); break;                      \
+    case 2: OCCK_UW(QQ, 2); break;                      \
+    case 3: OCCK_UW(QQ, 3); break;                      \
+    case 4: OCCK_UW(QQ, 4); break;                      \
+    case 5: OCCK_UW(QQ, 5); break;                      \
+    case 6: OCCK_UW(QQ, 6); break;                      \
+    default: throw std::invalid_argument("upward walk: unsupported depth"); \
+  }
+  switch (Q) {
+    case 1: OCCK_UWQ(1); break;
+    case 4: OCCK_UWQ(4); break;
+    case 9: OCCK_UWQ(9); break;
+    default: throw std::invalid_argument("upward walk: unsupported Q");
+  }
+#undef OCCK_UWQ
+#undef OCCK_UW
+  HIP_OK(hipGetLastError());
+}
+
 template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, const ColMap&, const double*,
                                        hipStream_t, const int8_t*);
 template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, const ColMap&, const float*,
@@ -572,8 +640,11 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
                          ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
     {
-      ProfScope ps(ds, prof, OCCK_K_UP, st, int(ds->up.size()));
-      for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, cm, ops, st);
+      ProfScope ps(ds, prof, OCCK_K_UP, st, ds->upw_nroots > 0 ? 1 : int(ds->up.size()));
+      if (ds->upw_nroots > 0)
+        launch_up_walk<T>(t, ds, data, box_stride, cm, ops, st);
+      else
+        for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, cm, ops, st);
     }
     if (stop_after_up) return;
     if (sel) {

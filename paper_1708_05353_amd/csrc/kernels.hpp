@@ -922,6 +922,91 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
                                int(logical % ntgt), logical / ntgt);
 }
 
+// --------------------------------------------------------------------------
+// upward pass as a walk (M2M, Eq. 8): one block per (subtree below a level
+// l_min box, 256 carried columns), one column per thread.  The block runs
+// the subtree's post-order program: UP_LEAF adds T_op M(leaf) into the
+// accumulator of the leaf's parent level; UP_CLOSE stores a finished box's
+// M and adds T_op M(box) into its parent's accumulator (op < 0: the subtree
+// root).  Internal boxes are written once and never read back, and every
+// accumulator takes the same FMA sequence as the level-by-level passes.
+// Accumulators are indexed by level relative to l_min (NLV levels in
+// registers); the next leaf's column values are in flight while the
+// current program step runs.
+// --------------------------------------------------------------------------
+struct UpInstr {
+  int32_t kind;    // UP_LEAF or UP_CLOSE
+  int32_t level;   // accumulator (level - l_min) the step adds into (LEAF) or closes (CLOSE)
+  int32_t box;     // box slot read (LEAF) or written (CLOSE)
+  int32_t op;      // operator into the parent level (CLOSE of a subtree root: -1)
+};
+enum { UP_LEAF = 0, UP_CLOSE = 1 };
+constexpr int kUpWalkLevels = 6;   // deepest subtree (levels below l_min) the walk holds in registers
+
+template <class T, int Q, int NLV>
+__global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
+                                                      const int32_t* __restrict__ prog_ptr,
+                                                      const UpInstr* __restrict__ prog, const T* __restrict__ ops,
+                                                      int nroots, int64_t nblocks) {
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  const int root = int(logical % nroots);
+  const int64_t ct = logical / nroots;
+  const int64_t v = ct * 256 + threadIdx.x;
+  const bool ok = v < cm.nvalid;
+  const int64_t col = ok ? carried_col(cm, v) : 0;   // invalid columns read column 0, store nothing
+  const int64_t ncol = cm.ncol;
+  const int64_t opsz = int64_t(KS) * 64;
+  const gbl<const T>* base = as_global(static_cast<const T*>(data));
+  const cst<UpInstr>* pg = as_const(prog);
+  const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
+  T acc[NLV][Q];
+#pragma unroll
+  for (int l = 0; l < NLV; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
+  // y += T_op x, in the order of the level-by-level kernel
+  auto apply = [&](T (&y)[Q], const T (&x)[Q], int op) {
+    const cst<T>* A = as_const(ops) + int64_t(op) * opsz;
+    for (int i = 0; i < Q; ++i)
+      for (int k = 0; k < Q; ++k) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
+  };
+  auto next_leaf = [&](int s) {
+    while (s < p1 && pg[s].kind != UP_LEAF) ++s;
+    return s;
+  };
+  T xn[Q];
+  auto fetch = [&](int s) {   // column values of the leaf of step s (s < p1)
+    const gbl<const T>* X = base + int64_t(pg[s].box) * box_stride;
+    for (int k = 0; k < Q; ++k) xn[k] = X[int64_t(k) * ncol + col];
+  };
+  int nl = next_leaf(p0);
+  if (nl < p1) fetch(nl);
+  for (int s = p0; s < p1; ++s) {
+    const UpInstr in = load_const(prog + s);
+    if (in.kind == UP_LEAF) {
+      T x[Q];
+      for (int k = 0; k < Q; ++k) x[k] = xn[k];
+      nl = next_leaf(s + 1);
+      if (nl < p1) fetch(nl);
+#pragma unroll
+      for (int l = 0; l < NLV; ++l)
+        if (l == in.level) apply(acc[l], x, in.op);
+    } else {
+      gbl<T>* Y = as_global(data) + int64_t(in.box) * box_stride;
+#pragma unroll
+      for (int l = 0; l < NLV; ++l)
+        if (l == in.level) {
+          if (ok)
+            for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col, acc[l][i]);
+          if (l > 0 && in.op >= 0) apply(acc[l > 0 ? l - 1 : 0], acc[l], in.op);
+          for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
+        }
+    }
+  }
+}
+
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
 static __global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
                                 int64_t rows, int64_t cols) {
