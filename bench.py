@@ -30,6 +30,21 @@ PEAK_HBM = 8.0e12
 ELEM_BYTES = {"fp64": 8, "fp32": 4, "bf16x3": 4, "bf16x6": 4}
 
 
+# Register levels of the library's tree walks (kUpWalkLevels and
+# kDownWalkLevels in csrc/kernels.hpp): the walks start at these levels.
+UP_WALK_LEVELS, DOWN_WALK_LEVELS = 6, 2
+
+
+def walk_roots(info):
+    """Root levels of the upward and downward walks (None: level passes only)."""
+    if info.ncomp > 9:
+        return None, None
+    D, lmin = info.depth, info.lmin
+    lr_up = max(lmin, D - UP_WALK_LEVELS) if D - lmin >= 1 else None
+    lr_dn = max(lmin, D + 1 - DOWN_WALK_LEVELS)
+    return lr_up, lr_dn
+
+
 def class_costs(info, n, jb, prec):
     """Algorithmic flops and bytes per call of each kernel class, for the full
     call (i and j over all n occupied orbitals, symmetric schedule).
@@ -49,11 +64,18 @@ def class_costs(info, n, jb, prec):
     nks = [n - k * jb for k in range(nblk)]          # carried i per batch
     nc_exec = sum(jb * nk for nk in nks)
     nc = n * (n + 1) // 2
-    if Q <= 9 and 1 <= D - lmin <= 6:   # the upward walk: leaves read once, every other box written once
-        up_boxes = nb[D] + sum(nb[l] for l in range(lmin, D))
-    else:                              # level by level: children read, parent written per level
+    lr_up, lr_dn = walk_roots(info)
+    if lr_up is not None:   # level passes above the walk's roots; the walk reads leaves, writes the rest
+        up_boxes = (sum(nb[l] + nb[l + 1] for l in range(lmin, lr_up)) + nb[D]
+                    + sum(nb[l] for l in range(lr_up, D)))
+    else:                   # level by level: children read, parent written per level
         up_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, D))
-    down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
+    if lr_dn is not None:   # level passes above; the walk reads sources and its roots' parents, writes leaves
+        down_boxes = (sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, lr_dn))
+                      + sum(nb[l] for l in range(lr_dn, D + 1)) + (nb[lr_dn - 1] if lr_dn > lmin else 0)
+                      + nb[D])
+    else:
+        down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
     z = info.m2m_nnz
     snb, snb2, nleaf = info.sum_nb, info.sum_nb2, info.nleaf
     half_b = (nblk * (snb2 * Q + snb * jb * (1 + Q)) + snb2 * Q + snb * n * (1 + Q)) * s
@@ -389,15 +411,20 @@ def _classify_last_call(names, info):
     n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
     ids = sorted(i for i in names if "occk::" in names[i])
     start = max(i for i in ids if "opgen" in names[i])      # the last call
-    if any("up_walk" in names[i] for i in ids if i >= start):
-        n_up = 0        # the upward pass ran as one walk per batch
+    lr_up, lr_dn = walk_roots(info)
+    walks = [i for i in ids if i >= start and "_walk" in names[i]]
+    if walks:           # level passes only above the walks' root levels
+        n_up, n_down = lr_up - info.lmin, lr_dn - info.lmin
+        ntr_all = sum(1 for i in ids if i >= start and "translate" in names[i])
+        if ntr_all != (len(walks) // 2) * (n_up + n_down):
+            raise SystemExit("translation launches do not match the walk root levels")
     cls_of, ntr = {}, 0
     for i in ids:
         if i < start:
             continue
         k = names[i]
-        if "up_walk" in k:
-            cls_of[i] = "up"
+        if "up_walk" in k or "down_walk" in k:
+            cls_of[i] = "up" if "up_walk" in k else "down"
             continue
         if "translate" in k:
             ntr += 1

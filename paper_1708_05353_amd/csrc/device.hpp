@@ -104,12 +104,22 @@ struct DeviceState {
   DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
   DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt;
   int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0;
-  // upward pass as one walk per subtree below each level-l_min box (Q <= 9,
-  // 1..6 levels of accumulators): programs [upw_ptr[r], upw_ptr[r + 1])
+  // upward pass as one walk per subtree below each box of level upw_lroot
+  // (Q <= 9; the levels above run level by level): programs
+  // [upw_ptr[r], upw_ptr[r + 1])
   DevBuf<int32_t> upw_ptr;
   DevBuf<UpInstr> upw_prog;
   int upw_nroots = 0;   // 0: the level-by-level passes run instead
-  int upw_nlv = 0;      // accumulator levels, D - l_min
+  int upw_nlv = 0;      // accumulator levels, D - upw_lroot
+  int upw_lroot = 0;
+  // downward pass as one walk per subtree below each box of level
+  // dnw_lroot (Q <= 9; the levels above run level by level; not in the
+  // learned-rank mode, whose ranks are per level-pass entry)
+  DevBuf<int32_t> dnw_ptr;
+  DevBuf<UpInstr> dnw_prog;
+  int dnw_nroots = 0;   // 0: the level-by-level passes run instead
+  int dnw_nlv = 0;      // accumulator levels, D - dnw_lroot + 1
+  int dnw_lroot = 0;
   // mirrored L2P in 64 x 144 tiles (a whole leaf per tile), built when they
   // pad the leaves by at most a tenth more than 48-wide tiles; the
   // persistent batch kernel uses the 64 x 48 list

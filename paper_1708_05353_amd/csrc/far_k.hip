@@ -131,41 +131,47 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.src_op.upload(so);
     ds->up.push_back(std::move(ps));
   }
-  // the upward walk: post-order program of every subtree below a level-lmin
-  // box, children in the order of the upward passes' source lists
-  if (Q <= 9 && D - lmin >= 1 && D - lmin <= kUpWalkLevels) {
-    std::vector<std::vector<std::vector<std::pair<int32_t, int32_t>>>> kids(static_cast<size_t>(D));
-    for (int lev = lmin; lev < D; ++lev) {
-      kids[size_t(lev)].resize(t->boxes[lev].size());
-      for (int32_t c = 0; c < int32_t(t->boxes[lev + 1].size()); ++c) {
-        const auto& cc = t->boxes[lev + 1][c];
-        const int oct = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
-        kids[size_t(lev)][size_t(t->parent(lev + 1, c))].push_back({c, t->op_up[(lev + 1) * 8 + oct]});
-      }
+  // children of every box above the leaves, in the order of the upward
+  // passes' source lists, with their M2M operators
+  std::vector<std::vector<std::vector<std::pair<int32_t, int32_t>>>> kids(static_cast<size_t>(D + 1));
+  for (int lev = lmin; lev < D; ++lev) {
+    kids[size_t(lev)].resize(t->boxes[lev].size());
+    for (int32_t c = 0; c < int32_t(t->boxes[lev + 1].size()); ++c) {
+      const auto& cc = t->boxes[lev + 1][c];
+      const int oct = (cc[0] & 1) | ((cc[1] & 1) << 1) | ((cc[2] & 1) << 2);
+      kids[size_t(lev)][size_t(t->parent(lev + 1, c))].push_back({c, t->op_up[(lev + 1) * 8 + oct]});
     }
+  }
+  // the upward walk: post-order program of every subtree below a box of
+  // level lr = max(lmin, D - kUpWalkLevels); the levels above lr keep their
+  // level-by-level passes, which read the walk's level-lr multipoles
+  if (Q <= 9 && D - lmin >= 1) {
+    const int lr = std::max(lmin, D - kUpWalkLevels);
     std::vector<UpInstr> prog;
     std::vector<int32_t> pptr{0};
     std::function<void(int, int32_t)> emit = [&](int lev, int32_t p) {
       for (const auto& kc : kids[size_t(lev)][size_t(p)]) {
         if (lev + 1 == D) {
-          prog.push_back({UP_LEAF, lev - lmin, slot0[D] + kc.first, kc.second});
+          prog.push_back({UP_LEAF, lev - lr, slot0[D] + kc.first, kc.second});
         } else {
           emit(lev + 1, kc.first);
-          prog.push_back({UP_CLOSE, lev + 1 - lmin, slot0[lev + 1] + kc.first, kc.second});
+          prog.push_back({UP_CLOSE, lev + 1 - lr, slot0[lev + 1] + kc.first, kc.second});
         }
       }
     };
-    for (int32_t r = 0; r < int32_t(t->boxes[lmin].size()); ++r) {
-      emit(lmin, r);
-      prog.push_back({UP_CLOSE, 0, slot0[lmin] + r, -1});
+    for (int32_t r = 0; r < int32_t(t->boxes[lr].size()); ++r) {
+      emit(lr, r);
+      prog.push_back({UP_CLOSE, 0, slot0[lr] + r, -1});
       pptr.push_back(int32_t(prog.size()));
     }
     ds->upw_prog.upload(prog);
     ds->upw_ptr.upload(pptr);
-    ds->upw_nroots = int(t->boxes[lmin].size());
-    ds->upw_nlv = D - lmin;
+    ds->upw_nroots = int(t->boxes[lr].size());
+    ds->upw_nlv = D - lr;
+    ds->upw_lroot = lr;
   }
   // downward passes: Mloc targets at lev; sources = parent Mloc (L2L) + IL Omega (M2L)
+  std::vector<std::vector<int32_t>> dn_ptr, dn_box;   // host CSR of each downward level
   for (int lev = lmin; lev <= D; ++lev) {
     const auto& bx = t->boxes[lev];
     Pass ps;
@@ -189,6 +195,8 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.ntgt = int(bx.size());
     ps.nent = int(sb.size());
     ps.host_op = so;
+    dn_ptr.push_back(sp);
+    dn_box.push_back(sb);
     for (int32_t b = 0; b < ps.ntgt; ++b)
       for (int32_t e = sp[b]; e < sp[b + 1]; ++e) ps.host_tgt.push_back(b);
     ps.ent_tgt.upload(ps.host_tgt);
@@ -197,6 +205,43 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.src_box.upload(sb);
     ps.src_op.upload(so);
     ds->down.push_back(std::move(ps));
+  }
+  // the downward walk: pre-order program of every subtree below a box of
+  // level lr = max(lmin, D + 1 - kDownWalkLevels); each box's terms in the
+  // order of its downward-pass source list.  A walk root reads its parent's
+  // local expansion (written by the level-by-level pass of level lr - 1)
+  // like any source; below it the parent term comes from the registers.
+  if (Q <= 9) {
+    const int lr = std::max(lmin, D + 1 - kDownWalkLevels);
+    std::vector<UpInstr> prog;
+    std::vector<int32_t> pptr{0};
+    std::function<void(int, int32_t)> visit = [&](int lev, int32_t b) {
+      const int lp = lev - lmin, li = lev - lr;   // pass index, accumulator level
+      const Pass& ps = ds->down[size_t(lp)];
+      int32_t e = dn_ptr[size_t(lp)][size_t(b)];
+      const int32_t e1 = dn_ptr[size_t(lp)][size_t(b) + 1];
+      if (lev > lr) {   // the parent term (L2L) comes first, from the parent level's accumulator
+        prog.push_back({DN_BEGIN, li, 0, ps.host_op[size_t(e)]});
+        ++e;
+      } else {
+        prog.push_back({DN_BEGIN, li, 0, -1});
+      }
+      for (; e < e1; ++e) prog.push_back({DN_SRC, li, dn_box[size_t(lp)][size_t(e)], ps.host_op[size_t(e)]});
+      if (lev == D) {
+        prog.push_back({DN_STORE, li, int32_t(nbox) + slot0[D] + b, -1});
+      } else {
+        for (const auto& kc : kids[size_t(lev)][size_t(b)]) visit(lev + 1, kc.first);
+      }
+    };
+    for (int32_t r = 0; r < int32_t(t->boxes[lr].size()); ++r) {
+      visit(lr, r);
+      pptr.push_back(int32_t(prog.size()));
+    }
+    ds->dnw_prog.upload(prog);
+    ds->dnw_ptr.upload(pptr);
+    ds->dnw_nroots = int(t->boxes[lr].size());
+    ds->dnw_nlv = D - lr + 1;
+    ds->dnw_lroot = lr;
   }
   // reduction lists: function r -> rows of KB (leaf order, then local order)
   std::vector<std::vector<int32_t>> occ(t->nbasis);
@@ -469,36 +514,41 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
   HIP_OK(hipGetLastError());
 }
 
-// the upward walk over every subtree below level lmin (setup built the programs)
+// the upward (up) or downward walk over every subtree below level lmin
+// (setup built the programs)
 template <class T>
-void launch_up_walk(const Tree* t, const DeviceState* ds, T* data, int64_t box_stride, const ColMap& cm,
-                    const T* ops, hipStream_t st) {
-  if (cm.nvalid <= 0 || ds->upw_nroots == 0) return;
+void launch_walk(const Tree* t, const int32_t* pptr, const UpInstr* prog, int nroots, int nlv, bool up, T* data,
+                 int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st) {
+  if (cm.nvalid <= 0 || nroots == 0) return;
   const int Q = t->Q, KS = ksteps_of(Q);
-  const int64_t nblocks = ((cm.nvalid + 255) / 256) * ds->upw_nroots;
+  const int64_t nblocks = ((cm.nvalid + 255) / 256) * nroots;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_UW(QQ, NL)                                                                                       \
-  hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, cm, \
-                     KS, ds->upw_ptr.p, ds->upw_prog.p, ops, ds->upw_nroots, nblocks)
-#define OCCK_UWQ(QQ)                                    \
-  switch (ds->upw_nlv) {                                \
-    case 1: OCCK_UW(QQ, 1); break;                      \
-    case 2: OCCK_UW(QQ, 2); break;                      \
-    case 3: OCCK_UW(QQ, 3); break;                      \
-    case 4: OCCK_UW(QQ, 4); break;                      \
-    case 5: OCCK_UW(QQ, 5); break;                      \
-    case 6: OCCK_UW(QQ, 6); break;                      \
-    default: throw std::invalid_argument("upward walk: unsupported depth"); \
+#define OCCK_W(QQ, NL)                                                                                          \
+  if (up)                                                                                                        \
+    hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,    \
+                       cm, KS, pptr, prog, ops, nroots, nblocks);                                                \
+  else                                                                                                           \
+    hipLaunchKernelGGL((down_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,  \
+                       cm, KS, pptr, prog, ops, nroots, nblocks)
+#define OCCK_WQ(QQ)                                                        \
+  switch (nlv) {                                                           \
+    case 1: OCCK_W(QQ, 1); break;                                          \
+    case 2: OCCK_W(QQ, 2); break;                                          \
+    case 3: OCCK_W(QQ, 3); break;                                          \
+    case 4: OCCK_W(QQ, 4); break;                                          \
+    case 5: OCCK_W(QQ, 5); break;                                          \
+    case 6: OCCK_W(QQ, 6); break;                                          \
+    default: throw std::invalid_argument("tree walk: unsupported depth"); \
   }
   switch (Q) {
-    case 1: OCCK_UWQ(1); break;
-    case 4: OCCK_UWQ(4); break;
-    case 9: OCCK_UWQ(9); break;
-    default: throw std::invalid_argument("upward walk: unsupported Q");
+    case 1: OCCK_WQ(1); break;
+    case 4: OCCK_WQ(4); break;
+    case 9: OCCK_WQ(9); break;
+    default: throw std::invalid_argument("tree walk: unsupported Q");
   }
-#undef OCCK_UWQ
-#undef OCCK_UW
+#undef OCCK_WQ
+#undef OCCK_W
   HIP_OK(hipGetLastError());
 }
 
@@ -640,11 +690,16 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
                          ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
     }
     {
-      ProfScope ps(ds, prof, OCCK_K_UP, st, ds->upw_nroots > 0 ? 1 : int(ds->up.size()));
-      if (ds->upw_nroots > 0)
-        launch_up_walk<T>(t, ds, data, box_stride, cm, ops, st);
-      else
-        for (const Pass& p : ds->up) launch_translate<T>(t, p, data, box_stride, cm, ops, st);
+      ProfScope ps(ds, prof, OCCK_K_UP, st,
+                   ds->upw_nroots > 0 ? 1 + ds->upw_lroot - t->lmin : int(ds->up.size()));
+      // ds->up holds levels D-1 down to lmin; the walk covers those at or below its root level
+      size_t k0 = 0;
+      if (ds->upw_nroots > 0) {
+        launch_walk<T>(t, ds->upw_ptr.p, ds->upw_prog.p, ds->upw_nroots, ds->upw_nlv, true, data, box_stride, cm,
+                       ops, st);
+        k0 = size_t(t->params.depth - ds->upw_lroot);
+      }
+      for (size_t k = k0; k < ds->up.size(); ++k) launch_translate<T>(t, ds->up[k], data, box_stride, cm, ops, st);
     }
     if (stop_after_up) return;
     if (sel) {
@@ -652,8 +707,15 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       learned_ranks<T>(t, ds, sel, data, box_stride, cm, st);
     }
     {
-      ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(ds->down.size()));
-      for (const Pass& p : ds->down) launch_translate<T>(t, p, data, box_stride, cm, ops, st, sel ? p.rank.p : nullptr);
+      // ds->down holds levels lmin..D; the walk covers those at or below its root level
+      const bool walk = !sel && ds->dnw_nroots > 0;
+      const size_t k1 = walk ? size_t(ds->dnw_lroot - t->lmin) : ds->down.size();
+      ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(k1) + (walk ? 1 : 0));
+      for (size_t k = 0; k < k1; ++k)
+        launch_translate<T>(t, ds->down[k], data, box_stride, cm, ops, st, sel ? ds->down[k].rank.p : nullptr);
+      if (walk)
+        launch_walk<T>(t, ds->dnw_ptr.p, ds->dnw_prog.p, ds->dnw_nroots, ds->dnw_nlv, false, data, box_stride, cm,
+                       ops, st);
     }
     {
       ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < ni ? 2 : 1);

@@ -941,7 +941,7 @@ struct UpInstr {
   int32_t op;      // operator into the parent level (CLOSE of a subtree root: -1)
 };
 enum { UP_LEAF = 0, UP_CLOSE = 1 };
-constexpr int kUpWalkLevels = 6;   // deepest subtree (levels below l_min) the walk holds in registers
+constexpr int kUpWalkLevels = 6;   // accumulator levels (below the walk's root level) held in registers
 
 template <class T, int Q, int NLV>
 __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
@@ -1003,6 +1003,86 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
           if (l > 0 && in.op >= 0) apply(acc[l > 0 ? l - 1 : 0], acc[l], in.op);
           for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
         }
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// downward pass as a walk (L2L and M2L, Eq. 8): one block per (subtree
+// below a level l_min box, 256 carried columns), one column per thread, in
+// pre-order.  DN_BEGIN opens a box at a level: its accumulator starts at
+// zero and takes T_op L(parent) from the parent level's accumulator (op < 0:
+// a subtree root, which has no parent term); DN_SRC adds T_op M(box) of an
+// interaction-list source; DN_STORE writes a leaf's local expansion.  The
+// local expansions above the leaves stay in registers and are never
+// written; every accumulator takes the terms in the order of the
+// level-by-level passes (parent first, then the interaction list).
+// --------------------------------------------------------------------------
+enum { DN_BEGIN = 0, DN_SRC = 1, DN_STORE = 2 };
+constexpr int kDownWalkLevels = 2;   // accumulator levels (root level..D) held in registers
+
+template <class T, int Q, int NLV>
+__global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
+                                                        const int32_t* __restrict__ prog_ptr,
+                                                        const UpInstr* __restrict__ prog, const T* __restrict__ ops,
+                                                        int nroots, int64_t nblocks) {
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;
+  const int root = int(logical % nroots);
+  const int64_t ct = logical / nroots;
+  const int64_t v = ct * 256 + threadIdx.x;
+  const bool ok = v < cm.nvalid;
+  const int64_t col = ok ? carried_col(cm, v) : 0;   // invalid columns read column 0, store nothing
+  const int64_t ncol = cm.ncol;
+  const int64_t opsz = int64_t(KS) * 64;
+  const gbl<const T>* base = as_global(static_cast<const T*>(data));
+  const cst<UpInstr>* pg = as_const(prog);
+  const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
+  T acc[NLV][Q];
+#pragma unroll
+  for (int l = 0; l < NLV; ++l)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
+  auto apply = [&](T (&y)[Q], const T (&x)[Q], int op) {   // y += T_op x, as the level-by-level kernel
+    const cst<T>* A = as_const(ops) + int64_t(op) * opsz;
+    for (int i = 0; i < Q; ++i)
+      for (int k = 0; k < Q; ++k) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
+  };
+  auto next_src = [&](int s) {
+    while (s < p1 && pg[s].kind != DN_SRC) ++s;
+    return s;
+  };
+  T xn[Q];
+  auto fetch = [&](int s) {   // column values of the source of step s (s < p1)
+    const gbl<const T>* X = base + int64_t(pg[s].box) * box_stride;
+    for (int k = 0; k < Q; ++k) xn[k] = X[int64_t(k) * ncol + col];
+  };
+  int ns = next_src(p0);
+  if (ns < p1) fetch(ns);
+  for (int s = p0; s < p1; ++s) {
+    const UpInstr in = load_const(prog + s);
+    if (in.kind == DN_SRC) {
+      T x[Q];
+      for (int k = 0; k < Q; ++k) x[k] = xn[k];
+      ns = next_src(s + 1);
+      if (ns < p1) fetch(ns);
+#pragma unroll
+      for (int l = 0; l < NLV; ++l)
+        if (l == in.level) apply(acc[l], x, in.op);
+    } else if (in.kind == DN_BEGIN) {
+#pragma unroll
+      for (int l = 0; l < NLV; ++l)
+        if (l == in.level) {
+          for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
+          if (l > 0 && in.op >= 0) apply(acc[l], acc[l > 0 ? l - 1 : 0], in.op);
+        }
+    } else {
+      gbl<T>* Y = as_global(data) + int64_t(in.box) * box_stride;
+#pragma unroll
+      for (int l = 0; l < NLV; ++l)
+        if (l == in.level && ok)
+          for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col, acc[l][i]);
     }
   }
 }
