@@ -1,0 +1,64 @@
+"""Host logic of bench.py that turns profiles into per-class figures: the
+kernel classes of one call's dispatch sequence (tree walks and level
+passes), and the algorithmic bytes of the walks against the level-by-level
+passes."""
+from types import SimpleNamespace
+
+import pytest
+
+import bench
+
+
+def _info(depth, lmin, ncomp=9, nb=None):
+    nb = nb or [2 ** l for l in range(depth + 1)]
+    return SimpleNamespace(depth=depth, lmin=lmin, ncomp=ncomp, boxes_per_level=nb, m2m_nnz=36,
+                           sum_nb=1000, sum_nb2=100000, nleaf=nb[depth], npairs=5000, n_edges=sum(nb[lmin + 1:]),
+                           n_il=10 * sum(nb[lmin:]), nbasis=800)
+
+
+def _call(depth, lmin, nbatch):
+    lr_up, lr_dn = bench.walk_roots(_info(depth, lmin))
+    seq = ["occk::opgen_kernel"]
+    for _ in range(nbatch):
+        seq += ["occk::half_kernel<0>", "occk::omega_kernel<0>", "occk::up_walk_kernel<double, 9, 6>"]
+        seq += ["occk::translate_vec_kernel<double, 9, 1>"] * (lr_up - lmin)
+        seq += ["occk::translate_vec_kernel<double, 9, 1>"] * (lr_dn - lmin)
+        seq += ["occk::down_walk_kernel<double, 9, 2>", "occk::l2p_wide_kernel<0>", "occk::l2pt_wide_kernel<0>"]
+    seq += ["occk::reduce_kernel"]
+    return {i + 1: k for i, k in enumerate(seq)}
+
+
+@pytest.mark.parametrize("depth,lmin", [(8, 2), (4, 2), (3, 2)])
+def test_classes_of_walks_and_level_passes(depth, lmin):
+    info = _info(depth, lmin)
+    lr_up, lr_dn = bench.walk_roots(info)
+    names = {0: "occk::opgen_kernel", **_call(depth, lmin, 3)}   # an earlier call's dispatch is ignored
+    cls = bench._classify_last_call(names, info)
+    got = [cls[i] for i in sorted(cls)]
+    per_batch = (["half", "omega", "up"] + ["up"] * (lr_up - lmin) + ["down"] * (lr_dn - lmin)
+                 + ["down", "l2p", "l2p"])
+    assert got == ["opgen"] + per_batch * 3 + ["reduce"]
+
+
+def test_walk_launch_count_mismatch_is_an_error():
+    info = _info(8, 2)
+    names = _call(8, 2, 2)
+    first_translate = min(i for i, k in names.items() if "translate" in k)
+    del names[first_translate]
+    with pytest.raises(SystemExit):
+        bench._classify_last_call(names, info)
+
+
+def test_walk_roots_and_bytes():
+    info = _info(8, 2)
+    assert bench.walk_roots(info) == (2, 7)
+    assert bench.walk_roots(_info(8, 2, ncomp=16)) == (None, None)
+    walk = bench.class_costs(info, 100, 32, "fp64")
+    nb = info.boxes_per_level
+    # upward: leaves read once, every other box written once
+    cols = sum(32 * (100 - k * 32) for k in range(4))
+    assert walk["up"][1] == (nb[8] + sum(nb[2:8])) * 9 * cols * 8
+    # downward: levels 2..6 level by level, then the walk reads sources and
+    # its roots' parents and writes the leaves
+    lv = sum(2 * nb[l] + (nb[l - 1] if l > 2 else 0) for l in range(2, 7))
+    assert walk["down"][1] == (lv + nb[7] + nb[8] + nb[6] + nb[8]) * 9 * cols * 8
