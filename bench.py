@@ -36,10 +36,15 @@ UP_WALK_LEVELS, DOWN_WALK_LEVELS = 6, 2
 
 
 def walk_roots(info):
-    """Root levels of the upward and downward walks (None: level passes only)."""
-    if info.ncomp > 9:
-        return None, None
+    """Root levels of the upward and downward walks (None: level passes only).
+    As in the library: walks for Q <= 9 on trees whose boxes above the
+    leaves have at most 2 children on average and whose interaction lists
+    hold at most 8 sources on average."""
     D, lmin = info.depth, info.lmin
+    nb = info.boxes_per_level
+    above, kids, tgt = sum(nb[lmin:D]), sum(nb[lmin + 1:D + 1]), sum(nb[lmin:D + 1])
+    if info.ncomp > 9 or kids > 2 * above or info.n_il > 8 * tgt:
+        return None, None
     lr_up = max(lmin, D - UP_WALK_LEVELS) if D - lmin >= 1 else None
     lr_dn = max(lmin, D + 1 - DOWN_WALK_LEVELS)
     return lr_up, lr_dn

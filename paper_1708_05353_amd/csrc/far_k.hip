@@ -142,10 +142,26 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
       kids[size_t(lev)][size_t(t->parent(lev + 1, c))].push_back({c, t->op_up[(lev + 1) * 8 + oct]});
     }
   }
+  // The walks pay off where a block's subtree is a long chain of cheap steps
+  // (binary splits, short interaction lists: the chain-like trees); on 2-D
+  // and 3-D trees, with up to 8 children and tens of interaction-list
+  // sources per box, the level-by-level passes keep more waves busy and are
+  // faster.  Both walks are used when the boxes above the leaves have at
+  // most 2 children on average and the interaction lists at most 8 sources.
+  int64_t n_above = 0, n_kids = 0, n_tgt = 0, n_src = 0;
+  for (int lev = lmin; lev < D; ++lev) {
+    n_above += int64_t(t->boxes[lev].size());
+    n_kids += int64_t(t->boxes[lev + 1].size());
+  }
+  for (int lev = lmin; lev <= D; ++lev) {
+    n_tgt += int64_t(t->boxes[lev].size());
+    n_src += int64_t(t->il_idx[lev].size());
+  }
+  const bool walks = Q <= 9 && n_kids <= 2 * n_above && n_src <= 8 * n_tgt;
   // the upward walk: post-order program of every subtree below a box of
   // level lr = max(lmin, D - kUpWalkLevels); the levels above lr keep their
   // level-by-level passes, which read the walk's level-lr multipoles
-  if (Q <= 9 && D - lmin >= 1) {
+  if (walks && D - lmin >= 1) {
     const int lr = std::max(lmin, D - kUpWalkLevels);
     std::vector<UpInstr> prog;
     std::vector<int32_t> pptr{0};
@@ -211,7 +227,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
   // order of its downward-pass source list.  A walk root reads its parent's
   // local expansion (written by the level-by-level pass of level lr - 1)
   // like any source; below it the parent term comes from the registers.
-  if (Q <= 9) {
+  if (walks) {
     const int lr = std::max(lmin, D + 1 - kDownWalkLevels);
     std::vector<UpInstr> prog;
     std::vector<int32_t> pptr{0};

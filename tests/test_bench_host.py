@@ -9,11 +9,11 @@ import pytest
 import bench
 
 
-def _info(depth, lmin, ncomp=9, nb=None):
+def _info(depth, lmin, ncomp=9, nb=None, il=4):
     nb = nb or [2 ** l for l in range(depth + 1)]
     return SimpleNamespace(depth=depth, lmin=lmin, ncomp=ncomp, boxes_per_level=nb, m2m_nnz=36,
                            sum_nb=1000, sum_nb2=100000, nleaf=nb[depth], npairs=5000, n_edges=sum(nb[lmin + 1:]),
-                           n_il=10 * sum(nb[lmin:]), nbasis=800)
+                           n_il=il * sum(nb[lmin:]), nbasis=800)
 
 
 def _call(depth, lmin, nbatch):
@@ -53,6 +53,8 @@ def test_walk_roots_and_bytes():
     info = _info(8, 2)
     assert bench.walk_roots(info) == (2, 7)
     assert bench.walk_roots(_info(8, 2, ncomp=16)) == (None, None)
+    assert bench.walk_roots(_info(8, 2, il=40)) == (None, None)          # long interaction lists
+    assert bench.walk_roots(_info(4, 2, nb=[1, 4, 16, 64, 256])) == (None, None)   # 4 children per box
     walk = bench.class_costs(info, 100, 32, "fp64")
     nb = info.boxes_per_level
     # upward: leaves read once, every other box written once
@@ -62,3 +64,15 @@ def test_walk_roots_and_bytes():
     # its roots' parents and writes the leaves
     lv = sum(2 * nb[l] + (nb[l - 1] if l > 2 else 0) for l in range(2, 7))
     assert walk["down"][1] == (lv + nb[7] + nb[8] + nb[6] + nb[8]) * 9 * cols * 8
+
+
+def test_classes_of_level_passes_only():
+    info = _info(4, 2, il=40)
+    seq = ["occk::opgen_kernel"]
+    for _ in range(2):
+        seq += ["occk::half_kernel<0>", "occk::omega_kernel<0>"]
+        seq += ["occk::translate_vec_kernel<double, 9, 1>"] * 5   # 2 upward, 3 downward levels
+        seq += ["occk::l2p_kernel<0>", "occk::l2pt_kernel<0>"]
+    cls = bench._classify_last_call({i + 1: k for i, k in enumerate(seq)}, info)
+    per_batch = ["half", "omega", "up", "up", "down", "down", "down", "l2p", "l2p"]
+    assert [cls[i] for i in sorted(cls)] == ["opgen"] + per_batch * 2
