@@ -176,3 +176,28 @@ def test_batched_L3_mfma_translations(prec, tol):
     b.free()
     for t in trees:
         t.free()
+
+
+def test_walks_equal_level_passes_bitwise():
+    """Alkane chain (binary tree, short interaction lists): occk_far_K runs
+    the translations as subtree walks and the L2P in whole-leaf tiles, the
+    persistent batch kernel as level-by-level passes and 48-wide tiles.  Every
+    output takes its terms in the same order, so the two agree bit for bit."""
+    import torch
+    from paper_1708_05353_amd import occk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    wl = workloads.alkane_chain(n_carbon=100, depth=6)
+    tr = occk.Tree(wl.system, wl.params)
+    C = torch.from_numpy(wl.orbitals()).cuda()
+    n = C.shape[1]
+    print("[batch] alkane C100 walks vs level passes", flush=True)
+    K1 = torch.zeros((wl.system.nbasis, n), dtype=torch.float64, device="cuda")
+    occk.far_K(tr, C, K1, jblock=64)
+    K2 = torch.zeros_like(K1)
+    b = occk.Batch([tr], [n], occk.PREC_FP64, jblock=64)
+    b.run([C], [K2])
+    torch.cuda.synchronize()
+    b.free()
+    tr.free()
+    assert np.array_equal(K1.cpu().numpy(), K2.cpu().numpy())
