@@ -356,8 +356,10 @@ int32_t occk_debug_mfma_probe(int32_t kind, int32_t ia, int32_t ka, int32_t jb, 
 
 /* Copies a workspace buffer of the handle's last occk_far_K call to host
  * memory after a device synchronisation: which = 0 translation operators,
- * 1 half-transformed multipoles H, 2 box data (Omega then Mloc), 3 per-leaf K
- * partials.  *count receives the element count; host may be NULL to query it.
+ * 1 half-transformed multipoles H, 2 box data (Omega then Mloc; where the
+ * downward pass ran as a subtree walk, the Mloc of the boxes below the walk's
+ * roots and above the leaves are not written), 3 per-leaf K partials.
+ * *count receives the element count; host may be NULL to query it.
  * ESTATE before the first occk_far_K. */
 int32_t occk_debug_buffer(occk_tree* tree, int32_t which, double* host, int64_t* count);
 
