@@ -108,7 +108,7 @@ struct DeviceState {
   // (Q <= 9; the levels above run level by level): programs
   // [upw_ptr[r], upw_ptr[r + 1])
   DevBuf<int32_t> upw_ptr;
-  DevBuf<UpInstr> upw_prog;
+  DevBuf<WalkStep> upw_prog;
   int upw_nroots = 0;   // 0: the level-by-level passes run instead
   int upw_nlv = 0;      // accumulator levels, D - upw_lroot
   int upw_lroot = 0;
@@ -116,7 +116,7 @@ struct DeviceState {
   // dnw_lroot (Q <= 9; the levels above run level by level; not in the
   // learned-rank mode, whose ranks are per level-pass entry)
   DevBuf<int32_t> dnw_ptr;
-  DevBuf<UpInstr> dnw_prog;
+  DevBuf<WalkStep> dnw_prog;
   int dnw_nroots = 0;   // 0: the level-by-level passes run instead
   int dnw_nlv = 0;      // accumulator levels, D - dnw_lroot + 1
   int dnw_lroot = 0;

@@ -163,7 +163,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
   // level-by-level passes, which read the walk's level-lr multipoles
   if (walks && D - lmin >= 1) {
     const int lr = std::max(lmin, D - kUpWalkLevels);
-    std::vector<UpInstr> prog;
+    std::vector<WalkStep> prog;
     std::vector<int32_t> pptr{0};
     std::function<void(int, int32_t)> emit = [&](int lev, int32_t p) {
       for (const auto& kc : kids[size_t(lev)][size_t(p)]) {
@@ -229,7 +229,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
   // like any source; below it the parent term comes from the registers.
   if (walks) {
     const int lr = std::max(lmin, D + 1 - kDownWalkLevels);
-    std::vector<UpInstr> prog;
+    std::vector<WalkStep> prog;
     std::vector<int32_t> pptr{0};
     std::function<void(int, int32_t)> visit = [&](int lev, int32_t b) {
       const int lp = lev - lmin, li = lev - lr;   // pass index, accumulator level
@@ -533,7 +533,7 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
 // the upward (up) or downward walk over every subtree below level lmin
 // (setup built the programs)
 template <class T>
-void launch_walk(const Tree* t, const int32_t* pptr, const UpInstr* prog, int nroots, int nlv, bool up, T* data,
+void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int nroots, int nlv, bool up, T* data,
                  int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st) {
   if (cm.nvalid <= 0 || nroots == 0) return;
   const int Q = t->Q, KS = ksteps_of(Q);

@@ -923,22 +923,22 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
 }
 
 // --------------------------------------------------------------------------
-// upward pass as a walk (M2M, Eq. 8): one block per (subtree below a level
-// l_min box, 256 carried columns), one column per thread.  The block runs
-// the subtree's post-order program: UP_LEAF adds T_op M(leaf) into the
-// accumulator of the leaf's parent level; UP_CLOSE stores a finished box's
-// M and adds T_op M(box) into its parent's accumulator (op < 0: the subtree
-// root).  Internal boxes are written once and never read back, and every
-// accumulator takes the same FMA sequence as the level-by-level passes.
-// Accumulators are indexed by level relative to l_min (NLV levels in
-// registers); the next leaf's column values are in flight while the
-// current program step runs.
+// upward pass as a walk (M2M, Eq. 8): one block per (subtree below a box of
+// the walk's root level, 256 carried columns), one column per thread.  The
+// block runs the subtree's post-order program: UP_LEAF adds T_op M(leaf)
+// into the accumulator of the leaf's parent level; UP_CLOSE stores a
+// finished box's M and adds T_op M(box) into its parent's accumulator (op <
+// 0: the subtree root).  Internal boxes are written once and never read
+// back, and every accumulator takes the same FMA sequence as the
+// level-by-level passes.  Accumulators are indexed by level relative to the
+// root level (NLV levels in registers); the next leaf's column values are in
+// flight while the current program step runs.
 // --------------------------------------------------------------------------
-struct UpInstr {
-  int32_t kind;    // UP_LEAF or UP_CLOSE
-  int32_t level;   // accumulator (level - l_min) the step adds into (LEAF) or closes (CLOSE)
-  int32_t box;     // box slot read (LEAF) or written (CLOSE)
-  int32_t op;      // operator into the parent level (CLOSE of a subtree root: -1)
+struct WalkStep {   // one step of an upward or downward walk program
+  int32_t kind;    // UP_LEAF, UP_CLOSE (upward); DN_BEGIN, DN_SRC, DN_STORE (downward)
+  int32_t level;   // accumulator: tree level minus the walk's root level
+  int32_t box;     // box slot read (UP_LEAF, DN_SRC) or written (UP_CLOSE, DN_STORE)
+  int32_t op;      // operator of the step's term (-1: none)
 };
 enum { UP_LEAF = 0, UP_CLOSE = 1 };
 constexpr int kUpWalkLevels = 6;   // accumulator levels (below the walk's root level) held in registers
@@ -946,7 +946,7 @@ constexpr int kUpWalkLevels = 6;   // accumulator levels (below the walk's root 
 template <class T, int Q, int NLV>
 __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                       const int32_t* __restrict__ prog_ptr,
-                                                      const UpInstr* __restrict__ prog, const T* __restrict__ ops,
+                                                      const WalkStep* __restrict__ prog, const T* __restrict__ ops,
                                                       int nroots, int64_t nblocks) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
   const int64_t ncol = cm.ncol;
   const int64_t opsz = int64_t(KS) * 64;
   const gbl<const T>* base = as_global(static_cast<const T*>(data));
-  const cst<UpInstr>* pg = as_const(prog);
+  const cst<WalkStep>* pg = as_const(prog);
   const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
   T acc[NLV][Q];
 #pragma unroll
@@ -984,7 +984,7 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
   int nl = next_leaf(p0);
   if (nl < p1) fetch(nl);
   for (int s = p0; s < p1; ++s) {
-    const UpInstr in = load_const(prog + s);
+    const WalkStep in = load_const(prog + s);
     if (in.kind == UP_LEAF) {
       T x[Q];
       for (int k = 0; k < Q; ++k) x[k] = xn[k];
@@ -1009,8 +1009,8 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
 
 // --------------------------------------------------------------------------
 // downward pass as a walk (L2L and M2L, Eq. 8): one block per (subtree
-// below a level l_min box, 256 carried columns), one column per thread, in
-// pre-order.  DN_BEGIN opens a box at a level: its accumulator starts at
+// below a box of the walk's root level, 256 carried columns), one column per
+// thread, in pre-order.  DN_BEGIN opens a box at a level: its accumulator starts at
 // zero and takes T_op L(parent) from the parent level's accumulator (op < 0:
 // a subtree root, which has no parent term); DN_SRC adds T_op M(box) of an
 // interaction-list source; DN_STORE writes a leaf's local expansion.  The
@@ -1024,7 +1024,7 @@ constexpr int kDownWalkLevels = 2;   // accumulator levels (root level..D) held 
 template <class T, int Q, int NLV>
 __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                         const int32_t* __restrict__ prog_ptr,
-                                                        const UpInstr* __restrict__ prog, const T* __restrict__ ops,
+                                                        const WalkStep* __restrict__ prog, const T* __restrict__ ops,
                                                         int nroots, int64_t nblocks) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
   const int64_t ncol = cm.ncol;
   const int64_t opsz = int64_t(KS) * 64;
   const gbl<const T>* base = as_global(static_cast<const T*>(data));
-  const cst<UpInstr>* pg = as_const(prog);
+  const cst<WalkStep>* pg = as_const(prog);
   const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
   T acc[NLV][Q];
 #pragma unroll
@@ -1061,7 +1061,7 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
   int ns = next_src(p0);
   if (ns < p1) fetch(ns);
   for (int s = p0; s < p1; ++s) {
-    const UpInstr in = load_const(prog + s);
+    const WalkStep in = load_const(prog + s);
     if (in.kind == DN_SRC) {
       T x[Q];
       for (int k = 0; k < Q; ++k) x[k] = xn[k];
