@@ -1,0 +1,50 @@
+"""Which schedule runs the translations: subtree walks on chain-like trees
+(binary splits, short interaction lists), level-by-level passes elsewhere.
+The library's launch counts per call must match bench.walk_roots, which
+prices and classifies the profiles with the same rule."""
+import pytest
+
+import bench
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _launches(wl, jblock):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1708_05353_amd import occk
+    tr = occk.Tree(wl.system, wl.params)
+    info = tr.info
+    C = torch.from_numpy(wl.orbitals()).cuda()
+    K = torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda")
+    tr.profile(True)
+    tr.profile_read()
+    occk.far_K(tr, C, K, jblock=jblock)
+    torch.cuda.synchronize()
+    prof = tr.profile_read()
+    tr.profile(False)
+    tr.free()
+    nbatch = -(-C.shape[1] // jblock)
+    return info, prof["up"][1] // nbatch, prof["down"][1] // nbatch, prof["up"][1] % nbatch
+
+
+@pytest.mark.parametrize("name", ["alkane_C100", "water75", "graphene"])
+def test_schedule_matches_bench_rule(name):
+    wl = {"alkane_C100": lambda: workloads.alkane_chain(n_carbon=100, depth=6),
+          "water75": lambda: workloads.water_cluster(15, 43, lmax=2),
+          "graphene": lambda: workloads.graphene_flake(lmax=2)}[name]()
+    print(f"[walks] {name}", flush=True)
+    info, up, down, rest = _launches(wl, 64)
+    assert rest == 0
+    lr_up, lr_dn = bench.walk_roots(info)
+    D, lmin = info.depth, info.lmin
+    if name == "alkane_C100":
+        assert lr_up is not None and lr_dn is not None
+    else:
+        assert lr_up is None and lr_dn is None
+    if lr_up is None:
+        assert (up, down) == (D - lmin, D - lmin + 1)
+    else:
+        assert (up, down) == (1 + lr_up - lmin, lr_dn - lmin + 1)
