@@ -169,3 +169,25 @@ def test_atom_permutation(sheet):
     K2 = far_K(st2, C[rowmap])
     assert rel(K2, far_K(st, C)[rowmap]) < 1e-12
     del inv
+
+
+@pytest.mark.parametrize("which", ["chain", "sheet"])
+def test_rank_truncated_m2l_equals_lower_lmax(which, tiny):
+    """Interaction-list truncation to l, l' <= p (Eq. 12 at rank p) inside an
+    L = 4 expansion equals the whole method run at lmax = p: M2M (Eq. 11) gives
+    order l only from orders l' <= l, so the rank-p multipoles are the lmax = p
+    ones; the truncated M2L leaves every local component above p at zero and
+    L2L (Eq. 13) keeps them at zero, so L2P sees exactly the lmax = p locals."""
+    if which == "chain":
+        wl, C, _ = tiny
+    else:
+        wl = small_sheet(lmax=4, depth=3)
+        C = wl.orbitals()
+    st4 = Setup(wl.system, with_params(wl, lmax=4))
+    for p in range(4):
+        stp = Setup(wl.system, with_params(wl, lmax=p))
+        Kp = far_K(stp, C)
+        Kt = far_K(st4, C, m2l_rank=p)
+        assert rel(Kt, Kp) < 1e-13, (which, p)
+    # the truncation is not a no-op: rank 3 differs from the full rank 4
+    assert rel(far_K(st4, C, m2l_rank=3), far_K(st4, C)) > 1e-6

@@ -45,3 +45,23 @@ def test_m2l_missing_parity_is_caught(tiny, monkeypatch):
     monkeypatch.setattr(fmm, "m2l_matrix", no_parity)
     bad = rel(fmm.far_K(st, C), Kp)
     assert good < 2e-2 and bad > 10 * good
+
+
+def test_truncation_keeping_p_squared_components_is_caught(tiny, monkeypatch):
+    """Rank truncation that keeps p^2 instead of (p+1)^2 components (drops the
+    whole order l = p) breaks the rank-p == lmax-p pin."""
+    from oracle.fmm import Setup
+    from conftest import with_params
+    wl, C, st = tiny
+    st3 = Setup(wl.system, with_params(wl, lmax=3))
+    st2 = Setup(wl.system, with_params(wl, lmax=2))
+    good = rel(fmm.far_K(st3, C, m2l_rank=2), fmm.far_K(st2, C))
+
+    def short(T, p):
+        n = p * p
+        out = np.zeros_like(T)
+        out[:n, :n] = T[:n, :n]
+        return out
+    monkeypatch.setattr(fmm, "truncate", short)
+    bad = rel(fmm.far_K(st3, C, m2l_rank=2), fmm.far_K(st2, C))
+    assert good < 1e-13 and bad > 1e-3
