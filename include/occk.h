@@ -146,6 +146,25 @@ int32_t occk_free_tree(occk_tree* tree);
 /* Counts of the built tree (host only). */
 int32_t occk_tree_info(const occk_tree* tree, occk_tree_info_t* info);
 
+/* Algorithmic flop model of one occk_far_K call over ni output columns i and
+ * nj summed columns j (host only).  The terms are the method's own work on the
+ * built tree, Q = (L+1)^2:
+ *   half   Eq. (15a)  2 Q nj npairs
+ *   omega  Eq. (15b)  2 Q ni nj sum_B nB, or Q n (n+1) sum_B nB when symmetric
+ *   m2m    Eq. (17a)  2 z nc E   (z = m2m_nnz, E = n_edges)
+ *   m2l    Eq. (17b)  2 Q^2 nc n_il
+ *   l2l    Eq. (17c)  2 z nc E
+ *   l2p    Eq. (18)   2 Q ni nj sum_B nB
+ * with nc = ni nj translated (j, i) columns, or nc = n (n+1)/2 when symmetric
+ * != 0: the occupied-pair multipoles and every translated expansion are
+ * symmetric in (i, j), so that many columns are all the method must carry
+ * (symmetric needs ni == nj = n; EINVAL otherwise).  A tree with no far field
+ * gives zeros.  out->total is the sum of the six terms. */
+typedef struct occk_flops_t {
+  int64_t half, omega, m2m, m2l, l2l, l2p, total;
+} occk_flops_t;
+int32_t occk_tree_flops(const occk_tree* tree, int32_t ni, int32_t nj, int32_t symmetric, occk_flops_t* out);
+
 /* Host-side export for checking the tree against an independent one.
  *   leaf_coords  [nleaf*3] int32 integer box indices of the leaves (level depth),
  *                in the library's leaf order; may be NULL

@@ -5,6 +5,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
@@ -39,17 +40,18 @@ def _run(cmd, verbose):
 def build(verbose: bool = False) -> str:
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
-    objs = []
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     cxx = os.path.join(ROCM, "llvm", "bin", "clang++")
+    jobs = []
     for src in HIP_SOURCES:
-        obj = os.path.join(bdir, src + ".o")
-        _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", os.path.join(bdir, src + ".o")])
     for src in CXX_SOURCES:
-        obj = os.path.join(bdir, src + ".o")
-        _run([cxx, *CXX_FLAGS, f"-I{ROCM}/include", "-c", os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append([cxx, *CXX_FLAGS, f"-I{ROCM}/include", "-c", os.path.join(CSRC, src),
+                     "-o", os.path.join(bdir, src + ".o")])
+    objs = [j[-1] for j in jobs]
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1)) as ex:
+        list(ex.map(lambda cmd: _run(cmd, verbose), jobs))
     tmp = OUT + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, OUT)

@@ -142,6 +142,37 @@ int32_t occk_tree_info(const occk_tree* tree, occk_tree_info_t* info) {
   return OCCK_OK;
 }
 
+int32_t occk_tree_flops(const occk_tree* tree, int32_t ni, int32_t nj, int32_t symmetric, occk_flops_t* out) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_flops: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!out || ni < 0 || nj < 0 || (symmetric && ni != nj)) {
+    set_error("occk_tree_flops: out must be non-NULL, ni, nj >= 0, and ni == nj when symmetric");
+    return OCCK_EINVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  if (t->lmin < 0) return OCCK_OK;
+  const int D = t->params.depth;
+  int64_t n_il = 0, n_edges = 0, sum_nb = 0;
+  for (int lev = 0; lev <= D; ++lev) {
+    n_il += int64_t(t->il_idx[lev].size());
+    if (lev > t->lmin) n_edges += int64_t(t->boxes[lev].size());
+  }
+  for (const auto& f : t->leaf_funcs) sum_nb += int64_t(f.size());
+  const int64_t Q = t->Q, a = ni, b = nj;
+  const int64_t nc = symmetric ? a * (a + 1) / 2 : a * b;
+  out->half = 2 * Q * b * int64_t(t->pairs.size());
+  out->omega = symmetric ? Q * a * (a + 1) * sum_nb : 2 * Q * a * b * sum_nb;
+  out->m2m = 2 * t->m2m_nnz * nc * n_edges;
+  out->m2l = 2 * Q * Q * nc * n_il;
+  out->l2l = out->m2m;
+  out->l2p = 2 * Q * a * b * sum_nb;
+  out->total = out->half + out->omega + out->m2m + out->m2l + out->l2l + out->l2p;
+  return OCCK_OK;
+}
+
 int32_t occk_tree_export(const occk_tree* tree, int32_t* leaf_coords, int32_t* il_level,
                          int32_t* il_target, int32_t* il_source, int32_t* pair_leaf) {
   const Tree* t = reinterpret_cast<const Tree*>(tree);

@@ -796,12 +796,24 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       HIP_OK(hipGetLastError());
       return OCCK_OK;
     }
-    if (!t->dev) upload_tree(t);
-    DeviceState* ds = t->dev;
-    if (mixed) ensure_mixed_operands(t, st);
     const size_t es = mixed ? 4 : 8;
     const bool sym = i0 == j0 && i1 == j1;   // symmetric schedule when the i and j ranges coincide
     const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es, sym);
+    {
+      // host-side check before any HIP call: leaf multipole blocks and the
+      // workspace of this batch width must fit under the device-byte cap
+      int64_t sum_nb = 0, sum_nb2 = 0, nbox = 0;
+      for (const auto& f : t->leaf_funcs) {
+        sum_nb += int64_t(f.size());
+        sum_nb2 += int64_t(f.size()) * int64_t(f.size());
+      }
+      for (int lev = t->lmin; lev <= t->params.depth; ++lev) nbox += int64_t(t->boxes[lev].size());
+      const size_t need = size_t(sum_nb2) * size_t(t->Q) * 8 + workspace_need(sum_nb, t->Q, nbox, jb, ni, es, sym);
+      if (need > device_cap()) throw std::bad_alloc();
+    }
+    if (!t->dev) upload_tree(t);
+    DeviceState* ds = t->dev;
+    if (mixed) ensure_mixed_operands(t, st);
     setup_workspace(t, jb, ni, prec, sym);
     const int Q = t->Q;
     const bool prof = t->profile != 0;

@@ -923,7 +923,7 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
 }
 
 // --------------------------------------------------------------------------
-// upward pass as a walk (M2M, Eq. 8): one block per (subtree below a box of
+// upward pass as a walk (M2M, Eqs. 11 and 17a): one block per (subtree below a box of
 // the walk's root level, 256 carried columns), one column per thread.  The
 // block runs the subtree's post-order program: UP_LEAF adds T_op M(leaf)
 // into the accumulator of the leaf's parent level; UP_CLOSE stores a
@@ -1008,7 +1008,7 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
 }
 
 // --------------------------------------------------------------------------
-// downward pass as a walk (L2L and M2L, Eq. 8): one block per (subtree
+// downward pass as a walk (L2L and M2L, Eqs. 12, 13 and 17b,c): one block per (subtree
 // below a box of the walk's root level, 256 carried columns), one column per
 // thread, in pre-order.  DN_BEGIN opens a box at a level: its accumulator starts at
 // zero and takes T_op L(parent) from the parent level's accumulator (op < 0:

@@ -46,6 +46,10 @@ class _Info(ct.Structure):
                 ("mid", ct.c_double * 3)]
 
 
+class _Flops(ct.Structure):
+    _fields_ = [(k, ct.c_int64) for k in ("half", "omega", "m2m", "m2l", "l2l", "l2p", "total")]
+
+
 class _Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
                 ("jblock", ct.c_int32), ("accumulate", ct.c_int32)]
@@ -57,6 +61,7 @@ EXPORTS = {
     "occk_build_tree": (ct.c_int32, [ct.POINTER(_System), ct.POINTER(_Params), ct.POINTER(ct.c_void_p)]),
     "occk_free_tree": (ct.c_int32, [ct.c_void_p]),
     "occk_tree_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(_Info)]),
+    "occk_tree_flops": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(_Flops)]),
     "occk_tree_export": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p]),
     "occk_tree_leaf": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.c_void_p,
@@ -248,35 +253,13 @@ class Tree:
 
     # ------------------------------------------------------------------
     def flops(self, ni: int, nj: int, symmetric: bool = False) -> dict:
-        """Algorithmic flop counts of one occk_far_K call.
+        """Algorithmic flop counts of one occk_far_K call (occk_tree_flops).
 
-        symmetric=False: paper-as-written, all ni*nj (j, i) columns carried
-        through the translations.  symmetric=True (i and j over the same n
-        orbitals): Omega and the translated expansions are symmetric in
-        (i, j), so n_c = n(n+1)/2 columns and F_Omega = Q n(n+1) sum_B n_B;
-        the half transform and L2P are unchanged."""
-        inf = self.info
-        Q = inf.ncomp
-        if inf.lmin < 0:
-            return dict(half=0, omega=0, m2m=0, m2l=0, l2l=0, l2p=0, total=0)
-        if symmetric:
-            if ni != nj:
-                raise ValueError("the symmetric count needs equal i and j ranges")
-            nc = ni * (ni + 1) // 2
-            omega = Q * ni * (ni + 1) * inf.sum_nb
-        else:
-            nc = ni * nj
-            omega = 2 * Q * nj * ni * inf.sum_nb
-        f = dict(
-            half=2 * Q * inf.npairs * nj,
-            omega=omega,
-            m2m=2 * inf.m2m_nnz * nc * inf.n_edges,
-            m2l=2 * Q * Q * nc * inf.n_il,
-            l2l=2 * inf.m2m_nnz * nc * inf.n_edges,
-            l2p=2 * Q * nj * ni * inf.sum_nb,
-        )
-        f["total"] = sum(f.values())
-        return f
+        symmetric=False: paper-as-written, all ni*nj (j, i) columns carried.
+        symmetric=True (i and j over the same n orbitals): n(n+1)/2 columns."""
+        f = _Flops()
+        _check(lib().occk_tree_flops(self._h, int(ni), int(nj), int(bool(symmetric)), ct.byref(f)))
+        return {k: int(getattr(f, k)) for k, _ in _Flops._fields_}
 
 
 def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,

@@ -78,6 +78,34 @@ def test_info_counts_tiny_chain():
     assert inf.lo[0] == pytest.approx(-1.015) and inf.width / 8 == pytest.approx(5.1125)
 
 
+def test_flop_model_matches_oracle_counts():
+    """occk_tree_flops against the survey's formulas, with every count taken
+    from the oracle's own tree (pairs, leaf functions, interaction lists)."""
+    wl = workloads.tiny_chain()
+    st = Setup(wl.system, wl.params)
+    tr = occk.Tree(wl.system, wl.params)
+    Q, z = 9, tr.info.m2m_nnz
+    npairs = len(st.r)
+    sum_nb = sum(len(f) for f in st.leaf_funcs)
+    t = st.tree
+    n_il = sum(len(v) for lev in range(t.lmin, t.depth + 1) for v in t.il[lev])
+    edges = sum(len(t.boxes[lev]) for lev in range(t.lmin + 1, t.depth + 1))
+    ni, nj = 7, 5
+    f = tr.flops(ni, nj)
+    nc = ni * nj
+    assert f == dict(half=2 * Q * nj * npairs, omega=2 * Q * ni * nj * sum_nb, m2m=2 * z * nc * edges,
+                     m2l=2 * Q * Q * nc * n_il, l2l=2 * z * nc * edges, l2p=2 * Q * ni * nj * sum_nb,
+                     total=f["total"])
+    assert f["total"] == sum(v for k, v in f.items() if k != "total")
+    n = 20
+    fs = tr.flops(n, n, symmetric=True)
+    assert fs["m2l"] == 2 * Q * Q * (n * (n + 1) // 2) * n_il
+    assert fs["omega"] == Q * n * (n + 1) * sum_nb
+    with pytest.raises(occk.OcckError):
+        tr.flops(3, 4, symmetric=True)
+    tr.free()
+
+
 def _sys_struct(wl):
     s = wl.system
     keep = []
@@ -143,6 +171,22 @@ def test_far_K_validates_before_device_work():
     assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(learned), K, 20, None) == occk.ESTATE
     neg = occk._Opts(0, 0, None, -4, 0)
     assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(neg), K, 20, None) == occk.EINVAL
+
+
+def test_device_byte_cap_gives_enomem_before_device_work(monkeypatch):
+    """OCCK_MAX_DEVICE_BYTES below the leaf multipole blocks plus the workspace
+    of one j batch: occk_far_K reports ENOMEM from the host-side size check,
+    before any HIP call (this runs without a GPU; the pointers are fake)."""
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    monkeypatch.setenv("OCCK_MAX_DEVICE_BYTES", "4096")
+    L = occk.lib()
+    opts = occk._Opts(0, 0, None, 0, 0)
+    rc = L.occk_far_K(tr.handle, ct.c_void_p(0x100000), 20, 20, 0, 20, 0, 20, ct.byref(opts),
+                      ct.c_void_p(0x900000), 20, None)
+    assert rc == occk.ENOMEM
+    assert b"OCCK_MAX_DEVICE_BYTES" in L.occk_last_error()
+    tr.free()
 
 
 def test_handles():
