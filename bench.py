@@ -97,8 +97,99 @@ def class_costs(info, n, jb, prec):
     }
 
 
-def cpu_baseline(wl, C, flops_total, nocc, jsample):
-    import numpy as np
+# kernel -> profile class of the library (occk.KERNEL_CLASSES) whose HIP-event
+# time is that kernel's; "half", "up_pass", "down_pass" are a class minus its
+# nested single-kernel class
+KERNELS = ["ht", "half", "omega", "up_walk", "up_pass", "down_walk", "down_pass", "l2p_direct", "l2p_mirror", "reduce"]
+
+
+def kernel_times(prof):
+    """ms and launches of each kernel from the per-class profile."""
+    def sub(a, b):
+        return (prof[a][0] - prof[b][0], prof[a][1] - prof[b][1])
+    return {"ht": prof["ht"], "half": sub("half", "ht"), "omega": prof["omega"],
+            "up_walk": prof["up_walk"], "up_pass": sub("up", "up_walk"),
+            "down_walk": prof["down_walk"], "down_pass": sub("down", "down_walk"),
+            "l2p_direct": prof["l2p_direct"], "l2p_mirror": prof["l2p_mirror"], "reduce": prof["reduce"]}
+
+
+def kernel_costs(info, n, jb, prec):
+    """Algorithmic flops and bytes per call of each kernel of the full
+    symmetric call (i and j over all n orbitals).
+
+    Flops: the method's counts with n_c = n(n+1)/2 translated columns, split
+    by the levels each kernel covers; the half transform F_half = 2 Q n
+    sum_B pi_B is the method's once, and both its launches (all columns for
+    the mirrored L2P, then per j batch) are priced with it, so their sum is
+    twice the method's; the L2P's 2 Q n^2 sum_B n_B splits into the column
+    pairs the direct contraction covers (j in the batch, i from the batch's
+    first j on) and the mirrored rest.  Bytes: the compulsory traffic of the
+    schedule as executed (every box a kernel touches read or written once per
+    batch, GEMM operands once), as in class_costs."""
+    Q = info.ncomp
+    s = ELEM_BYTES[prec]
+    nb, il = info.boxes_per_level, info.il_per_level
+    lmin, D = info.lmin, info.depth
+    nblk = -(-n // jb)
+    nks = [n - k * jb for k in range(nblk)]
+    nc_exec = sum(jb * nk for nk in nks)
+    nc = n * (n + 1) // 2
+    z = info.m2m_nnz
+    snb, snb2, nleaf = info.sum_nb, info.sum_nb2, info.nleaf
+    lr_up, lr_dn = walk_roots(info)
+    if lr_up is None:
+        lr_up = D
+    if lr_dn is None:
+        lr_dn = D + 1
+    f_up = lambda a, b: 2 * z * nc * sum(nb[l] for l in range(a, b))              # children at levels [a, b)
+    f_m2l = lambda a, b: 2 * Q * Q * nc * sum(il[l] for l in range(a, b))
+    f_l2l = lambda a, b: 2 * z * nc * sum(nb[l] for l in range(max(a, lmin + 1), b))
+    up_walk_boxes = (nb[D] + sum(nb[l] for l in range(lr_up, D))) if lr_up < D else 0
+    up_pass_boxes = sum(nb[l] + nb[l + 1] for l in range(lmin, lr_up))
+    dn_pass_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, min(lr_dn, D + 1)))
+    dn_walk_boxes = ((sum(nb[l] for l in range(lr_dn, D + 1)) + (nb[lr_dn - 1] if lr_dn > lmin else 0) + nb[D])
+                     if lr_dn <= D else 0)
+    f_half = 2 * Q * info.npairs * n
+    return {
+        "ht": (f_half, (snb2 * Q + snb * n * (1 + Q)) * s),
+        "half": (f_half, nblk * (snb2 * Q + snb * jb * (1 + Q)) * s),
+        "omega": (Q * n * (n + 1) * snb, sum(snb * Q * jb + snb * nk + nleaf * Q * jb * nk for nk in nks) * s),
+        "up_walk": (f_up(lr_up + 1, D + 1), up_walk_boxes * Q * nc_exec * s),
+        "up_pass": (f_up(lmin + 1, lr_up + 1), up_pass_boxes * Q * nc_exec * s),
+        "down_walk": (f_m2l(lr_dn, D + 1) + f_l2l(lr_dn, D + 1), dn_walk_boxes * Q * nc_exec * s),
+        "down_pass": (f_m2l(lmin, lr_dn) + f_l2l(lmin, lr_dn), dn_pass_boxes * Q * nc_exec * s),
+        "l2p_direct": (2 * Q * snb * nc_exec, sum(nleaf * Q * jb * nk * s + snb * nk * 8 for nk in nks)),
+        "l2p_mirror": (2 * Q * snb * (n * n - nc_exec),
+                       sum((nleaf * Q * jb * max(0, nk - jb) + snb * Q * max(0, nk - jb)) * s + 2 * snb * jb * 8
+                           for nk in nks)),
+        "reduce": (0, (snb * n + info.nbasis * n) * 8),
+    }
+
+
+def cpu_model() -> str:
+    """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, C, flops_total, nocc, jsample, repeats):
+    """The FP64 oracle on the host cores: far_K for all i and j in [0, jsample),
+    best of `repeats` runs, scaled linearly to all nocc j columns (the oracle's
+    cost is linear in the summed j columns)."""
     from oracle.fmm import Setup, far_K as oracle_far_K
     try:
         from threadpoolctl import threadpool_info
@@ -108,15 +199,18 @@ def cpu_baseline(wl, C, flops_total, nocc, jsample):
     t0 = time.perf_counter()
     st = Setup(wl.system, wl.params)
     t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle_far_K(st, C, j_range=(0, jsample))
-    t = time.perf_counter() - t0
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        oracle_far_K(st, C, j_range=(0, jsample), jblock=jsample)
+        times.append(time.perf_counter() - t0)
+    t = min(times)
     t_full = t * nocc / jsample
     return {"value": round(flops_total / t_full / 1e9, 4), "unit": "GFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"oracle far_K for j in [0,{jsample}) of {nocc} (all i): {t:.1f} s, scaled x{nocc / jsample:.1f} "
-                      f"(cost is linear in the j columns); oracle setup {t_setup:.0f} s excluded, as the tree build "
-                      f"is excluded on the GPU"}
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "sample": f"oracle far_K for all i and j in [0,{jsample}) of {nocc}: best of {repeats} runs "
+                      f"({', '.join(f'{x:.1f}' for x in times)} s), scaled x{nocc / jsample:.1f} (cost is linear in "
+                      f"the j columns); oracle setup {t_setup:.0f} s excluded, as the tree build is excluded on the GPU"}
 
 
 def bench_batch(args):
@@ -393,6 +487,21 @@ def measured_traffic(cls: str):
     return None
 
 
+def measured_call_traffic():
+    """HBM bytes of one whole call from the committed counter summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            for line in fh:
+                if line.startswith("<!-- traffic "):
+                    rec = json.loads(line[len("<!-- traffic "):].rsplit("-->", 1)[0])
+                    if rec["digest"] != kernel_source_digest():
+                        return None
+                    return rec.get("call_bytes")
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def _pmc_rows(d, counter):
     import csv
     import glob
@@ -408,11 +517,12 @@ def _pmc_rows(d, counter):
 
 
 def _classify_last_call(names, info):
-    """Kernel class of every dispatch of the last occk_far_K call in a
-    profile of 'bench.py --no-mixed' (dispatch id -> kernel name): each call
-    starts with the operator generation; the translations of a j batch are
-    n_up upward then n_down downward launches (or one upward walk, then the
-    downward launches)."""
+    """Kernel (one of KERNELS, or "opgen") of every dispatch of the last
+    occk_far_K call in a profile of 'bench.py --no-mixed' (dispatch id ->
+    kernel name): each call starts with the operator generation and, in the
+    symmetric schedule, the all-column half transform; the translations of a
+    j batch are the upward level passes, then the downward ones, with the
+    walks (when used) covering the levels below their roots."""
     n_up, n_down = info.depth - info.lmin, info.depth - info.lmin + 1
     ids = sorted(i for i in names if "occk::" in names[i])
     start = max(i for i in ids if "opgen" in names[i])      # the last call
@@ -423,33 +533,37 @@ def _classify_last_call(names, info):
         ntr_all = sum(1 for i in ids if i >= start and "translate" in names[i])
         if ntr_all != (len(walks) // 2) * (n_up + n_down):
             raise SystemExit("translation launches do not match the walk root levels")
-    cls_of, ntr = {}, 0
+    kind, ntr, seen_half = {}, 0, False
     for i in ids:
         if i < start:
             continue
         k = names[i]
         if "up_walk" in k or "down_walk" in k:
-            cls_of[i] = "up" if "up_walk" in k else "down"
+            kind[i] = "up_walk" if "up_walk" in k else "down_walk"
             continue
         if "translate" in k:
             ntr += 1
-            cls_of[i] = "up" if (ntr - 1) % (n_up + n_down) < n_up else "down"
+            kind[i] = "up_pass" if (ntr - 1) % (n_up + n_down) < n_up else "down_pass"
             continue
-        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("half_kernel", "half"),
-                       ("omega_kernel", "omega"), ("l2pt_kernel", "l2p"), ("l2pt_wide_kernel", "l2p"),
-                       ("l2p_kernel", "l2p"), ("l2p_wide_kernel", "l2p")):
+        if "half_kernel" in k:
+            kind[i] = "half" if seen_half else "ht"
+            seen_half = True
+            continue
+        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("omega_kernel", "omega"),
+                       ("l2pt_kernel", "l2p_mirror"), ("l2pt_wide_kernel", "l2p_mirror"),
+                       ("l2p_kernel", "l2p_direct"), ("l2p_wide_kernel", "l2p_direct")):
             if key in k:
-                cls_of[i] = c
+                kind[i] = c
                 break
         else:
             raise SystemExit(f"unexpected kernel in the sequence: {k}")
-    return cls_of
+    return kind
 
 
 def trace_summary(trace_dir):
-    """Per-class launch times of the last occk_far_K call recorded by
-    'rocprofv3 --kernel-trace' of 'bench.py --no-mixed' (the same classes
-    and launch averages as the bench line's breakdown); prints markdown."""
+    """Per-kernel launch times of the last occk_far_K call recorded by
+    'rocprofv3 --kernel-trace' of 'bench.py --no-mixed' (the same kernels
+    and launch averages as the bench line's "kernels"); prints markdown."""
     import csv
     import glob
     import re
@@ -464,15 +578,15 @@ def trace_summary(trace_dir):
                 dur[i] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
     wl = workloads.alkane_chain()
     tr = occk.Tree(wl.system, wl.params)
-    cls_of = _classify_last_call(names, tr.info)
+    kind = _classify_last_call(names, tr.info)
     tot = {}
-    for i, c in cls_of.items():
+    for i, c in kind.items():
         n, t = tot.get(c, (0, 0.0))
         tot[c] = (n + 1, t + dur[i])
-    print("Per kernel class, last call of the run (the bench line's classes; `python3 bench.py --trace-summary "
+    print("Per kernel, last call of the run (the bench line's \"kernels\"; `python3 bench.py --trace-summary "
           f"{trace_dir}`):\n")
-    print("| class | launches | ms | average launch, us |\n|---|---|---|---|")
-    for c in ["half", "omega", "up", "down", "l2p", "reduce"]:
+    print("| kernel | launches | ms | average launch, us |\n|---|---|---|---|")
+    for c in KERNELS:
         if c in tot:
             n, t = tot[c]
             print(f"| {c} | {n} | {t * 1e3:.2f} | {t / n * 1e6:.1f} |")
@@ -497,36 +611,42 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
     wl = workloads.alkane_chain()
     tr = occk.Tree(wl.system, wl.params)
     info = tr.info
-    cls_of = _classify_last_call({i: F[i][0] for i in F}, info)
+    kind = _classify_last_call({i: F[i][0] for i in F}, info)
     tot = {}
-    for i, c in cls_of.items():
+    for i, c in kind.items():
         n, fb, wb = tot.get(c, (0, 0.0, 0.0))
         tot[c] = (n + 1, fb + F[i][1] * 1024 * fetch_scale, wb + W.get(i, ("", 0.0))[1] * 1024 * write_scale)
     jb = 256
-    costs = class_costs(info, wl.system.nocc, jb, "fp64")
-    print("# HBM traffic per kernel class: alkane chain, L = 2, FP64 (one occk_far_K call)\n")
+    costs = kernel_costs(info, wl.system.nocc, jb, "fp64")
+    b_alg = 8 * (info.ncomp * info.npairs + 2 * info.nbasis * wl.system.nocc)
+    print("# HBM traffic per kernel: alkane chain, L = 2, FP64 (one occk_far_K call)\n")
     print("Commands (repository root, one MI355X, `export TMPDIR=/tmp`):\n\n```")
     for c in cmds:
         print(c)
     print("```\n")
     print(f"Scale factors from the {copy_mib} MiB copy: FETCH_SIZE x{fetch_scale:.3f}, WRITE_SIZE x{write_scale:.3f} "
-          "(bytes moved per byte the counter reports).  Algorithmic bytes: the compulsory traffic of the schedule "
-          "as executed (`class_costs` in bench.py).  The half class includes the all-column HT transform, l2p "
-          "both L2P contractions.\n")
-    print("| class | launches | HBM read GB | HBM write GB | HBM total GB | algorithmic GB | ratio | bytes per launch |")
+          "(bytes moved per byte the counter reports).  Schedule bytes: the compulsory traffic of the schedule "
+          "as executed (`kernel_costs` in bench.py: every box a kernel touches read or written once per j batch, "
+          "GEMM operands once).\n")
+    print("| kernel | launches | HBM read GB | HBM write GB | HBM total GB | schedule GB | ratio | bytes per launch |")
     print("|---|---|---|---|---|---|---|---|")
-    per_launch = {}
-    for c in ["half", "omega", "up", "down", "l2p", "reduce"]:
+    per_launch, call = {}, 0.0
+    for c in KERNELS + ["opgen"]:
         if c not in tot:
             continue
         n, fb, wb = tot[c]
+        call += fb + wb
+        if c == "opgen":
+            continue
         alg = costs[c][1]
         per_launch[c] = (fb + wb) / n
         print(f"| {c} | {n} | {fb / 1e9:.2f} | {wb / 1e9:.2f} | {(fb + wb) / 1e9:.2f} | {alg / 1e9:.2f} | "
               f"{(fb + wb) / alg:.2f} | {per_launch[c]:.4g} |")
     print()
+    print(f"Whole call: {call / 1e9:.1f} GB of HBM traffic against the method's compulsory "
+          f"B_alg = 8 (Q sum_B pi_B + 2 nbasis nocc) = {b_alg / 1e9:.3f} GB (ratio {call / b_alg:.0f}).\n")
     print("<!-- traffic " + json.dumps({"digest": kernel_source_digest(), "fetch_scale": round(fetch_scale, 4),
-                                        "write_scale": round(write_scale, 4),
+                                        "write_scale": round(write_scale, 4), "call_bytes": round(call),
                                         "per_launch_bytes": {k: round(v) for k, v in per_launch.items()}}) + " -->")
 
 
@@ -549,7 +669,8 @@ def main():
     ap.add_argument("--jblock", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 mixed-path comparison")
-    ap.add_argument("--cpu-sample-j", type=int, default=2)
+    ap.add_argument("--cpu-sample-j", type=int, default=16)
+    ap.add_argument("--cpu-repeats", type=int, default=2)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -632,24 +753,49 @@ def main():
         breakdown[cls] = {"ms_per_step": round(per_call_ms, 3), "launches_per_step": nl // args.steps,
                           "TFLOP/s": round(flops / (per_call_ms * 1e-3) / 1e12, 2),
                           "GB/s": round(nbytes / (per_call_ms * 1e-3) / 1e9, 1)}
-    dom = max(breakdown, key=lambda c: breakdown[c]["ms_per_step"])
-    flops, nbytes = costs[dom]
-    t_dom = breakdown[dom]["ms_per_step"] * 1e-3
-    hbm_bound = nbytes / PEAK_HBM > flops / PEAK_FLOPS[args.precision]
-    if hbm_bound:
+    # single kernels: time from the nested HIP-event scopes, algorithmic flops
+    # and bytes per kernel, fraction of the MFMA (or vector) and HBM peaks
+    kcost = kernel_costs(tree.info, nocc, jb, args.precision)
+    ktime = kernel_times(prof)
+    pk = PEAK_FLOPS[args.precision]
+    kernels = {}
+    for k in KERNELS:
+        t_ms, nl = ktime[k]
+        if t_ms <= 0 or nl <= 0:
+            continue
+        flops, nbytes = kcost[k]
+        t = t_ms / args.steps * 1e-3
+        kernels[k] = {"ms_per_step": round(t * 1e3, 3), "launches_per_step": nl // args.steps,
+                      "alg_flops": flops, "alg_bytes": nbytes,
+                      "TFLOP/s": round(flops / t / 1e12, 2), "frac_flops_peak": round(flops / t / pk, 4),
+                      "GB/s": round(nbytes / t / 1e9, 1), "frac_hbm_peak": round(nbytes / t / PEAK_HBM, 4)}
+    # the roofline object: the kernel with the largest time per call
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    flops, nbytes = kd["alg_flops"], kd["alg_bytes"]
+    t_dom = kd["ms_per_step"] * 1e-3
+    nl_dom = kd["launches_per_step"]
+    if nbytes / PEAK_HBM > flops / pk:
         ach = nbytes / t_dom / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                 "frac": round(ach / (PEAK_HBM / 1e9), 4), "traffic": None, "kernel": dom}
     else:
         ach = flops / t_dom / 1e12
-        pk = PEAK_FLOPS[args.precision] / 1e12
-        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(pk, 1), "unit": "TFLOP/s",
-                "frac": round(ach / pk, 4), "traffic": None, "kernel": dom}
-    nl_dom = breakdown[dom]["launches_per_step"]
+        roof = {"bound": "mfma", "achieved": round(ach, 2), "peak": round(pk / 1e12, 1), "unit": "TFLOP/s",
+                "frac": round(ach * 1e12 / pk, 4), "traffic": None, "kernel": dom}
     roof["alg_bytes_per_launch"] = round(nbytes / max(1, nl_dom))
     roof["alg_flops_per_launch"] = round(flops / max(1, nl_dom))
+    roof["avg_launch_us"] = round(t_dom / max(1, nl_dom) * 1e6, 1)
     if args.precision == "fp64" and args.lmax == 2 and args.jblock in (0, 256):
         roof["traffic"] = measured_traffic(dom)   # HBM bytes per launch from the counter summary, if current
+    # the whole call's HBM bytes against the method's compulsory bytes
+    inf = tree.info
+    b_alg = 8 * (inf.ncomp * inf.npairs + 2 * inf.nbasis * nocc)
+    meas = measured_call_traffic() if (args.precision == "fp64" and args.lmax == 2 and args.jblock in (0, 256)) \
+        else None
+    hbm_call = {"alg_bytes": b_alg, "measured_bytes": meas,
+                "measured_over_alg": round(meas / b_alg, 1) if meas else None,
+                "note": "alg_bytes = 8 (Q sum_B pi_B + 2 nbasis nocc): AO multipoles once, C read, K written"}
     out = {
         "metric": "far-field K_ri GFLOP/s",
         "value": round(value, 1),
@@ -670,7 +816,9 @@ def main():
                    "pct_peak": round(100 * value * 1e9 / PEAK_FLOPS[args.precision], 2),
                    "tree_build_s": round(t_tree, 2), "wall_s_timed": round(wall, 3)},
         "roofline": roof,
+        "kernels": kernels,
         "breakdown": breakdown,
+        "hbm_call": hbm_call,
     }
     if args.precision == "fp64" and not args.no_mixed:
         # the mixed path on the same inputs: FP32 contractions and translations,
@@ -697,7 +845,7 @@ def main():
               flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, C, fl["total"], nocc, args.cpu_sample_j)
+        out["cpu_baseline"] = cpu_baseline(wl, C, fl["total"], nocc, args.cpu_sample_j, args.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 

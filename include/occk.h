@@ -352,7 +352,13 @@ enum {
   OCCK_K_REDUCE = 6,  /* sum of the per-leaf partials into K                    */
   OCCK_K_CONVERT = 7, /* operand conversion of the mixed-precision paths       */
   OCCK_K_SELECT = 8,  /* learned ranks: multipole norms, features, MLP         */
-  OCCK_K_NCLASS = 9
+  /* single kernels inside the classes above (their time also counts there) */
+  OCCK_K_HT = 9,          /* all-column half transform of the symmetric schedule, in HALF */
+  OCCK_K_UP_WALK = 10,    /* upward subtree walk, in UP                               */
+  OCCK_K_DOWN_WALK = 11,  /* downward subtree walk, in DOWN                           */
+  OCCK_K_L2P_DIRECT = 12, /* direct L2P GEMM, in L2P                                  */
+  OCCK_K_L2P_MIRROR = 13, /* mirrored L2P GEMM of the symmetric schedule, in L2P      */
+  OCCK_K_NCLASS = 14
 };
 
 /* While enabled, every occk_far_K on the handle records a HIP event pair on

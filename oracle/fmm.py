@@ -12,6 +12,10 @@ Steps, in the paper's order:
   6. K^ff_ri = 2 sum_X sum_j sum_lm O^{rj,X}_{lm} Mloc^{ij}_{lm}(X), Eq. (18) with the
      factor 2 of Eq. (5) and the sum over leaf boxes X made explicit.
 
+``far_J`` is the far-field Coulomb matrix through the same tree and
+translations, with one density-contracted column (the Coulomb passage of the
+Theory section, Eq. 10).
+
 Truncation: l <= L and l' <= L everywhere (the irregular harmonics are
 therefore needed to 2L).  Optional i and j ranges restrict the output
 columns and the summed occupied index.
@@ -25,6 +29,7 @@ re-centring of a degree-L polynomial, so both must agree to rounding.
 from __future__ import annotations
 
 import numpy as np
+from scipy import sparse
 
 from . import harmonics as H
 from .basis import Functions, ao_multipoles, function_pairs
@@ -72,10 +77,18 @@ def l2l_matrix(L: int, d: np.ndarray) -> np.ndarray:
     return T
 
 
-class Setup:
-    """Step 1: pairs, tree and the leaf AO multipoles (per geometry)."""
+def _leaf_multipoles(args):
+    fn, r, s, X, L, nquad = args
+    return ao_multipoles(fn, r, s, X, L, nquad)
 
-    def __init__(self, system, params, nquad: int | None = None):
+
+class Setup:
+    """Step 1: pairs, tree and the leaf AO multipoles (per geometry).
+
+    workers > 1 evaluates the leaves' multipole integrals in that many
+    processes; each leaf's integrals are the same computation either way."""
+
+    def __init__(self, system, params, nquad: int | None = None, workers: int = 1):
         self.system, self.params = system, params
         self.L = int(params.lmax)
         self.fn = Functions(system)
@@ -84,22 +97,43 @@ class Setup:
         t = self.tree
         self.nleaf = len(t.boxes[t.depth])
         self.leaf_pairs = [np.nonzero(t.pair_leaf == b)[0] for b in range(self.nleaf)]
-        self.leaf_funcs, self.leaf_O = [], []
-        Q = H.ncomp(self.L)
-        for b in range(self.nleaf):
+        jobs = [(self.fn, self.r[k], self.s[k], t.centre(t.depth, t.boxes[t.depth][b]), self.L, nquad)
+                for b, k in enumerate(self.leaf_pairs)]
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                mps = pool.map(_leaf_multipoles, jobs, chunksize=1)
+        else:
+            mps = map(_leaf_multipoles, jobs)
+        # per leaf: its sorted functions, the local (row, column) of each of
+        # its pairs and the pairs' multipoles (npairs_B, Q)
+        self.leaf_funcs, self.leaf_ra, self.leaf_sa, self.leaf_pm = [], [], [], []
+        for b, om in enumerate(mps):
             k = self.leaf_pairs[b]
             f = np.unique(np.concatenate([self.r[k], self.s[k]]))
-            loc = {int(v): n for n, v in enumerate(f)}
-            X = t.centre(t.depth, t.boxes[t.depth][b])
-            om = ao_multipoles(self.fn, self.r[k], self.s[k], X, self.L, nquad)
-            dense = np.zeros((len(f), len(f), Q), dtype=np.complex128)
-            a = np.searchsorted(f, self.r[k])
-            b = np.searchsorted(f, self.s[k])
-            np.add.at(dense, (a, b), om)
-            dense = np.ascontiguousarray(dense.transpose(2, 0, 1))
-            del loc
             self.leaf_funcs.append(f)
-            self.leaf_O.append(dense)
+            self.leaf_ra.append(np.searchsorted(f, self.r[k]))
+            self.leaf_sa.append(np.searchsorted(f, self.s[k]))
+            self.leaf_pm.append(om)
+
+    def dense_block(self, b: int) -> np.ndarray:
+        """O^{rs,X}_q of leaf b as a dense (Q, nb, nb) block over its functions
+        (zero where (r, s) is not one of the leaf's pairs)."""
+        nb = len(self.leaf_funcs[b])
+        dense = np.zeros((nb, nb, self.leaf_pm[b].shape[1]), dtype=np.complex128)
+        np.add.at(dense, (self.leaf_ra[b], self.leaf_sa[b]), self.leaf_pm[b])
+        return np.ascontiguousarray(dense.transpose(2, 0, 1))
+
+    def half(self, b: int, Cj: np.ndarray) -> np.ndarray:
+        """Eq. (15a) in leaf b: O^{rj}_q = sum_s O^{rs}_q C_sj, the s-sum running
+        over the pairs (r, s) assigned to b.  Cj: (nbasis, nj) -> (Q, nb, nj)."""
+        f = self.leaf_funcs[b]
+        om, ra, sa = self.leaf_pm[b], self.leaf_ra[b], self.leaf_sa[b]
+        CB = Cj[f]
+        out = np.empty((om.shape[1], len(f), Cj.shape[1]), dtype=np.complex128)
+        for q in range(om.shape[1]):
+            out[q] = sparse.csr_matrix((om[:, q], (ra, sa)), shape=(len(f), len(f))) @ CB
+        return out
 
     @property
     def nbasis(self) -> int:
@@ -120,20 +154,10 @@ def truncate(T: np.ndarray, p: int) -> np.ndarray:
     return out
 
 
-def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int = 64,
-          return_imag: bool = False, m2l_rank=None):
-    """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM.
-
-    m2l_rank: optional int p (0 <= p <= L) applied to every interaction-list
-    translation (l, l' <= p), the uniform version of a per-interaction rank."""
-    t, L = setup.tree, setup.L
-    nocc = C.shape[1]
-    i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
-    K = np.zeros((setup.nbasis, i1 - i0), dtype=np.complex128)
-    if t.lmin is None or j1 <= j0 or i1 <= i0:
-        return (K.real, 0.0) if return_imag else K.real
-    D = t.depth
-    # translation operators
+def _operators(setup: Setup, m2l_rank=None):
+    """Translation matrices of the tree: M2M (Eq. 11) and L2L (Eq. 13) per
+    child box, M2L (Eq. 12) per interaction-list pair, optionally truncated."""
+    t, L, D = setup.tree, setup.L, setup.tree.depth
     up = {}
     for lev in range(t.lmin + 1, D + 1):
         for b, c in enumerate(t.boxes[lev]):
@@ -150,15 +174,101 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
             for b2 in t.il[lev][b]:
                 T = m2l_matrix(L, t.centre(lev, c) - t.centre(lev, t.boxes[lev][b2]))
                 m2l[(lev, b, b2)] = T if m2l_rank is None else truncate(T, int(m2l_rank))
+    return up, down, m2l
+
+
+def far_J(setup: Setup, Dm: np.ndarray, return_imag: bool = False):
+    """Far-field Coulomb matrix J^ff_rs = sum_lm O^{rs,X}_lm Mloc_lm(X) (Theory
+    section, the Coulomb passage with Eq. 10), for the pairs (r, s) of every
+    leaf X; dense (nbasis, nbasis), zero outside the screened pairs.
+
+    Steps: density-contracted multipoles of each leaf,
+    O^X_lm = sum_{(t,u) in X} D_tu O^{tu,X}_lm; upward translations (Eq. 11);
+    interaction lists (Eq. 12, i.e. Eq. 10 summed hierarchically); downward
+    translations (Eq. 13); the contraction with each pair's multipoles."""
+    t = setup.tree
+    n = setup.nbasis
+    J = np.zeros((n, n), dtype=np.complex128)
+    if t.lmin is None:
+        return (J.real, 0.0) if return_imag else J.real
+    D = t.depth
+    up, down, m2l = _operators(setup)
+    Om = {D: [setup.leaf_pm[b].T @ Dm[setup.r[k], setup.s[k]] for b, k in enumerate(setup.leaf_pairs)]}
+    for lev in range(D - 1, t.lmin - 1, -1):
+        acc = [np.zeros_like(Om[D][0]) for _ in t.boxes[lev]]
+        for b in range(len(t.boxes[lev + 1])):
+            acc[t.parent(lev + 1, b)] += up[(lev + 1, b)] @ Om[lev + 1][b]
+        Om[lev] = acc
+    Ml = {}
+    for lev in range(t.lmin, D + 1):
+        cur = []
+        for b in range(len(t.boxes[lev])):
+            acc = np.zeros_like(Om[D][0])
+            for b2 in t.il[lev][b]:
+                acc += m2l[(lev, b, b2)] @ Om[lev][b2]
+            if lev > t.lmin:
+                acc += down[(lev, b)] @ Ml[lev - 1][t.parent(lev, b)]
+            cur.append(acc)
+        Ml[lev] = cur
+    for b, k in enumerate(setup.leaf_pairs):
+        J[setup.r[k], setup.s[k]] += setup.leaf_pm[b] @ Ml[D][b]
+    if return_imag:
+        return J.real, float(np.abs(J.imag).max())
+    return J.real
+
+
+def far_J_direct(setup: Setup, Dm: np.ndarray, nquad=None):
+    """The same truncated J^ff from ancestor-centred expansions, one M2L per
+    far leaf pair (no translations)."""
+    t, L = setup.tree, setup.L
+    n = setup.nbasis
+    J = np.zeros((n, n), dtype=np.complex128)
+    if t.lmin is None:
+        return J.real
+    cache = {}
+
+    def mult(leaf, lev):   # pair multipoles of a leaf about its level-lev ancestor's centre
+        if (leaf, lev) not in cache:
+            X = t.centre(lev, t.boxes[lev][t.ancestor(lev, leaf)])
+            k = setup.leaf_pairs[leaf]
+            cache[(leaf, lev)] = (ao_multipoles(setup.fn, setup.r[k], setup.s[k], X, L, nquad), X)
+        return cache[(leaf, lev)]
+
+    for b1 in range(setup.nleaf):
+        for b2 in range(setup.nleaf):
+            lev = t.far_level(b1, b2)
+            if lev is None:
+                continue
+            O1, X1 = mult(b1, lev)
+            O2, X2 = mult(b2, lev)
+            k1, k2 = setup.leaf_pairs[b1], setup.leaf_pairs[b2]
+            om = O2.T @ Dm[setup.r[k2], setup.s[k2]]
+            J[setup.r[k1], setup.s[k1]] += O1 @ (m2l_matrix(L, X1 - X2) @ om)
+    return J.real
+
+
+def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int = 64,
+          return_imag: bool = False, m2l_rank=None):
+    """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM.
+
+    m2l_rank: optional int p (0 <= p <= L) applied to every interaction-list
+    translation (l, l' <= p), the uniform version of a per-interaction rank."""
+    t, L = setup.tree, setup.L
+    nocc = C.shape[1]
+    i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
+    K = np.zeros((setup.nbasis, i1 - i0), dtype=np.complex128)
+    if t.lmin is None or j1 <= j0 or i1 <= i0:
+        return (K.real, 0.0) if return_imag else K.real
+    D = t.depth
+    up, down, m2l = _operators(setup, m2l_rank)
     for jb0 in range(j0, j1, jblock):
         jb1 = min(j1, jb0 + jblock)
         # Step 2: MO transforms at the leaves
         Hb, Om = [], {D: []}
         for b in range(setup.nleaf):
-            CB = C[setup.leaf_funcs[b]]
-            h = np.matmul(setup.leaf_O[b], CB[:, jb0:jb1])                      # O^{rj}_q = O^{rs}_q C_sj
+            h = setup.half(b, C[:, jb0:jb1])                                     # O^{rj}_q = O^{rs}_q C_sj
             Hb.append(h)
-            Om[D].append(np.matmul(CB[:, i0:i1].T, h))                           # O^{ij}_q = sum_r C_ri O^{rj}_q
+            Om[D].append(np.matmul(C[setup.leaf_funcs[b], i0:i1].T, h))          # O^{ij}_q = sum_r C_ri O^{rj}_q
         # Step 3: upward
         for lev in range(D - 1, t.lmin - 1, -1):
             acc = [np.zeros_like(Om[D][0]) for _ in t.boxes[lev]]

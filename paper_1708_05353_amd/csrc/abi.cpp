@@ -219,32 +219,35 @@ int32_t occk_tree_leaf(const occk_tree* tree, int32_t leaf, int32_t* nb, int32_t
   OCCK_GUARD_END
 }
 
-int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
-                   int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
-                   void* hip_stream) {
-  Tree* t = reinterpret_cast<Tree*>(tree);
+}  // extern "C"
+
+// Host-side checks of occk_far_K arguments; fills o.
+static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0,
+                           int32_t i1, int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
+                           occk_far_opts& o) {
+  const std::string f(fn);
   if (!live(t)) {
-    set_error("occk_far_K: handle is not live");
+    set_error(f + ": handle is not live");
     return OCCK_EHANDLE;
   }
   if (!C || !K) {
-    set_error("occk_far_K: C and K must be non-NULL device pointers");
+    set_error(f + ": C and K must be non-NULL device pointers");
     return OCCK_EINVAL;
   }
   if (nocc <= 0 || ldc < nocc) {
-    set_error("occk_far_K: need nocc > 0 and ldc >= nocc");
+    set_error(f + ": need nocc > 0 and ldc >= nocc");
     return OCCK_EINVAL;
   }
   if (!(0 <= i0 && i0 <= i1 && i1 <= nocc) || !(0 <= j0 && j0 <= j1 && j1 <= nocc)) {
-    set_error("occk_far_K: need 0 <= i0 <= i1 <= nocc and 0 <= j0 <= j1 <= nocc");
+    set_error(f + ": need 0 <= i0 <= i1 <= nocc and 0 <= j0 <= j1 <= nocc");
     return OCCK_EINVAL;
   }
   if (ldk < i1 || ldk <= 0) {
-    set_error("occk_far_K: need ldk >= i1");
+    set_error(f + ": need ldk >= i1");
     return OCCK_EINVAL;
   }
   if ((reinterpret_cast<uintptr_t>(C) | reinterpret_cast<uintptr_t>(K)) & 7) {
-    set_error("occk_far_K: C and K must be 8-byte aligned");
+    set_error(f + ": C and K must be 8-byte aligned");
     return OCCK_EINVAL;
   }
   {
@@ -253,28 +256,40 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
     const uintptr_t k0 = reinterpret_cast<uintptr_t>(K);
     const uintptr_t k1 = k0 + uintptr_t(t->nbasis) * uintptr_t(ldk) * 8;
     if (c0 < k1 && k0 < c1) {
-      set_error("occk_far_K: K overlaps C");
+      set_error(f + ": K overlaps C");
       return OCCK_EINVAL;
     }
   }
-  occk_far_opts o{};
+  o = occk_far_opts{};
   if (opts) o = *opts;
   if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X6) {
-    set_error("occk_far_K: unknown precision");
+    set_error(f + ": unknown precision");
     return OCCK_EINVAL;
   }
   if (o.rank_mode != OCCK_RANK_FIXED && o.rank_mode != OCCK_RANK_LEARNED) {
-    set_error("occk_far_K: unknown rank_mode");
+    set_error(f + ": unknown rank_mode");
     return OCCK_EINVAL;
   }
   if (o.rank_mode == OCCK_RANK_LEARNED && !sel_live(o.selector)) {
-    set_error("occk_far_K: LEARNED rank mode needs a live selector");
+    set_error(f + ": LEARNED rank mode needs a live selector");
     return OCCK_ESTATE;
   }
   if (o.jblock < 0) {
-    set_error("occk_far_K: jblock must be >= 0");
+    set_error(f + ": jblock must be >= 0");
     return OCCK_EINVAL;
   }
+  return OCCK_OK;
+}
+
+extern "C" {
+
+int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
+                   int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
+                   void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  occk_far_opts o{};
+  const int32_t rc = check_far_K("occk_far_K", t, C, ldc, nocc, i0, i1, j0, j1, opts, K, ldk, o);
+  if (rc != OCCK_OK) return rc;
   OCCK_GUARD_BEGIN
   return far_K(t, C, ldc, nocc, i0, i1, j0, j1, &o, K, ldk, hip_stream);
   OCCK_GUARD_END

@@ -28,29 +28,40 @@ template <class T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  bool own = true;   // false: a view into memory owned elsewhere (never freed here)
   // owns its allocation: freed on destruction, moved but never copied
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), own(o.own) {
     o.p = nullptr;
     o.n = 0;
+    o.own = true;
   }
   DevBuf& operator=(DevBuf&& o) noexcept {
     if (this != &o) {
       free();
       p = o.p;
       n = o.n;
+      own = o.own;
       o.p = nullptr;
       o.n = 0;
+      o.own = true;
     }
     return *this;
   }
   ~DevBuf() { free(); }
   void free() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
     p = nullptr;
     n = 0;
+    own = true;
+  }
+  void view(T* ptr, size_t count) {
+    free();
+    p = ptr;
+    n = count;
+    own = false;
   }
   void upload(const std::vector<T>& v) {
     free();
@@ -65,6 +76,32 @@ struct DevBuf {
     if (count == 0) return;
     HIP_OK(hipMalloc(&p, count * sizeof(T)));
     n = count;
+  }
+};
+
+// Places workspace buffers one after another (256-byte aligned) in a fixed
+// device region instead of allocating them; tables are copied in.  Throws
+// ScratchFull when the region is too small.
+struct ScratchFull : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+struct ScratchArena {
+  char* base = nullptr;
+  size_t cap = 0, off = 0;
+  template <class T>
+  void place(DevBuf<T>& b, size_t count) {
+    const size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (off + bytes > cap)
+      throw ScratchFull("the workspace needs more than the " + std::to_string(cap >> 20) +
+                        " MiB scratch region of the allocation-free entry point");
+    b.view(reinterpret_cast<T*>(base + off), count);
+    off += bytes;
+  }
+  template <class T>
+  void upload(DevBuf<T>& b, const std::vector<T>& v) {
+    place(b, v.size());
+    if (!v.empty()) HIP_OK(hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   }
 };
 
@@ -138,6 +175,7 @@ struct DeviceState {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<int> ev_class;
+  std::vector<size_t> ev_idx;       // first event of each recorded pair (scopes may nest)
   std::vector<int64_t> launches;
   // learned ranks
   DevBuf<float> box_norm;         // [nbox][L+1] multipole norms of the current batch
@@ -161,10 +199,20 @@ struct ProfScope {   // records a start/end event pair around a group of launche
     ds->ev_used += 2;
     HIP_OK(hipEventRecord(ds->ev_pool[idx], st));
   }
+  // records the end event now instead of at the end of the scope
+  void close() {
+    if (!ds) return;
+    end();
+    ds = nullptr;
+  }
   ~ProfScope() {
     if (!ds) return;
+    end();
+  }
+  void end() {
     (void)hipEventRecord(ds->ev_pool[idx + 1], st);
     ds->ev_class.push_back(cls);
+    ds->ev_idx.push_back(idx);
     if (ds->launches.size() < OCCK_K_NCLASS) ds->launches.assign(OCCK_K_NCLASS, 0);
     ds->launches[cls] += nlaunch;
   }
@@ -172,7 +220,8 @@ struct ProfScope {   // records a start/end event pair around a group of launche
 
 size_t device_cap();
 void upload_tree(Tree* t);
-void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym = false);
+// arena != nullptr: place every buffer and table in that region (no allocation)
+void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym = false, ScratchArena* arena = nullptr);
 // largest j batch width (<= 256) whose workspace fits min(cap/2, 32 GiB)
 int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym);
 void ensure_mixed_operands(Tree* t, hipStream_t st);

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <tuple>
 #include <string>
@@ -323,15 +324,24 @@ static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni
 // symmetric schedule (sym) in addition:
 //   ht     HT^B[q][i][t] = sum_s O^B_q[t, s] C[s, i0 + i]  for every column i
 //   l2pt   KB[r, jstart + j] += sum_q sum_(i >= koff) HT^B[q][i][r] Mloc^B[(q, j), i]
-void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
+void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* arena) {
   DeviceState* ds = t->dev;
-  if (ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec && ds->ws_sym == int(sym)) return;
+  if (!arena && ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec && ds->ws_sym == int(sym)) return;
   const int Q = t->Q, nl = t->nleaf();
   const size_t es = prec == OCCK_PREC_FP64 ? 8 : 4;
   const int64_t sum_nb = ds->f_off[nl];
   const int64_t ncol = int64_t(jb) * ni;
   const size_t need = workspace_need(sum_nb, Q, ds->nbox, jb, ni, es, sym);
-  if (need + ds->bytes > device_cap()) throw std::bad_alloc();
+  if (!arena && need + ds->bytes > device_cap()) throw std::bad_alloc();
+  // buffers and tables: allocated, or placed in the arena
+  auto alloc = [arena](auto& buf, size_t count) {
+    if (arena) arena->place(buf, count);
+    else buf.alloc(count);
+  };
+  auto upload = [arena](auto& buf, const auto& v) {
+    if (arena) arena->upload(buf, v);
+    else buf.upload(v);
+  };
   ++ds->ws_gen;
   ds->ws_jb = -1;   // invalid until every buffer and descriptor is in place
   ds->ws_ni = -1;
@@ -341,10 +351,10 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->HT.free();
   ds->data.free();
   ds->KB.free();
-  ds->H.alloc(size_t(sum_nb) * Q * jb * es);
-  ds->data.alloc(size_t(2) * ds->nbox * Q * size_t(ncol) * es);
-  ds->KB.alloc(size_t(sum_nb) * ni);
-  if (sym) ds->HT.alloc(size_t(sum_nb) * Q * ni * es);
+  alloc(ds->H, size_t(sum_nb) * Q * jb * es);
+  alloc(ds->data, size_t(2) * ds->nbox * Q * size_t(ncol) * es);
+  alloc(ds->KB, size_t(sum_nb) * ni);
+  if (sym) alloc(ds->HT, size_t(sum_nb) * Q * ni * es);
   const int64_t box_stride = int64_t(Q) * ncol;
   const char* Obase = prec == OCCK_PREC_FP64 ? reinterpret_cast<const char*>(ds->O.p)
                                              : reinterpret_cast<const char*>(ds->Of.p);
@@ -446,7 +456,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->t_l2pw.free();
   if (wide) {
     ds->l2pw_nt_start = chunked_tile_lists(tl2w, [](const GemmTile& x) { return std::make_tuple(x.prob, x.nt, x.mt); });
-    ds->t_l2pw.upload(tl2w);
+    upload(ds->t_l2pw, tl2w);
   }
   // l2pt: the j tiles sharing one HT panel adjacent
   auto by_leaf = [](const GemmTile& x, const GemmTile& y) {
@@ -454,12 +464,12 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   };
   std::stable_sort(tlt.begin(), tlt.end(), by_leaf);
   std::stable_sort(tltw.begin(), tltw.end(), by_leaf);
-  ds->d_half.upload(dh);
-  ds->t_half.upload(th);
-  ds->d_omega.upload(dom);
-  ds->t_omega.upload(tom);
-  ds->d_l2p.upload(dl);
-  ds->t_l2p.upload(tl2);
+  upload(ds->d_half, dh);
+  upload(ds->t_half, th);
+  upload(ds->d_omega, dom);
+  upload(ds->t_omega, tom);
+  upload(ds->d_l2p, dl);
+  upload(ds->t_l2p, tl2);
   ds->n_half = int(th.size());
   ds->n_omega = ds->omega_nt_start.size() > 1 ? ds->omega_nt_start[1] : 0;   // list 0: every tile
   ds->n_l2p = ds->l2p_nt_start.size() > 1 ? ds->l2p_nt_start[1] : 0;
@@ -470,14 +480,14 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym) {
   ds->t_l2ptw.free();
   ds->n_ht = ds->n_l2pt = ds->n_l2ptw = 0;
   if (sym) {
-    ds->d_ht.upload(dht);
-    ds->t_ht.upload(tht);
-    ds->d_l2pt.upload(dlt);
-    ds->t_l2pt.upload(tlt);
+    upload(ds->d_ht, dht);
+    upload(ds->t_ht, tht);
+    upload(ds->d_l2pt, dlt);
+    upload(ds->t_l2pt, tlt);
     ds->n_ht = int(tht.size());
     ds->n_l2pt = int(tlt.size());
     if (wide) {   // a whole leaf per tile: each Mloc panel is read once
-      ds->t_l2ptw.upload(tltw);
+      upload(ds->t_l2ptw, tltw);
       ds->n_l2ptw = int(tltw.size());
     }
   }
@@ -668,6 +678,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   const int nblk = (nj + jb - 1) / jb;
   if (sym) {   // HT for every column, once per call
     ProfScope ps(ds, prof, OCCK_K_HALF, st);
+    ProfScope ps_ht(ds, prof, OCCK_K_HT, st);
     GemmRun r{};
     r.boff = i0;
     r.blim = i1;
@@ -711,6 +722,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       // ds->up holds levels D-1 down to lmin; the walk covers those at or below its root level
       size_t k0 = 0;
       if (ds->upw_nroots > 0) {
+        ProfScope ps_w(ds, prof, OCCK_K_UP_WALK, st);
         launch_walk<T>(t, ds->upw_ptr.p, ds->upw_prog.p, ds->upw_nroots, ds->upw_nlv, true, data, box_stride, cm,
                        ops, st);
         k0 = size_t(t->params.depth - ds->upw_lroot);
@@ -729,15 +741,18 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(k1) + (walk ? 1 : 0));
       for (size_t k = 0; k < k1; ++k)
         launch_translate<T>(t, ds->down[k], data, box_stride, cm, ops, st, sel ? ds->down[k].rank.p : nullptr);
-      if (walk)
+      if (walk) {
+        ProfScope ps_w(ds, prof, OCCK_K_DOWN_WALK, st);
         launch_walk<T>(t, ds->dnw_ptr.p, ds->dnw_prog.p, ds->dnw_nroots, ds->dnw_nlv, false, data, box_stride, cm,
                        ops, st);
+      }
     }
     {
       ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < ni ? 2 : 1);
       GemmRun r{};
       r.accumulate = kb > 0 ? 1 : 0;
       r.nlo = int(istart);
+      ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, st);
       if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
         r.tile0 = ds->l2pw_nt_start[size_t(ct0 / 4)];
         r.ntiles = ds->l2pw_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
@@ -749,7 +764,9 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
         hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
                            ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       }
+      ps_d.close();
       if (sym && jrel + jb < ni) {
+        ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, st);
         GemmRun m{};
         m.accumulate = 1;
         m.koff = jrel + jb;
@@ -950,9 +967,10 @@ int32_t profile_read(Tree* t, double* ms, int64_t* launches) {
   if (!ds) return OCCK_OK;
   try {
     for (size_t k = 0; k < ds->ev_class.size(); ++k) {
-      HIP_OK(hipEventSynchronize(ds->ev_pool[2 * k + 1]));
+      const size_t i = ds->ev_idx[k];
+      HIP_OK(hipEventSynchronize(ds->ev_pool[i + 1]));
       float e = 0.f;
-      HIP_OK(hipEventElapsedTime(&e, ds->ev_pool[2 * k], ds->ev_pool[2 * k + 1]));
+      HIP_OK(hipEventElapsedTime(&e, ds->ev_pool[i], ds->ev_pool[i + 1]));
       if (ms) ms[ds->ev_class[k]] += double(e);
     }
     if (launches && !ds->launches.empty())
@@ -962,6 +980,7 @@ int32_t profile_read(Tree* t, double* ms, int64_t* launches) {
     return OCCK_EHIP;
   }
   ds->ev_class.clear();
+  ds->ev_idx.clear();
   ds->ev_used = 0;
   ds->launches.assign(OCCK_K_NCLASS, 0);
   return OCCK_OK;

@@ -103,7 +103,8 @@ EXPORTS = {
     "occk_profile_read": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
 }
 
-KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert", "select"]
+KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert", "select",
+                  "ht", "up_walk", "down_walk", "l2p_direct", "l2p_mirror"]
 NFEAT, NOUT, NPARAM = 24, 8, 6280
 
 _lib = None

@@ -1,7 +1,8 @@
-"""Host logic of bench.py that turns profiles into per-class figures: the
-kernel classes of one call's dispatch sequence (tree walks and level
-passes), and the algorithmic bytes of the walks against the level-by-level
-passes."""
+"""Host logic of bench.py that turns profiles into per-kernel figures: the
+kernel of every dispatch of one call (all-column half transform, tree walks
+and level passes, direct and mirrored L2P), the algorithmic bytes of the
+walks against the level-by-level passes, and the per-kernel cost model
+against the per-class one."""
 from types import SimpleNamespace
 
 import pytest
@@ -11,14 +12,15 @@ import bench
 
 def _info(depth, lmin, ncomp=9, nb=None, il=4):
     nb = nb or [2 ** l for l in range(depth + 1)]
+    ilp = [il * nb[l] if l >= lmin else 0 for l in range(depth + 1)]
     return SimpleNamespace(depth=depth, lmin=lmin, ncomp=ncomp, boxes_per_level=nb, m2m_nnz=36,
                            sum_nb=1000, sum_nb2=100000, nleaf=nb[depth], npairs=5000, n_edges=sum(nb[lmin + 1:]),
-                           n_il=il * sum(nb[lmin:]), nbasis=800)
+                           n_il=il * sum(nb[lmin:]), il_per_level=ilp, nbasis=800)
 
 
 def _call(depth, lmin, nbatch):
     lr_up, lr_dn = bench.walk_roots(_info(depth, lmin))
-    seq = ["occk::opgen_kernel"]
+    seq = ["occk::opgen_kernel", "occk::half_kernel<0>"]      # the all-column half transform first
     for _ in range(nbatch):
         seq += ["occk::half_kernel<0>", "occk::omega_kernel<0>", "occk::up_walk_kernel<double, 9, 6>"]
         seq += ["occk::translate_vec_kernel<double, 9, 1>"] * (lr_up - lmin)
@@ -35,9 +37,9 @@ def test_classes_of_walks_and_level_passes(depth, lmin):
     names = {0: "occk::opgen_kernel", **_call(depth, lmin, 3)}   # an earlier call's dispatch is ignored
     cls = bench._classify_last_call(names, info)
     got = [cls[i] for i in sorted(cls)]
-    per_batch = (["half", "omega", "up"] + ["up"] * (lr_up - lmin) + ["down"] * (lr_dn - lmin)
-                 + ["down", "l2p", "l2p"])
-    assert got == ["opgen"] + per_batch * 3 + ["reduce"]
+    per_batch = (["half", "omega", "up_walk"] + ["up_pass"] * (lr_up - lmin) + ["down_pass"] * (lr_dn - lmin)
+                 + ["down_walk", "l2p_direct", "l2p_mirror"])
+    assert got == ["opgen", "ht"] + per_batch * 3 + ["reduce"]
 
 
 def test_walk_launch_count_mismatch_is_an_error():
@@ -68,11 +70,32 @@ def test_walk_roots_and_bytes():
 
 def test_classes_of_level_passes_only():
     info = _info(4, 2, il=40)
-    seq = ["occk::opgen_kernel"]
+    seq = ["occk::opgen_kernel", "occk::half_kernel<0>"]
     for _ in range(2):
         seq += ["occk::half_kernel<0>", "occk::omega_kernel<0>"]
         seq += ["occk::translate_vec_kernel<double, 9, 1>"] * 5   # 2 upward, 3 downward levels
         seq += ["occk::l2p_kernel<0>", "occk::l2pt_kernel<0>"]
     cls = bench._classify_last_call({i + 1: k for i, k in enumerate(seq)}, info)
-    per_batch = ["half", "omega", "up", "up", "down", "down", "down", "l2p", "l2p"]
-    assert [cls[i] for i in sorted(cls)] == ["opgen"] + per_batch * 2
+    per_batch = ["half", "omega", "up_pass", "up_pass", "down_pass", "down_pass", "down_pass", "l2p_direct",
+                 "l2p_mirror"]
+    assert [cls[i] for i in sorted(cls)] == ["opgen", "ht"] + per_batch * 2
+
+
+@pytest.mark.parametrize("il", [4, 40])
+def test_kernel_costs_add_up_to_the_class_costs(il):
+    """Walk + level-pass and direct + mirrored figures add up to the class
+    figures; the translation flops to the method's F_M2M, F_M2L + F_L2L; the
+    two L2P kernels to F_L2P = 2 Q n^2 sum_B n_B."""
+    info = _info(8, 2, il=il)
+    n, jb = 100, 32
+    k = bench.kernel_costs(info, n, jb, "fp64")
+    c = bench.class_costs(info, n, jb, "fp64")
+    add = lambda a, b, i: k[a][i] + k[b][i]
+    assert add("up_walk", "up_pass", 0) == c["up"][0]
+    assert add("down_walk", "down_pass", 0) == c["down"][0]
+    assert add("l2p_direct", "l2p_mirror", 0) == c["l2p"][0] == 2 * 9 * n * n * info.sum_nb
+    for a, b, cl in (("up_walk", "up_pass", "up"), ("down_walk", "down_pass", "down"),
+                     ("l2p_direct", "l2p_mirror", "l2p"), ("ht", "half", "half")):
+        assert add(a, b, 1) == c[cl][1], cl
+    assert k["omega"] == c["omega"]
+    assert k["ht"][0] == k["half"][0] == c["half"][0]

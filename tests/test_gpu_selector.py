@@ -178,12 +178,12 @@ def test_trained_selector_gain(occk):
     sel = occk.Selector(seed=11)
     sel.train(X, T, epochs=25, batch=512, lr=2e-3, seed=2)
 
-    def run(tr, C, wl, s):
+    def run(tr, C, wl, s, jr=(0, 16)):
         n = C.shape[1]
         Kf = torch.zeros((wl.system.nbasis, n), dtype=torch.float64, device="cuda")
-        occk.far_K(tr, C, Kf, j_range=(0, 16))
+        occk.far_K(tr, C, Kf, j_range=jr)
         Kl = torch.zeros_like(Kf)
-        occk.far_K(tr, C, Kl, j_range=(0, 16), selector=s)
+        occk.far_K(tr, C, Kl, j_range=jr, selector=s)
         torch.cuda.synchronize()
         return rel(Kl.cpu().numpy(), Kf.cpu().numpy()), _work_fraction(tr.rank_stats())
 
@@ -224,5 +224,14 @@ def test_trained_selector_gain(occk):
     print(f"untrained: err {erru:.3e} M2L work fraction {fracu:.3f}")
     assert erru > 1e-6 or fracu > frac
     tr.free()
-    sel.free()
     untrained.free()
+    # the full 644-site globule (nbasis 6187, nocc 1261), all i, j in [0, 64)
+    wl = workloads.protein_blob()
+    C = torch.from_numpy(wl.orbitals()).cuda()
+    tr = occk.Tree(wl.system, wl.params)
+    print("[selector] full globule, j in [0, 64)", flush=True)
+    errf, fracf = run(tr, C, wl, sel, jr=(0, 64))
+    print(f"full globule: learned vs fixed L = 8 err {errf:.3e} M2L work fraction {fracf:.3f}", flush=True)
+    assert errf <= 1e-6
+    tr.free()
+    sel.free()

@@ -27,6 +27,14 @@ def _launches(wl, jblock):
     tr.profile(False)
     tr.free()
     nbatch = -(-C.shape[1] // jblock)
+    # single-kernel scopes nested in their classes: one walk per batch when
+    # walks run, one direct L2P per batch, and their times within the class
+    walks = prof["up_walk"][1] > 0
+    assert prof["up_walk"][1] == prof["down_walk"][1] == (nbatch if walks else 0)
+    assert prof["l2p_direct"][1] == nbatch and prof["ht"][1] == 1
+    for sub, cls in (("up_walk", "up"), ("down_walk", "down"), ("l2p_direct", "l2p"), ("l2p_mirror", "l2p"),
+                     ("ht", "half")):
+        assert prof[sub][0] <= prof[cls][0] * 1.0001 + 1e-3, (sub, prof[sub], prof[cls])
     return info, prof["up"][1] // nbatch, prof["down"][1] // nbatch, prof["up"][1] % nbatch
 
 

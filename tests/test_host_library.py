@@ -64,7 +64,7 @@ def test_tree_and_multipoles_match_oracle(case):
     for b in range(tr.info.nleaf):
         f, O = tr.leaf(b)
         assert np.array_equal(f, st.leaf_funcs[b])
-        Or = _real_form(st.leaf_O[b], L)
+        Or = _real_form(st.dense_block(b), L)
         assert np.abs(O - Or).max() <= 1e-12 * max(np.abs(Or).max(), 1e-300)
 
 

@@ -65,3 +65,31 @@ def test_truncation_keeping_p_squared_components_is_caught(tiny, monkeypatch):
     monkeypatch.setattr(fmm, "truncate", short)
     bad = rel(fmm.far_K(st3, C, m2l_rank=2), fmm.far_K(st2, C))
     assert good < 1e-13 and bad > 1e-3
+
+
+def test_coulomb_missing_parity_is_caught(tiny, monkeypatch):
+    """(-1)^l dropped from the M2L operator: J^ff no longer converges to the
+    point-charge far field."""
+    from oracle.exact import far_J_exact_s
+    wl, C, st = tiny
+    Dm = 2.0 * C @ C.T
+    Jp = far_J_exact_s(st, Dm, "pc")
+    good = rel(fmm.far_J(st, Dm), Jp)
+    orig = fmm.m2l_matrix
+
+    def no_parity(L, R):
+        T = orig(L, R)
+        for l in range(L + 1):
+            T[l * l:(l + 1) * (l + 1)] *= (-1) ** l
+        return T
+    monkeypatch.setattr(fmm, "m2l_matrix", no_parity)
+    bad = rel(fmm.far_J(st, Dm), Jp)
+    assert good < 2e-2 and bad > 10 * good
+
+
+def test_coulomb_transposed_m2m_is_caught(tiny, monkeypatch):
+    wl, C, st = tiny
+    Dm = 2.0 * C @ C.T
+    orig = fmm.m2m_matrix
+    monkeypatch.setattr(fmm, "m2m_matrix", lambda L, d: orig(L, d).T.copy())
+    assert rel(fmm.far_J(st, Dm), fmm.far_J_direct(st, Dm)) > 1e-3
