@@ -70,7 +70,8 @@ typedef struct occk_system {
  *   depth       number of subdivisions (2^depth boxes per split dimension), 1..12
  *   ws          two boxes of one level are near iff the Chebyshev distance of
  *               their integer indices is <= ws (0..4)
- *   lmax        multipole rank L (0..8); l <= L and l' <= L
+ *   lmax        multipole rank L (0..15); l <= L and l' <= L.  The exchange
+ *               entry points take L <= 8; occk_far_J takes any rank
  *   pair_log_thresh  keep an ordered shell pair iff (ab/(a+b))|A-B|^2 <= thresh
  *               (+inf keeps every pair)
  * Root box: over the split dimensions E = largest extent of the pair centres,
@@ -202,6 +203,39 @@ int32_t occk_tree_leaf(const occk_tree* tree, int32_t leaf, int32_t* nb, int32_t
 int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
                    int32_t i0, int32_t i1, int32_t j0, int32_t j1,
                    const occk_far_opts* opts, double* K, int64_t ldk, void* hip_stream);
+
+/* Far-field Coulomb matrix on the GPU, through the same tree (Theory section:
+ * the Coulomb passage with Eq. 10 and the J^ff formula after it):
+ *   O^B_lm    = sum over the pairs (t,u) of leaf B of D_tu O^{tu,B}_lm
+ *   Mloc_lm(X) = (-1)^l sum_far sum M_{l+l',m+m'}(X - X') O^{X'}_{l'm'}, by
+ *               upward (Eq. 11), interaction-list (Eq. 12) and downward
+ *               (Eq. 13) translations of that single column
+ *   J[r, s]   = sum_lm O^{rs,X}_lm Mloc_lm(X) for every screened pair (r,s)
+ *               of every leaf X (the pair's own leaf)
+ * at the tree's rank L (the paper's L^J = 10 for Coulomb; trees of any rank
+ * up to 15).  FP64 throughout.
+ * D: device, row-major nbasis x ldd FP64, the density matrix (only the
+ *    entries D[t, u] of screened pairs are read); ldd >= nbasis.
+ * J: device, row-major nbasis x ldj FP64; accumulate = 0: J = J^ff with zeros
+ *    outside the screened pairs; accumulate = 1: J[r, s] += J^ff_rs at the
+ *    screened pairs only.  J must not overlap D.
+ * Asynchronous on hip_stream; the first call on a handle uploads the pair
+ * multipoles and the tables (synchronous).  Errors: EINVAL, EHANDLE, ENOMEM
+ * (beyond OCCK_MAX_DEVICE_BYTES, checked before any HIP call), EHIP. */
+int32_t occk_far_J(occk_tree* tree, const double* D, int64_t ldd, double* J, int64_t ldj,
+                   int32_t accumulate, void* hip_stream);
+
+/* Algorithmic flop model of one occk_far_J call (host only), Q = (L+1)^2:
+ *   dens  2 Q npairs     density-contracted leaf multipoles
+ *   m2m   2 z E          upward (z = m2m_nnz, E = n_edges)
+ *   m2l   2 Q^2 n_il     interaction lists
+ *   l2l   2 z E          downward
+ *   pair  2 Q npairs     J_rs from the leaf's local expansion
+ * A tree with no far field gives zeros. */
+typedef struct occk_jflops_t {
+  int64_t dens, m2m, m2l, l2l, pair, total;
+} occk_jflops_t;
+int32_t occk_tree_flops_J(const occk_tree* tree, occk_jflops_t* out);
 
 /* Workspace of the handle's last occk_far_K: the j batch width used (-1
  * before the first call) and the device bytes held by the handle.  Either

@@ -96,6 +96,7 @@ int32_t occk_free_tree(occk_tree* tree) {
     g_live.erase(t);
   }
   device_free(t);
+  jstate_free(t);
   t->magic = 0;
   delete t;
   return OCCK_OK;
@@ -260,6 +261,10 @@ static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc
       return OCCK_EINVAL;
     }
   }
+  if (t->L > kMaxL) {
+    set_error(f + ": the exchange kernels take lmax <= 8 (the tree has a higher rank, for occk_far_J)");
+    return OCCK_EINVAL;
+  }
   o = occk_far_opts{};
   if (opts) o = *opts;
   if (o.precision < OCCK_PREC_FP64 || o.precision > OCCK_PREC_BF16X6) {
@@ -293,6 +298,63 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
   OCCK_GUARD_BEGIN
   return far_K(t, C, ldc, nocc, i0, i1, j0, j1, &o, K, ldk, hip_stream);
   OCCK_GUARD_END
+}
+
+int32_t occk_far_J(occk_tree* tree, const double* D, int64_t ldd, double* J, int64_t ldj, int32_t accumulate,
+                   void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_far_J: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  const int64_t n = t->nbasis;
+  if (!D || !J || ldd < n || ldj < n || (accumulate != 0 && accumulate != 1)) {
+    set_error("occk_far_J: D and J must be non-NULL, ldd and ldj >= nbasis, accumulate 0 or 1");
+    return OCCK_EINVAL;
+  }
+  if ((reinterpret_cast<uintptr_t>(D) | reinterpret_cast<uintptr_t>(J)) & 7) {
+    set_error("occk_far_J: D and J must be 8-byte aligned");
+    return OCCK_EINVAL;
+  }
+  {
+    const uintptr_t d0 = reinterpret_cast<uintptr_t>(D), d1 = d0 + uintptr_t(n) * uintptr_t(ldd) * 8;
+    const uintptr_t j0 = reinterpret_cast<uintptr_t>(J), j1 = j0 + uintptr_t(n) * uintptr_t(ldj) * 8;
+    if (d0 < j1 && j0 < d1) {
+      set_error("occk_far_J: J overlaps D");
+      return OCCK_EINVAL;
+    }
+  }
+  OCCK_GUARD_BEGIN
+  return far_J(t, D, ldd, J, ldj, accumulate, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_tree_flops_J(const occk_tree* tree, occk_jflops_t* out) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_flops_J: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!out) {
+    set_error("occk_tree_flops_J: out is NULL");
+    return OCCK_EINVAL;
+  }
+  std::memset(out, 0, sizeof(*out));
+  if (t->lmin < 0) return OCCK_OK;
+  const int D = t->params.depth;
+  int64_t n_il = 0, n_edges = 0;
+  for (int lev = 0; lev <= D; ++lev) {
+    n_il += int64_t(t->il_idx[lev].size());
+    if (lev > t->lmin) n_edges += int64_t(t->boxes[lev].size());
+  }
+  const int64_t Q = t->Q, np = int64_t(t->pairs.size());
+  out->dens = 2 * Q * np;
+  out->m2m = 2 * t->m2m_nnz * n_edges;
+  out->m2l = 2 * Q * Q * n_il;
+  out->l2l = out->m2m;
+  out->pair = 2 * Q * np;
+  out->total = out->dens + out->m2m + out->m2l + out->l2l + out->pair;
+  return OCCK_OK;
 }
 
 int32_t occk_debug_mfma_probe(int32_t kind, int32_t ia, int32_t ka, int32_t jb, double* host_out) {
@@ -384,6 +446,10 @@ int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* 
       }
     if (t->lmin < 0) {
       set_error("occk_batch_create: a system has no far field");
+      return OCCK_EINVAL;
+    }
+    if (t->L > kMaxL) {
+      set_error("occk_batch_create: the exchange kernels take lmax <= 8");
       return OCCK_EINVAL;
     }
     if (t->L != reinterpret_cast<Tree*>(trees[0])->L) {
@@ -668,8 +734,8 @@ int32_t occk_selector_collect(occk_tree* tree, const double* C, int64_t ldc, int
     set_error("occk_selector_collect: bad arguments");
     return OCCK_EINVAL;
   }
-  if (t->lmin < 0) {
-    set_error("occk_selector_collect: the tree has no far field");
+  if (t->lmin < 0 || t->L > kMaxL) {
+    set_error("occk_selector_collect: the tree has no far field or a rank above 8");
     return OCCK_EINVAL;
   }
   OCCK_GUARD_BEGIN

@@ -197,7 +197,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           for (int64_t lb = tk.b; lb < e1; ++lb) {
             if constexpr (QV > 0)
               translate_vec_tile<T, QV, kVecCols, false>(static_cast<T*>(S.data), S.box_stride, cm, S.KS, P.tgt_box,
-                                                  P.src_ptr, P.src_box, P.src_op, ops, int(lb % P.ntgt), lb / P.ntgt);
+                                                  P.src_ptr, P.src_box, P.src_op, S.ops, int(lb % P.ntgt), lb / P.ntgt);
             else
               translate_tile<T, MT, (sizeof(BatchSmem<MODE>) >= sizeof(T) * MT * 4 * MT * 64)>(
                   static_cast<T*>(S.data), S.box_stride, cm, S.Q, S.KS, P.tgt_box, P.src_ptr, P.src_box, P.src_op,

@@ -21,7 +21,6 @@
 #include <cmath>
 #include <cstdlib>
 #include <functional>
-#include <mutex>
 #include <stdexcept>
 #include <tuple>
 #include <string>
@@ -502,14 +501,15 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
                       hipStream_t st, const int8_t* src_rank) {
   const int Q = t->Q, KS = ksteps_of(Q);
   if (cm.nvalid <= 0 || ps.ntgt == 0) return;
-  if (Q <= 9 && !src_rank) {
+  if (Q <= 9 && !src_rank) {   // vector ALU, FP64 operators and accumulators in every mode
+    const double* ops64 = t->dev->ops.p;
     constexpr int NC = 1;   // columns per thread
     const int64_t nblocks = ((cm.nvalid + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
     const int64_t grid = ((nblocks + 7) / 8) * 8;
     if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
 #define OCCK_TV(QQ)                                                                                            \
   hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NC>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
-                     cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks)
+                     cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops64, ps.ntgt, nblocks)
     switch (Q) {
       case 1: OCCK_TV(1); break;
       case 4: OCCK_TV(4); break;

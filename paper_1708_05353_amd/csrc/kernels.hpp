@@ -851,7 +851,7 @@ template <class T, int Q, int NC, bool PIPE = true>
 __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int KS,
                                    const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                    const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
-                                   const T* __restrict__ ops, int t, int64_t ct) {
+                                   const double* __restrict__ ops, int t, int64_t ct) {
   static_assert(Q <= 16, "one operator row tile");
   const int64_t v0 = ct * (256 * NC) + threadIdx.x;
   const int64_t ncol = cm.ncol;
@@ -861,9 +861,12 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
     ok[c] = v0 + c * 256 < cm.nvalid;
     col[c] = ok[c] ? carried_col(cm, v0 + c * 256) : 0;
   }
-  T acc[NC][Q];
+  // FP64 operators and accumulators in every mode: a target sums up to a few
+  // hundred terms per component (3-D interaction lists), which FP32 sums
+  // would round to ~1e-6; the products cost the same on the vector ALU
+  double acc[NC][Q];
   for (int c = 0; c < NC; ++c)
-    for (int i = 0; i < Q; ++i) acc[c][i] = T(0);
+    for (int i = 0; i < Q; ++i) acc[c][i] = 0.0;
   const int64_t opsz = int64_t(KS) * 64;
   const cst<int32_t>* sbox = as_const(src_box);
   const cst<int32_t>* sop = as_const(src_op);
@@ -880,11 +883,14 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
       for (int k = 0; k < Q; ++k) x[c][k] = X[int64_t(k) * ncol + col[c]];
   };
   auto apply = [&](const T (&x)[NC][Q], int e) {
-    const cst<T>* A = as_const(ops) + int64_t(sop[e]) * opsz;
+    const cst<double>* A = as_const(ops) + int64_t(sop[e]) * opsz;
+    double xd[NC][Q];
+    for (int c = 0; c < NC; ++c)
+      for (int k = 0; k < Q; ++k) xd[c][k] = double(x[c][k]);
     for (int i = 0; i < Q; ++i)
       for (int k = 0; k < Q; ++k) {
-        const T a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
-        for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, x[c][k], acc[c][i]);
+        const double a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
+        for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, xd[c][k], acc[c][i]);
       }
   };
   if constexpr (PIPE) {
@@ -905,7 +911,7 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
   gbl<T>* Y = as_global(data) + int64_t(as_const(tgt_box)[t]) * box_stride;
   for (int c = 0; c < NC; ++c)
     if (ok[c])
-      for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col[c], acc[c][i]);
+      for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col[c], T(acc[c][i]));
 }
 
 template <class T, int Q, int NC>
@@ -914,7 +920,7 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
                                                             const int32_t* __restrict__ src_ptr,
                                                             const int32_t* __restrict__ src_box,
                                                             const int32_t* __restrict__ src_op,
-                                                            const T* __restrict__ ops, int ntgt, int64_t nblocks) {
+                                                            const double* __restrict__ ops, int ntgt, int64_t nblocks) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
@@ -961,6 +967,8 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
   const gbl<const T>* base = as_global(static_cast<const T*>(data));
   const cst<WalkStep>* pg = as_const(prog);
   const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
+  // the walks run on chain-like trees, whose interaction lists are short:
+  // the accumulators take few terms, and the mode's precision is kept
   T acc[NLV][Q];
 #pragma unroll
   for (int l = 0; l < NLV; ++l)
@@ -1039,6 +1047,8 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
   const gbl<const T>* base = as_global(static_cast<const T*>(data));
   const cst<WalkStep>* pg = as_const(prog);
   const int p0 = as_const(prog_ptr)[root], p1 = as_const(prog_ptr)[root + 1];
+  // the walks run on chain-like trees, whose interaction lists are short:
+  // the accumulators take few terms, and the mode's precision is kept
   T acc[NLV][Q];
 #pragma unroll
   for (int l = 0; l < NLV; ++l)

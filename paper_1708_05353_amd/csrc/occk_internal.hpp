@@ -11,7 +11,8 @@
 namespace occk {
 
 constexpr uint32_t kTreeMagic = 0x6f63636bu;  // "occk"
-constexpr int kMaxL = 8;
+constexpr int kMaxL = 8;        // multipole rank of the exchange kernels
+constexpr int kMaxLTree = 15;   // multipole rank of a tree (the Coulomb path takes up to 15)
 
 void set_error(const std::string& msg);
 
@@ -38,6 +39,7 @@ struct OpDesc {
 };
 
 struct DeviceState;   // defined in the HIP translation unit
+struct JState;        // device state of the Coulomb path (far_j.hip)
 
 struct Tree {
   uint32_t magic = kTreeMagic;
@@ -64,6 +66,7 @@ struct Tree {
   int64_t m2m_nnz = 0;
 
   DeviceState* dev = nullptr;
+  JState* jdev = nullptr;     // device state of the Coulomb path (far_j.hip)
   int profile = 0;
 
   double h(int level) const { return W / double(int64_t(1) << level); }
@@ -84,6 +87,8 @@ inline int rqim(int l, int m) { return l * l + 2 * m; }
 
 // Dense real-form AO multipole block of one leaf (Q x nb x nb), FP64, host.
 void leaf_multipoles(const Tree& t, int leaf, double* out);
+// Real-form AO multipoles of the leaf's pairs, [pair][q] in leaf_pairs order, FP64, host.
+void leaf_pair_multipoles(const Tree& t, int leaf, double* out);
 
 // Builds everything host-side; throws std::runtime_error / std::bad_alloc.
 Tree* build_tree(const occk_system* sys, const occk_tree_params* p);
@@ -93,6 +98,8 @@ void device_free(Tree* t);
 int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
               int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
               void* stream);
+void jstate_free(Tree* t);
+int32_t far_J(Tree* t, const double* D, int64_t ldd, double* J, int64_t ldj, int32_t accumulate, void* stream);
 int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);
 int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);
 int32_t profile_read(Tree* t, double* ms, int64_t* launches);

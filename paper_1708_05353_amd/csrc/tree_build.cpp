@@ -152,7 +152,7 @@ static void pair_multipole(const Tree& t, const Pair& pr, const double X[3], dou
     return (mp & 1) ? -v : v;
   };
   double dv[3] = {pr.P[0] - X[0], pr.P[1] - X[1], pr.P[2] - X[2]};
-  cplx Od[(kMaxL + 1) * (kMaxL + 2) / 2];
+  cplx Od[(kMaxLTree + 1) * (kMaxLTree + 2) / 2];
   regular_cplx(L, dv, Od);
   auto Oget = [&](int l, int m) -> cplx {
     if (m >= 0) return Od[l * (l + 1) / 2 + m];
@@ -191,6 +191,14 @@ void leaf_multipoles(const Tree& t, int leaf, double* out) {
   }
 }
 
+void leaf_pair_multipoles(const Tree& t, int leaf, double* out) {
+  const int Q = t.Q;
+  double X[3];
+  t.centre(t.params.depth, t.boxes[t.params.depth][leaf], X);
+  size_t k = 0;
+  for (int32_t pi : t.leaf_pairs[leaf]) pair_multipole(t, t.pairs[pi], X, out + (k++) * size_t(Q));
+}
+
 // --------------------------------------------------------------------------
 // tree construction
 // --------------------------------------------------------------------------
@@ -204,7 +212,7 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
   if ((p->split_mask & 7) == 0 || (p->split_mask & ~7)) fail("split_mask must be a non-empty subset of {x,y,z}");
   if (p->depth < 1 || p->depth > 12) fail("depth must be in [1, 12]");
   if (p->ws < 0 || p->ws > 4) fail("ws must be in [0, 4]");
-  if (p->lmax < 0 || p->lmax > kMaxL) fail("lmax must be in [0, 8]");
+  if (p->lmax < 0 || p->lmax > kMaxLTree) fail("lmax must be in [0, 15]");
   if (std::isnan(p->pair_log_thresh) || p->pair_log_thresh <= 0) fail("pair_log_thresh must be > 0");
   for (int a = 0; a < 3 * sys->natoms; ++a)
     if (!std::isfinite(sys->xyz[a])) fail("non-finite coordinate");

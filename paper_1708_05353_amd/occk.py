@@ -50,6 +50,10 @@ class _Flops(ct.Structure):
     _fields_ = [(k, ct.c_int64) for k in ("half", "omega", "m2m", "m2l", "l2l", "l2p", "total")]
 
 
+class _JFlops(ct.Structure):
+    _fields_ = [(k, ct.c_int64) for k in ("dens", "m2m", "m2l", "l2l", "pair", "total")]
+
+
 class _Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
                 ("jblock", ct.c_int32), ("accumulate", ct.c_int32)]
@@ -62,6 +66,9 @@ EXPORTS = {
     "occk_free_tree": (ct.c_int32, [ct.c_void_p]),
     "occk_tree_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(_Info)]),
     "occk_tree_flops": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_int32, ct.c_int32, ct.POINTER(_Flops)]),
+    "occk_tree_flops_J": (ct.c_int32, [ct.c_void_p, ct.POINTER(_JFlops)]),
+    "occk_far_J": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32,
+                                ct.c_void_p]),
     "occk_tree_export": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p]),
     "occk_tree_leaf": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.c_void_p,
@@ -253,6 +260,12 @@ class Tree:
             pass
 
     # ------------------------------------------------------------------
+    def flops_J(self) -> dict:
+        """Algorithmic flop counts of one occk_far_J call (occk_tree_flops_J)."""
+        f = _JFlops()
+        _check(lib().occk_tree_flops_J(self._h, ct.byref(f)))
+        return {k: int(getattr(f, k)) for k, _ in _JFlops._fields_}
+
     def flops(self, ni: int, nj: int, symmetric: bool = False) -> dict:
         """Algorithmic flop counts of one occk_far_K call (occk_tree_flops).
 
@@ -284,6 +297,19 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))
+
+
+def far_J(tree: Tree, D, J, accumulate: bool = False, stream=None):
+    """J (+)= J^ff of the density D on the GPU (occk_far_J).  D, J: row-major
+    float64 CUDA tensors (nbasis, ld); asynchronous on ``stream``."""
+    import torch
+    for t in (D, J):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError("D and J must be row-major 2-D float64 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(D.device)
+    _check(lib().occk_far_J(tree.handle, ct.c_void_p(D.data_ptr()), int(D.stride(0)), ct.c_void_p(J.data_ptr()),
+                            int(J.stride(0)), int(bool(accumulate)), ct.c_void_p(stream.cuda_stream)))
 
 
 def debug_mfma_probe(kind: int, ia: int, ka: int, jb: int) -> np.ndarray:

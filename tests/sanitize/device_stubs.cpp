@@ -13,6 +13,8 @@ static int32_t no_gpu() {
 }
 
 void device_free(Tree*) {}
+void jstate_free(Tree*) {}
+int32_t far_J(Tree*, const double*, int64_t, double*, int64_t, int32_t, void*) { return no_gpu(); }
 int32_t far_K(Tree*, const double*, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, const occk_far_opts*,
               double*, int64_t, void*) { return no_gpu(); }
 int32_t debug_mfma_probe(int, int, int, int, double*) { return no_gpu(); }

@@ -129,11 +129,17 @@ def test_water_batch16_in_one_launch():
         print(f"[configs] batch16 {prec}", flush=True)
         plan.run(Cd, Ks)
         torch.cuda.synchronize()
-        errs = []
+        errs, alone = [], []
         for k, K in enumerate(Ks):
             samples = [tuple(int(v) for v in s) for s in g[f"samples{k}"]]
             errs.append(_err(_sampled(K.cpu().numpy(), samples), g[f"K{k}"]))
-        print(f"[configs] batch16 {prec}: worst eps_max {max(errs):.3e}", flush=True)
+            Ka = torch.zeros_like(K)                  # the same system in its own occk_far_K call
+            occk.far_K(trees[k], Cd[k], Ka, precision=code)
+            torch.cuda.synchronize()
+            alone.append(_err(_sampled(Ka.cpu().numpy(), samples), g[f"K{k}"]))
+        print(f"[configs] batch16 {prec}: worst eps_max {max(errs):.3e}; per system batched "
+              + " ".join(f"{e:.2e}" for e in errs) + "; standalone " + " ".join(f"{e:.2e}" for e in alone),
+              flush=True)
         plan.free()
         assert max(errs) <= TOL[prec], (prec, errs)
     for t in trees:

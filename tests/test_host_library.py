@@ -14,6 +14,8 @@ from oracle import harmonics as H
 from oracle.fmm import Setup
 from paper_1708_05353_amd import occk
 
+from conftest import with_params
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -118,7 +120,7 @@ def _sys_struct(wl):
     return st, keep
 
 
-@pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 13), ("ws", -1), ("lmax", 9),
+@pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 13), ("ws", -1), ("lmax", 16),
                                          ("split_mask", 0), ("split_mask", 9), ("pair_log_thresh", -1.0)])
 def test_build_tree_rejects_bad_params(field, value):
     wl = workloads.tiny_chain()
@@ -186,6 +188,44 @@ def test_device_byte_cap_gives_enomem_before_device_work(monkeypatch):
                       ct.c_void_p(0x900000), 20, None)
     assert rc == occk.ENOMEM
     assert b"OCCK_MAX_DEVICE_BYTES" in L.occk_last_error()
+    tr.free()
+
+
+def test_coulomb_entry_point_checks_before_device_work(monkeypatch):
+    """occk_far_J rejects bad arguments on the host (fake device pointers are
+    never touched); the device-byte cap gives ENOMEM before any HIP call; the
+    exchange entry point refuses a tree above its rank limit."""
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, with_params(wl, lmax=10))
+    L = occk.lib()
+    D, J = ct.c_void_p(0x100000), ct.c_void_p(0x900000)
+    assert L.occk_far_J(tr.handle, None, 80, J, 80, 0, None) == occk.EINVAL
+    assert L.occk_far_J(tr.handle, D, 79, J, 80, 0, None) == occk.EINVAL            # ldd < nbasis
+    assert L.occk_far_J(tr.handle, D, 80, J, 80, 2, None) == occk.EINVAL            # accumulate not 0/1
+    assert L.occk_far_J(tr.handle, D, 80, ct.c_void_p(0x100000 + 64), 80, 0, None) == occk.EINVAL  # overlap
+    assert L.occk_far_J(tr.handle, ct.c_void_p(0x100004), 80, J, 80, 0, None) == occk.EINVAL       # misaligned
+    monkeypatch.setenv("OCCK_MAX_DEVICE_BYTES", "4096")
+    assert L.occk_far_J(tr.handle, D, 80, J, 80, 0, None) == occk.ENOMEM
+    opts = occk._Opts(0, 0, None, 0, 0)
+    assert L.occk_far_K(tr.handle, ct.c_void_p(0x100000), 20, 20, 0, 20, 0, 20, ct.byref(opts),
+                        ct.c_void_p(0x900000), 20, None) == occk.EINVAL
+    assert b"lmax <= 8" in L.occk_last_error()
+    tr.free()
+
+
+def test_coulomb_flop_model_matches_oracle_counts():
+    wl = workloads.tiny_chain()
+    p = with_params(wl, lmax=10)
+    st = Setup(wl.system, with_params(wl, lmax=0))        # same pairs and tree; rank does not matter here
+    tr = occk.Tree(wl.system, p)
+    Q, z = 121, tr.info.m2m_nnz
+    t = st.tree
+    n_il = sum(len(v) for lev in range(t.lmin, t.depth + 1) for v in t.il[lev])
+    edges = sum(len(t.boxes[lev]) for lev in range(t.lmin + 1, t.depth + 1))
+    f = tr.flops_J()
+    assert f == dict(dens=2 * Q * len(st.r), m2m=2 * z * edges, m2l=2 * Q * Q * n_il, l2l=2 * z * edges,
+                     pair=2 * Q * len(st.r), total=f["total"])
+    assert f["total"] == sum(v for k, v in f.items() if k != "total")
     tr.free()
 
 
