@@ -204,6 +204,32 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
                    int32_t i0, int32_t i1, int32_t j0, int32_t j1,
                    const occk_far_opts* opts, double* K, int64_t ldk, void* hip_stream);
 
+/* Allocation-free variant of occk_far_K, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, result and errors as
+ * occk_far_K, within these limits:
+ *   - FP64 and fixed rank only (EINVAL otherwise);
+ *   - the tree's device copy must exist: the handle's first occk_far_K makes
+ *     it (ESTATE before that; EINVAL when it is on another device);
+ *   - the workspace (box expansions, half-transformed multipoles, per-leaf K
+ *     partials, GEMM tile tables) is placed in one fixed device region of
+ *     OCCK_NOALLOC_SCRATCH_BYTES per GPU, a static device array held from
+ *     the library's loading until the process ends; jblock = 0 takes the
+ *     widest j batch (<= 256) whose workspace fits; ENOMEM, with the sizes in
+ *     the message, when an explicit jblock does not fit or the workspace of a
+ *     one-column batch does not;
+ *   - it synchronises hip_stream on entry, copies the tile tables into the
+ *     region with hipMemcpy, and calls neither hipMalloc nor hipFree;
+ *   - every call on one GPU uses the same region, which keeps the last
+ *     call's contents (nothing in it has to start at zero): calls that
+ *     overlap in time on one GPU (other streams or threads) race, and the
+ *     caller must serialise them.
+ * The handle's own workspace (that of occk_far_K) is left as it was. */
+#define OCCK_NOALLOC_SCRATCH_BYTES (128ll << 20)
+int32_t occk_far_K_noalloc(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
+                           int32_t i0, int32_t i1, int32_t j0, int32_t j1,
+                           const occk_far_opts* opts, double* K, int64_t ldk, void* hip_stream);
+
 /* Far-field Coulomb matrix on the GPU, through the same tree (Theory section:
  * the Coulomb passage with Eq. 10 and the J^ff formula after it):
  *   O^B_lm    = sum over the pairs (t,u) of leaf B of D_tu O^{tu,B}_lm

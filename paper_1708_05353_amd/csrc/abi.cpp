@@ -222,7 +222,7 @@ int32_t occk_tree_leaf(const occk_tree* tree, int32_t leaf, int32_t* nb, int32_t
 
 }  // extern "C"
 
-// Host-side checks of occk_far_K arguments; fills o.
+// Host-side checks shared by occk_far_K and occk_far_K_noalloc; fills o.
 static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0,
                            int32_t i1, int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
                            occk_far_opts& o) {
@@ -297,6 +297,22 @@ int32_t occk_far_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, 
   if (rc != OCCK_OK) return rc;
   OCCK_GUARD_BEGIN
   return far_K(t, C, ldc, nocc, i0, i1, j0, j1, &o, K, ldk, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_far_K_noalloc(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
+                           int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
+                           void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  occk_far_opts o{};
+  const int32_t rc = check_far_K("occk_far_K_noalloc", t, C, ldc, nocc, i0, i1, j0, j1, opts, K, ldk, o);
+  if (rc != OCCK_OK) return rc;
+  if (o.precision != OCCK_PREC_FP64 || o.rank_mode != OCCK_RANK_FIXED) {
+    set_error("occk_far_K_noalloc: only FP64 with fixed rank");
+    return OCCK_EINVAL;
+  }
+  OCCK_GUARD_BEGIN
+  return far_K_noalloc(t, C, ldc, nocc, i0, i1, j0, j1, &o, K, ldk, hip_stream);
   OCCK_GUARD_END
 }
 

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <functional>
+#include <mutex>
 #include <stdexcept>
 #include <tuple>
 #include <string>
@@ -866,6 +867,123 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
   } catch (const std::bad_alloc&) {
     set_error("device workspace exceeds OCCK_MAX_DEVICE_BYTES or allocation failed");
     return OCCK_ENOMEM;
+  }
+  return OCCK_OK;
+}
+
+// --------------------------------------------------------------------------
+// allocation-free variant of far_K
+// --------------------------------------------------------------------------
+// The workspace of an allocation-free call lives in this region.  Host code
+// never uses the array's name as an address: the per-device address comes
+// from hipGetSymbolAddress (scratch_base).
+static __device__ __align__(256) unsigned char scratch[size_t(OCCK_NOALLOC_SCRATCH_BYTES)];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+// Device address of `scratch` on device dev (current), looked up once per device.
+static char* scratch_base(int dev) {
+  if (dev < 0 || dev >= 64) throw std::invalid_argument("device ordinal out of range for the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError("hipGetSymbolAddress returned a null scratch address");
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
+
+// The owned workspace of a DeviceState, moved aside while an allocation-free
+// call places its own workspace in the scratch region, then moved back.
+struct WorkspaceStash {
+  int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;
+  uint64_t ws_gen = 0;
+  DevBuf<char> H, data, HT;
+  DevBuf<double> KB;
+  DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
+  DevBuf<GemmTile> t_half, t_omega, t_l2p, t_ht, t_l2pt, t_l2ptw, t_l2pw;
+  int n_half = 0, n_omega = 0, n_l2p = 0, n_ht = 0, n_l2pt = 0, n_l2ptw = 0;
+  std::vector<int32_t> l2pw_nt_start, omega_nt_start, l2p_nt_start;
+};
+
+static void swap_workspace(DeviceState* ds, WorkspaceStash& w) {
+  using std::swap;
+  swap(ds->ws_jb, w.ws_jb); swap(ds->ws_ni, w.ws_ni); swap(ds->ws_prec, w.ws_prec); swap(ds->ws_sym, w.ws_sym);
+  swap(ds->ws_gen, w.ws_gen);
+  swap(ds->H, w.H); swap(ds->data, w.data); swap(ds->HT, w.HT); swap(ds->KB, w.KB);
+  swap(ds->d_half, w.d_half); swap(ds->d_omega, w.d_omega); swap(ds->d_l2p, w.d_l2p); swap(ds->d_ht, w.d_ht);
+  swap(ds->d_l2pt, w.d_l2pt);
+  swap(ds->t_half, w.t_half); swap(ds->t_omega, w.t_omega); swap(ds->t_l2p, w.t_l2p); swap(ds->t_ht, w.t_ht);
+  swap(ds->t_l2pt, w.t_l2pt); swap(ds->t_l2ptw, w.t_l2ptw); swap(ds->t_l2pw, w.t_l2pw);
+  swap(ds->n_half, w.n_half); swap(ds->n_omega, w.n_omega); swap(ds->n_l2p, w.n_l2p); swap(ds->n_ht, w.n_ht);
+  swap(ds->n_l2pt, w.n_l2pt); swap(ds->n_l2ptw, w.n_l2ptw);
+  swap(ds->l2pw_nt_start, w.l2pw_nt_start); swap(ds->omega_nt_start, w.omega_nt_start);
+  swap(ds->l2p_nt_start, w.l2p_nt_start);
+}
+
+// FP64, fixed rank (checked by the caller).  Same steps and kernels as far_K;
+// only the workspace placement differs.
+int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1, int32_t j0,
+                      int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk, void* stream) {
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int ni = i1 - i0, nj = j1 - j0;
+  const int nbasis = t->nbasis;
+  try {
+    if (t->lmin < 0 || nj == 0 || ni == 0) {   // no far field
+      if (!opts->accumulate && ni > 0)
+        hipLaunchKernelGGL(zero_cols_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
+                           K, ldk, i0, int64_t(ni));
+      HIP_OK(hipGetLastError());
+      return OCCK_OK;
+    }
+    DeviceState* ds = t->dev;
+    if (!ds) {
+      set_error("occk_far_K_noalloc: the tree has no device copy yet; one occk_far_K call on the handle makes it");
+      return OCCK_ESTATE;
+    }
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != ds->device) {
+      set_error("occk_far_K_noalloc: the tree's device copy is on another device");
+      return OCCK_EINVAL;
+    }
+    char* base = scratch_base(dev);
+    // earlier work on this stream may still read the region's tables
+    HIP_OK(hipStreamSynchronize(st));
+    const bool sym = i0 == j0 && i1 == j1;
+    WorkspaceStash stash;
+    swap_workspace(ds, stash);
+    struct Restore {
+      DeviceState* ds;
+      WorkspaceStash& w;
+      ~Restore() { swap_workspace(ds, w); }   // the views left in w are dropped, never freed
+    } restore{ds, stash};
+    int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : std::min(nj, 256);
+    for (;;) {
+      ScratchArena arena{base, size_t(OCCK_NOALLOC_SCRATCH_BYTES), 0};
+      try {
+        setup_workspace(t, jb, ni, OCCK_PREC_FP64, sym, &arena);
+        break;
+      } catch (const ScratchFull& e) {
+        if (opts->jblock > 0 || jb == 1) {
+          set_error(std::string("occk_far_K_noalloc: ") + e.what() + " (j batch " + std::to_string(jb) + ")");
+          return OCCK_ENOMEM;
+        }
+        jb = (jb + 1) / 2;
+      }
+    }
+    hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p,
+                       t->L, t->Q);
+    HIP_OK(hipGetLastError());
+    run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, false, st, nullptr, false, sym);
+    hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
+                       ds->KB.p, int64_t(ni), ds->occ_ptr.p, ds->occ_row.p, K, ldk, i0, opts->accumulate);
+    HIP_OK(hipGetLastError());
+  } catch (const HipError& e) {
+    set_error(e.what());
+    return OCCK_EHIP;
   }
   return OCCK_OK;
 }

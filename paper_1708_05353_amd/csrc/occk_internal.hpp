@@ -98,6 +98,8 @@ void device_free(Tree* t);
 int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
               int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk,
               void* stream);
+int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
+                      int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk, void* stream);
 void jstate_free(Tree* t);
 int32_t far_J(Tree* t, const double* D, int64_t ldd, double* J, int64_t ldj, int32_t accumulate, void* stream);
 int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);

@@ -76,6 +76,9 @@ EXPORTS = {
     "occk_far_K": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
                                 ct.c_int32, ct.c_int32, ct.POINTER(_Opts), ct.c_void_p, ct.c_int64,
                                 ct.c_void_p]),
+    "occk_far_K_noalloc": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_int32, ct.c_int32,
+                                        ct.c_int32, ct.c_int32, ct.POINTER(_Opts), ct.c_void_p, ct.c_int64,
+                                        ct.c_void_p]),
     "occk_debug_mfma_probe": (ct.c_int32, [ct.c_int32, ct.c_int32, ct.c_int32, ct.c_int32, ct.c_void_p]),
     "occk_debug_buffer": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.c_void_p, ct.POINTER(ct.c_int64)]),
     "occk_batch_create": (ct.c_int32, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(_Opts),
@@ -297,6 +300,25 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))
+
+
+def far_K_noalloc(tree: Tree, C, K, i_range=None, j_range=None, jblock: int = 0, accumulate: bool = False,
+                  stream=None):
+    """occk_far_K_noalloc: FP64, fixed rank, workspace in the library's fixed
+    scratch region (no device allocation).  Same tensors as far_K."""
+    import torch
+    nocc = int(C.shape[1])
+    i0, i1 = (0, nocc) if i_range is None else i_range
+    j0, j1 = (0, nocc) if j_range is None else j_range
+    for t in (C, K):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError("C and K must be row-major 2-D float64 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(C.device)
+    opts = _Opts(PREC_FP64, RANK_FIXED, None, int(jblock), int(bool(accumulate)))
+    _check(lib().occk_far_K_noalloc(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0),
+                                    int(i1), int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()),
+                                    int(K.stride(0)), ct.c_void_p(stream.cuda_stream)))
 
 
 def far_J(tree: Tree, D, J, accumulate: bool = False, stream=None):

@@ -17,6 +17,8 @@ void jstate_free(Tree*) {}
 int32_t far_J(Tree*, const double*, int64_t, double*, int64_t, int32_t, void*) { return no_gpu(); }
 int32_t far_K(Tree*, const double*, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, const occk_far_opts*,
               double*, int64_t, void*) { return no_gpu(); }
+int32_t far_K_noalloc(Tree*, const double*, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t,
+                      const occk_far_opts*, double*, int64_t, void*) { return no_gpu(); }
 int32_t debug_mfma_probe(int, int, int, int, double*) { return no_gpu(); }
 int32_t debug_buffer(Tree*, int, double*, int64_t*) { return no_gpu(); }
 int32_t profile_read(Tree*, double*, int64_t*) { return no_gpu(); }
