@@ -78,13 +78,28 @@ typedef struct occk_system {
  * delta = 0.05 E + 1, lo = min - 0.35 delta, width W = E + delta; a dimension
  * that is not split is one layer centred on the midpoint of the pair centres.
  * The interaction list of a box holds the non-near boxes of its level whose
- * parents are near its parent; empty boxes are pruned. */
+ * parents are near its parent; empty boxes are pruned.
+ *   near_rule   OCCK_NEAR_BOXES: near iff the box-index distance is <= ws (above);
+ *               OCCK_NEAR_EXTENT: the paper's criterion by extents (Theory
+ *               section, the near/far paragraph): a pair distribution of
+ *               exponent p = a + b has extent erfc^-1(ext_tau)/sqrt(p); a box's
+ *               extent is the largest |P - X_box| + extent over the
+ *               distributions it holds; two boxes of one level are far iff
+ *               |X_a - X_b| > (1 + ext_ws)(ext_a + ext_b); near lists are
+ *               formed top down (ws is then unused)
+ *   ext_ws      slack of the extent rule (the paper's ws; 0 typical), -1 < ext_ws <= 10
+ *   ext_tau     extent threshold, 0 < ext_tau < 0.5 (1e-8: the s-type
+ *               penetration erfc of two separated distributions stays below it) */
+enum { OCCK_NEAR_BOXES = 0, OCCK_NEAR_EXTENT = 1 };
 typedef struct occk_tree_params {
   int32_t split_mask;
   int32_t depth;
   int32_t ws;
   int32_t lmax;
   double pair_log_thresh;
+  int32_t near_rule;
+  double ext_ws;
+  double ext_tau;
 } occk_tree_params;
 
 typedef struct occk_tree occk_tree;

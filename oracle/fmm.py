@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import numpy as np
 from scipy import sparse
+from scipy.special import erfcinv
 
 from . import harmonics as H
 from .basis import Functions, ao_multipoles, function_pairs
@@ -93,7 +94,13 @@ class Setup:
         self.L = int(params.lmax)
         self.fn = Functions(system)
         self.r, self.s, self.P = function_pairs(system, self.fn, params.pair_log_thresh)
-        self.tree = Tree(self.P, params.split_mask, params.depth, params.ws)
+        if getattr(params, "near_rule", 0) == 1:
+            # extent of a pair distribution of exponent p = a + b: erfc^-1(tau) / sqrt(p)
+            pe = self.fn.exp[self.r] + self.fn.exp[self.s]
+            ext = erfcinv(params.ext_tau) / np.sqrt(pe)
+            self.tree = Tree(self.P, params.split_mask, params.depth, params.ext_ws, extents=ext)
+        else:
+            self.tree = Tree(self.P, params.split_mask, params.depth, params.ws)
         t = self.tree
         self.nleaf = len(t.boxes[t.depth])
         self.leaf_pairs = [np.nonzero(t.pair_leaf == b)[0] for b in range(self.nleaf)]

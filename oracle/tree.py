@@ -17,6 +17,16 @@ to the implementation.  This oracle takes the following readings:
 * Interaction list: the non-near boxes of the same level whose parents are
   near the box's parent.  Leaf pairs that are near are the near field and are
   not part of K^ff.
+
+Extent rule (the paper's criterion: two charge distributions are separated
+when the distance of their centres exceeds the sum of their extents, with a
+slack ws): given the extent e_k of every pair distribution, the extent of a
+box is the largest |P_k - X_box| + e_k over the distributions whose centres
+lie in it; two boxes of one level are far when |X_a - X_b| > (1 + ws)(e_a +
+e_b) and near otherwise.  Near lists are formed top down: the root is near
+itself, and a box's candidates are the children of its parent's near boxes;
+a candidate far from the box enters its interaction list, the others its
+near list.
 """
 from __future__ import annotations
 
@@ -26,9 +36,9 @@ import numpy as np
 
 
 class Tree:
-    def __init__(self, centres: np.ndarray, split_mask: int, depth: int, ws: int):
+    def __init__(self, centres: np.ndarray, split_mask: int, depth: int, ws, extents=None):
         centres = np.asarray(centres, dtype=np.float64)
-        self.depth, self.ws = int(depth), int(ws)
+        self.depth, self.ws = int(depth), ws
         self.split = [d for d in range(3) if (split_mask >> d) & 1]
         if not self.split:
             raise ValueError("no split dimension")
@@ -63,6 +73,11 @@ class Tree:
         self.pair_leaf = np.array([leafidx[tuple(int(v) for v in c)] for c in coords], dtype=np.int64)
         # interaction lists
         self.il: list[list[list[int]]] = [[[] for _ in self.boxes[lev]] for lev in range(depth + 1)]
+        if extents is not None:
+            self._extent_lists(centres, coords, np.asarray(extents, dtype=np.float64), float(ws))
+            levels = [lev for lev in range(depth + 1) if any(self.il[lev][b] for b in range(len(self.boxes[lev])))]
+            self.lmin = min(levels) if levels else None
+            return
         for lev in range(1, depth + 1):
             for b, c in enumerate(self.boxes[lev]):
                 pc = tuple(v >> 1 for v in c)
@@ -72,6 +87,37 @@ class Tree:
                         self.il[lev][b].append(b2)
         levels = [lev for lev in range(depth + 1) if any(self.il[lev][b] for b in range(len(self.boxes[lev])))]
         self.lmin = min(levels) if levels else None
+
+    def _extent_lists(self, centres, coords, extents, ws):
+        D = self.depth
+        self.box_ext = []
+        for lev in range(D + 1):
+            sh = D - lev
+            ext = np.zeros(len(self.boxes[lev]))
+            for k in range(len(centres)):
+                b = self.index[lev][tuple(int(v) >> sh for v in coords[k])]
+                d = np.linalg.norm(centres[k] - self.centre(lev, self.boxes[lev][b]))
+                ext[b] = max(ext[b], d + extents[k])
+            self.box_ext.append(ext)
+        self.near_list = [[[0]]]
+        for lev in range(1, D + 1):
+            nl = []
+            for b, c in enumerate(self.boxes[lev]):
+                mine = []
+                Xb = self.centre(lev, c)
+                for q in self.near_list[lev - 1][self.parent(lev, b)]:
+                    qc = self.boxes[lev - 1][q]
+                    for b2, c2 in enumerate(self.boxes[lev]):
+                        if tuple(v >> 1 for v in c2) != qc:
+                            continue
+                        dist = np.linalg.norm(Xb - self.centre(lev, c2))
+                        if dist > (1.0 + ws) * (self.box_ext[lev][b] + self.box_ext[lev][b2]):
+                            self.il[lev][b].append(b2)
+                        else:
+                            mine.append(b2)
+                self.il[lev][b].sort()
+                nl.append(sorted(mine))
+            self.near_list.append(nl)
 
     def near(self, c1, c2) -> bool:
         return max(abs(c1[d] - c2[d]) for d in range(3)) <= self.ws

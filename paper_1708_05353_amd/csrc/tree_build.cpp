@@ -204,6 +204,90 @@ void leaf_pair_multipoles(const Tree& t, int leaf, double* out) {
 // --------------------------------------------------------------------------
 static void fail(const std::string& m) { throw std::invalid_argument(m); }
 
+// x >= 0 with erfc(x) = tau (0 < tau < 1/2), by Newton's method on erfc from
+// x0 = sqrt(-ln tau); erfc is convex and decreasing there, so the iterates
+// increase monotonically to the root.
+static double erfc_inverse(double tau) {
+  double x = std::sqrt(-std::log(tau)) - 1.0;
+  if (x < 0.0) x = 0.0;
+  for (int it = 0; it < 100; ++it) {
+    const double f = std::erfc(x) - tau;
+    const double df = -2.0 / std::sqrt(M_PI) * std::exp(-x * x);
+    const double nx = x - f / df;
+    if (std::fabs(nx - x) <= 1e-15 * std::max(1.0, nx)) return nx;
+    x = nx;
+  }
+  return x;
+}
+
+// Interaction lists by the extents of the charge distributions (Theory
+// section, the near/far paragraph): a pair distribution of exponent
+// p = a + b has extent e = erfc^-1(tau)/sqrt(p); a box's extent is the largest
+// |P - X_box| + e over the distributions whose centres it holds; two boxes of
+// one level are far when |X_a - X_b| > (1 + ws)(e_a + e_b).  Near lists are
+// formed top down from the root (near itself): a box's candidates are the
+// children of its parent's near boxes, the far ones form its interaction
+// list, the rest its near list.
+static void extent_lists(Tree& t, const std::vector<std::array<int32_t, 3>>& pc) {
+  const occk_tree_params& p = t.params;
+  const int D = p.depth;
+  const double einv = erfc_inverse(p.ext_tau);
+  std::vector<std::vector<double>> ext(size_t(D + 1));
+  std::vector<std::vector<std::array<double, 3>>> X(size_t(D + 1));
+  for (int lev = 0; lev <= D; ++lev) {
+    ext[size_t(lev)].assign(t.boxes[lev].size(), 0.0);
+    X[size_t(lev)].resize(t.boxes[lev].size());
+    for (size_t b = 0; b < t.boxes[lev].size(); ++b) t.centre(lev, t.boxes[lev][b], X[size_t(lev)][b].data());
+  }
+  for (size_t k = 0; k < t.pairs.size(); ++k) {
+    const Pair& pr = t.pairs[k];
+    const double e = einv / std::sqrt(t.funcs[size_t(pr.r)].exp + t.funcs[size_t(pr.s)].exp);
+    for (int lev = 0; lev <= D; ++lev) {
+      const int sh = D - lev;
+      const int32_t b = t.index[lev].at(coord_key(pc[k][0] >> sh, pc[k][1] >> sh, pc[k][2] >> sh));
+      const auto& x = X[size_t(lev)][size_t(b)];
+      double d2 = 0.0;
+      for (int d = 0; d < 3; ++d) d2 += (pr.P[d] - x[d]) * (pr.P[d] - x[d]);
+      double& eb = ext[size_t(lev)][size_t(b)];
+      eb = std::max(eb, std::sqrt(d2) + e);
+    }
+  }
+  // children of every box, in box order
+  std::vector<std::vector<std::vector<int32_t>>> kids(size_t(D + 1));
+  for (int lev = 1; lev <= D; ++lev) {
+    kids[size_t(lev - 1)].assign(t.boxes[lev - 1].size(), {});
+    for (int32_t b = 0; b < int32_t(t.boxes[lev].size()); ++b) kids[size_t(lev - 1)][size_t(t.parent(lev, b))].push_back(b);
+  }
+  std::vector<std::vector<int32_t>> near_prev{{0}}, near_cur;
+  t.il_ptr[0].assign(t.boxes[0].size() + 1, 0);
+  for (int lev = 1; lev <= D; ++lev) {
+    const auto& bx = t.boxes[lev];
+    t.il_ptr[lev].assign(bx.size() + 1, 0);
+    near_cur.assign(bx.size(), {});
+    for (int32_t b = 0; b < int32_t(bx.size()); ++b) {
+      const auto& xb = X[size_t(lev)][size_t(b)];
+      const size_t e0 = t.il_idx[lev].size();
+      for (int32_t q : near_prev[size_t(t.parent(lev, b))])
+        for (int32_t b2 : kids[size_t(lev - 1)][size_t(q)]) {
+          const auto& x2 = X[size_t(lev)][size_t(b2)];
+          double d2 = 0.0;
+          for (int d = 0; d < 3; ++d) d2 += (xb[d] - x2[d]) * (xb[d] - x2[d]);
+          if (std::sqrt(d2) > (1.0 + p.ext_ws) * (ext[size_t(lev)][size_t(b)] + ext[size_t(lev)][size_t(b2)])) {
+            for (int d = 0; d < 3; ++d)
+              if (std::abs(bx[size_t(b)][d] - bx[size_t(b2)][d]) >= 64)
+                fail("extent rule: an interaction-list displacement beyond 63 boxes");
+            t.il_idx[lev].push_back(b2);
+          } else {
+            near_cur[size_t(b)].push_back(b2);
+          }
+        }
+      std::sort(t.il_idx[lev].begin() + int64_t(e0), t.il_idx[lev].end());
+      t.il_ptr[lev][size_t(b) + 1] = int32_t(t.il_idx[lev].size());
+    }
+    near_prev.swap(near_cur);
+  }
+}
+
 Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
   if (!sys || !p) fail("null system or params");
   if (sys->natoms <= 0 || !sys->xyz) fail("natoms must be > 0 and xyz non-null");
@@ -214,6 +298,10 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
   if (p->ws < 0 || p->ws > 4) fail("ws must be in [0, 4]");
   if (p->lmax < 0 || p->lmax > kMaxLTree) fail("lmax must be in [0, 15]");
   if (std::isnan(p->pair_log_thresh) || p->pair_log_thresh <= 0) fail("pair_log_thresh must be > 0");
+  if (p->near_rule != OCCK_NEAR_BOXES && p->near_rule != OCCK_NEAR_EXTENT) fail("near_rule must be 0 or 1");
+  if (p->near_rule == OCCK_NEAR_EXTENT &&
+      (!(p->ext_tau > 0.0) || !(p->ext_tau < 0.5) || !std::isfinite(p->ext_ws) || p->ext_ws <= -1.0 || p->ext_ws > 10.0))
+    fail("extent rule: need 0 < ext_tau < 0.5 and -1 < ext_ws <= 10");
   for (int a = 0; a < 3 * sys->natoms; ++a)
     if (!std::isfinite(sys->xyz[a])) fail("non-finite coordinate");
   for (int s = 0; s < sys->nshell; ++s) {
@@ -320,6 +408,11 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
     }
     for (size_t k = 0; k < t.pairs.size(); ++k)
       t.pairs[k].leaf = t.index[D].at(coord_key(pc[k][0], pc[k][1], pc[k][2]));
+    t.il_ptr.assign(D + 1, {});
+    t.il_idx.assign(D + 1, {});
+    if (p->near_rule == OCCK_NEAR_EXTENT) {
+      extent_lists(t, pc);
+    } else {
     // interaction lists: non-near boxes whose parent is near the box's parent
     const int ws = p->ws;
     auto near = [ws](const std::array<int32_t, 3>& a, const std::array<int32_t, 3>& b) {
@@ -327,8 +420,6 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
       for (int d = 0; d < 3; ++d) m = std::max(m, std::abs(a[d] - b[d]));
       return m <= ws;
     };
-    t.il_ptr.assign(D + 1, {});
-    t.il_idx.assign(D + 1, {});
     for (int lev = 0; lev <= D; ++lev) {
       const auto& bx = t.boxes[lev];
       t.il_ptr[lev].assign(bx.size() + 1, 0);
@@ -365,8 +456,10 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
         }
         t.il_ptr[lev][b + 1] = int32_t(t.il_idx[lev].size());
       }
-      if (t.lmin < 0 && !t.il_idx[lev].empty()) t.lmin = lev;
     }
+    }
+    for (int lev = 0; lev <= D; ++lev)
+      if (t.lmin < 0 && !t.il_idx[lev].empty()) t.lmin = lev;
     // leaves
     const int nl = int(t.boxes[D].size());
     t.leaf_pairs.assign(nl, {});

@@ -32,7 +32,8 @@ class _System(ct.Structure):
 
 class _Params(ct.Structure):
     _fields_ = [("split_mask", ct.c_int32), ("depth", ct.c_int32), ("ws", ct.c_int32),
-                ("lmax", ct.c_int32), ("pair_log_thresh", ct.c_double)]
+                ("lmax", ct.c_int32), ("pair_log_thresh", ct.c_double), ("near_rule", ct.c_int32),
+                ("ext_ws", ct.c_double), ("ext_tau", ct.c_double)]
 
 
 class _Info(ct.Structure):
@@ -181,7 +182,8 @@ class Tree:
         s = _System(int(xyz.shape[0]), _ptr(xyz, ct.c_double), int(sl.shape[0]), _ptr(sa, ct.c_int32),
                     _ptr(sl, ct.c_int32), _ptr(se, ct.c_double))
         p = _Params(int(params.split_mask), int(params.depth), int(params.ws), int(params.lmax),
-                    float(params.pair_log_thresh))
+                    float(params.pair_log_thresh), int(getattr(params, "near_rule", 0)),
+                    float(getattr(params, "ext_ws", 0.0)), float(getattr(params, "ext_tau", 1e-8)))
         h = ct.c_void_p()
         _check(L.occk_build_tree(ct.byref(s), ct.byref(p), ct.byref(h)))
         self._h = h

@@ -77,6 +77,7 @@ int main() {
     for (int k = 0; k < 20; ++k) s.add_atom(2.0 * k, 0, 0, {0.1, 0.4641588833612779, 2.154434690031884, 10.0}, {});
     exercise(s, occk_tree_params{1, 3, 2, 2, inf});
     exercise(s, occk_tree_params{1, 3, 1, 5, inf});
+    exercise(s, occk_tree_params{1, 3, 0, 2, inf, OCCK_NEAR_EXTENT, 0.0, 1e-8});
   }
   {  // 2-D sheet with s and p shells, screened pairs
     Sys s;
@@ -84,6 +85,7 @@ int main() {
       for (int b = 0; b < 5; ++b)
         s.add_atom(2.4 * a + 1.2 * (b % 2), 2.1 * b, 0.0, {21.13, 1.774, 0.15}, {1.774, 0.15});
     exercise(s, occk_tree_params{3, 3, 1, 4, std::log(1e12)});
+    exercise(s, occk_tree_params{3, 3, 0, 10, std::log(1e12), OCCK_NEAR_EXTENT, -0.1, 1e-8});
   }
   {  // 3-D cluster
     Sys s;

@@ -70,6 +70,33 @@ def test_tree_and_multipoles_match_oracle(case):
         assert np.abs(O - Or).max() <= 1e-12 * max(np.abs(Or).max(), 1e-300)
 
 
+@pytest.mark.parametrize("case,ws", [("chain", 0.0), ("sheet", 0.0), ("sheet", -0.1), ("water", 0.0),
+                                     ("alkane", 0.5)])
+def test_extent_rule_lists_match_oracle(case, ws):
+    """Interaction lists of the extent rule: the library's (C++, Newton on
+    erfc) against the oracle's (scipy erfcinv, plain loops)."""
+    from scipy.special import erfcinv
+    from oracle.basis import Functions, function_pairs
+    from oracle.tree import Tree as OTree
+    wl = {"chain": workloads.tiny_chain, "sheet": lambda: workloads.graphene_flake(n=3, nocc=20, depth=4),
+          "water": lambda: workloads.water_cluster(20, 40),
+          "alkane": lambda: workloads.alkane_chain(n_carbon=40, depth=5)}[case]()
+    p = with_params(wl, near_rule=1, ext_ws=ws, ext_tau=1e-8)
+    tr = occk.Tree(wl.system, p)
+    fn = Functions(wl.system)
+    r, s, P = function_pairs(wl.system, fn, p.pair_log_thresh)
+    ot = OTree(P, p.split_mask, p.depth, ws, extents=erfcinv(1e-8) / np.sqrt(fn.exp[r] + fn.exp[s]))
+    leaf, lev, tgt, src, pl = tr.export()
+    assert [tuple(x) for x in leaf] == [tuple(x) for x in ot.boxes[ot.depth]]
+    assert tr.info.lmin == (ot.lmin if ot.lmin is not None else -1)
+    key = lambda c: c[0] + 4096 * (c[1] + 4096 * c[2])
+    ref = {(l, key(ot.boxes[l][b]), key(ot.boxes[l][b2])) for l in range(ot.depth + 1)
+           for b, lst in enumerate(ot.il[l]) for b2 in lst}
+    assert len(ref) > 0
+    assert set(zip(lev.tolist(), tgt.tolist(), src.tolist())) == ref
+    tr.free()
+
+
 def test_info_counts_tiny_chain():
     wl = workloads.tiny_chain()
     tr = occk.Tree(wl.system, wl.params)
@@ -121,12 +148,15 @@ def _sys_struct(wl):
 
 
 @pytest.mark.parametrize("field,value", [("depth", 0), ("depth", 13), ("ws", -1), ("lmax", 16),
-                                         ("split_mask", 0), ("split_mask", 9), ("pair_log_thresh", -1.0)])
+                                         ("split_mask", 0), ("split_mask", 9), ("pair_log_thresh", -1.0),
+                                         ("near_rule", 2), ("ext_tau", 0.7), ("ext_ws", -1.5)])
 def test_build_tree_rejects_bad_params(field, value):
     wl = workloads.tiny_chain()
     st, keep = _sys_struct(wl)
     p = wl.params
     pr = occk._Params(p.split_mask, p.depth, p.ws, p.lmax, p.pair_log_thresh)
+    if field.startswith("ext_"):
+        pr.near_rule, pr.ext_tau = 1, 1e-8
     setattr(pr, field, value)
     h = ct.c_void_p()
     code = occk.lib().occk_build_tree(ct.byref(st), ct.byref(pr), ct.byref(h))

@@ -99,6 +99,9 @@ class TreeParams:
     ws: int                  # near iff Chebyshev box-index distance <= ws (same level)
     lmax: int                # multipole rank L (l <= L and l' <= L)
     pair_log_thresh: float = math.log(1e12)  # keep pair iff (ab/(a+b))|A-B|^2 <= thresh
+    near_rule: int = 0       # 0: box-index ws above; 1: extents of the charge distributions
+    ext_ws: float = 0.0      # extent rule: far iff |Xa - Xb| > (1 + ext_ws)(ext_a + ext_b)
+    ext_tau: float = 1e-8    # extent of a distribution of exponent p: erfc^-1(ext_tau) / sqrt(p)
 
 
 @dataclass
