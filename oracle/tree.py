@@ -119,6 +119,13 @@ class Tree:
                 nl.append(sorted(mine))
             self.near_list.append(nl)
 
+    def near_leaves(self, leaf: int) -> list:
+        """Leaves near the given leaf (itself included): the near field."""
+        if hasattr(self, "near_list"):
+            return list(self.near_list[self.depth][leaf])
+        c = self.boxes[self.depth][leaf]
+        return [b for b, c2 in enumerate(self.boxes[self.depth]) if self.near(c, c2)]
+
     def near(self, c1, c2) -> bool:
         return max(abs(c1[d] - c2[d]) for d in range(3)) <= self.ws
 

@@ -58,6 +58,8 @@ def site_shells(kind: str) -> list[tuple[int, float]]:
         return [(0, 13.0), (0, 0.12), (1, math.sqrt(0.12 * 13.0))]
     if kind == "X":  # tiny-chain site: 4 s shells, geometric 0.1 .. 10
         return [(0, 0.1 * 100.0 ** (k / 3.0)) for k in range(4)]
+    if kind == "Y":  # small s+p test site: 2 s shells and one p shell, compact
+        return [(0, 4.0), (0, 1.2), (1, 1.5)]
     raise ValueError(kind)
 
 
@@ -140,6 +142,17 @@ def tiny_chain() -> Workload:
     xyz[:, 0] = 2.0 * np.arange(20)
     sysm = _build("tiny_chain", xyz, ["X"] * 20, 20)
     return Workload(sysm, TreeParams(SPLIT_X, 3, 2, 2, math.inf), seed=1)
+
+
+def sp_chain(n: int = 10, spacing: float = 2.4, lmax: int = 2, depth: int = 3) -> Workload:
+    """n compact s+p sites (2 s shells, 1 p shell) on the x axis, slightly
+    zig-zag in y; nbasis 5n, nocc n; no pair screening (small tests of the
+    near field, which needs exact integrals over every function type)."""
+    xyz = np.zeros((n, 3))
+    xyz[:, 0] = spacing * np.arange(n)
+    xyz[:, 1] = 0.3 * (np.arange(n) % 2)
+    sysm = _build(f"sp_chain_{n}", xyz, ["Y"] * n, n)
+    return Workload(sysm, TreeParams(SPLIT_X, depth, 1, lmax, math.inf), seed=11)
 
 
 def alkane_chain(n_carbon: int = 400, lmax: int = 2, depth: int = 8) -> Workload:
