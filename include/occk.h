@@ -129,6 +129,7 @@ typedef struct occk_tree_info_t {
   int64_t m2m_nnz;             /* structural nonzeros of one real-form M2M
                                   (= L2L) operator                           */
   double lo[3], width, mid[3];
+  int64_t n_near;              /* ordered near leaf pairs (the near field), self pairs included */
 } occk_tree_info_t;
 
 typedef struct occk_far_opts {
@@ -193,6 +194,11 @@ int32_t occk_tree_flops(const occk_tree* tree, int32_t ni, int32_t nj, int32_t s
  *                ascending; may be NULL */
 int32_t occk_tree_export(const occk_tree* tree, int32_t* leaf_coords, int32_t* il_level,
                          int32_t* il_target, int32_t* il_source, int32_t* pair_leaf);
+
+/* Host export of the near field: for every leaf (library order), the sorted
+ * leaves near it, itself included, as CSR: ptr [nleaf+1], idx [n_near]
+ * (tree_info).  Either may be NULL. */
+int32_t occk_tree_near(const occk_tree* tree, int32_t* ptr, int32_t* idx);
 
 /* Host copy of one leaf's data: its sorted function list (nb entries) and the
  * dense real-form AO multipole block O[q][a][b] (q over (L+1)^2 real
@@ -265,6 +271,31 @@ int32_t occk_far_K_noalloc(occk_tree* tree, const double* C, int64_t ldc, int32_
  * (beyond OCCK_MAX_DEVICE_BYTES, checked before any HIP call), EHIP. */
 int32_t occk_far_J(occk_tree* tree, const double* D, int64_t ldd, double* J, int64_t ldj,
                    int32_t accumulate, void* hip_stream);
+
+/* Near-field occupied exchange with exact integrals over the s/p primitives
+ * (Theory section: the distributions whose leaf boxes are near are not
+ * expanded; with the exchange definition of the Introduction):
+ *   K[r, i] (+)= 2 sum_j sum_{(r,s) in B, (t,u) in B'} (rs|tu) C_sj C_tj C_ui
+ * over the ordered pairs of leaves B, B' that are near (B = B' included;
+ * the leaf-level near relation of the tree's near_rule), i.e.
+ * K = X C with X_ru = sum_{s,t} (rs|tu) D_st, D = 2 C C^T.  Together with
+ * occk_far_K it gives the whole exchange.  Integrals: McMurchie-Davidson
+ * over the screened shell pairs, FP64; X is accumulated with atomic adds, so
+ * the last bits may differ between runs.
+ * C: device, row-major nbasis x ldc FP64 (ldc >= nocc; all nocc columns are
+ *    the occupied orbitals).  K: device, row-major nbasis x ldk FP64 (ldk >=
+ *    nocc); accumulate = 0: K[:, :nocc] = K^nf, 1: K[:, :nocc] += K^nf.  K must
+ *    not overlap C.
+ * The first call on a handle (or with another nocc) builds the shell-pair
+ * tables and allocates D, X and C^T on the device (3 nbasis^2-sized FP64
+ * buffers at most; checked against OCCK_MAX_DEVICE_BYTES before any HIP
+ * call).  Asynchronous on hip_stream.  Errors: EINVAL, EHANDLE, ENOMEM, EHIP. */
+int32_t occk_near_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, double* K, int64_t ldk,
+                    int32_t accumulate, void* hip_stream);
+
+/* Work of the handle's near-field tables: wave tasks and shell quartets per
+ * occk_near_K call (either pointer may be NULL).  ESTATE before the first call. */
+int32_t occk_near_info(occk_tree* tree, int64_t* tasks, int64_t* quartets);
 
 /* Algorithmic flop model of one occk_far_J call (host only), Q = (L+1)^2:
  *   dens  2 Q npairs     density-contracted leaf multipoles

@@ -163,6 +163,27 @@ def near_K(setup, C: np.ndarray, i_range=None, j_range=None) -> np.ndarray:
     return K
 
 
+def near_K_rows(setup, C: np.ndarray, rows) -> np.ndarray:
+    """Rows r of K^nf (all i, all j): only the pairs (r, s) with that r and the
+    pairs of the leaves near theirs; for sampling a large system."""
+    t = setup.tree
+    r_all, s_all = setup.r, setup.s
+    out = np.zeros((len(rows), C.shape[1]))
+    for n, rr in enumerate(rows):
+        k1_all = np.nonzero(r_all == rr)[0]
+        for b1 in np.unique(t.pair_leaf[k1_all]):
+            k1 = k1_all[t.pair_leaf[k1_all] == b1]
+            for b2 in t.near_leaves(int(b1)):
+                k2 = setup.leaf_pairs[b2]
+                R, T = np.meshgrid(k1, k2, indexing="ij")
+                V = eri(setup.fn, r_all[R.ravel()], s_all[R.ravel()], r_all[T.ravel()],
+                        s_all[T.ravel()]).reshape(len(k1), len(k2))
+                # sum_j C_sj sum_(t,u) V C_tj C_ui
+                W = V.T @ C[s_all[k1]]                       # (k2, j)
+                out[n] += 2.0 * np.einsum("kj,kj,ki->i", W, C[r_all[k2]], C[s_all[k2]])
+    return out
+
+
 def all_K(setup, C: np.ndarray) -> np.ndarray:
     """The whole exchange K_ri = 2 sum_j (rj|ji) with exact integrals over
     every pair of screened distributions (no tree; for small systems)."""

@@ -23,7 +23,7 @@ HIP_FLAGS = [
 ]
 CXX_FLAGS = ["-O2", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
 
-HIP_SOURCES = ["far_k.hip", "batch.hip", "selector.hip", "far_j.hip"]
+HIP_SOURCES = ["far_k.hip", "batch.hip", "selector.hip", "far_j.hip", "near_k.hip"]
 CXX_SOURCES = ["tree_build.cpp", "abi.cpp"]
 
 

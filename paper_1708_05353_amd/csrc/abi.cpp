@@ -97,6 +97,7 @@ int32_t occk_free_tree(occk_tree* tree) {
   }
   device_free(t);
   jstate_free(t);
+  nstate_free(t);
   t->magic = 0;
   delete t;
   return OCCK_OK;
@@ -140,6 +141,18 @@ int32_t occk_tree_info(const occk_tree* tree, occk_tree_info_t* info) {
     info->mid[d] = t->mid[d];
   }
   info->width = t->W;
+  info->n_near = int64_t(t->near_idx.size());
+  return OCCK_OK;
+}
+
+int32_t occk_tree_near(const occk_tree* tree, int32_t* ptr, int32_t* idx) {
+  const Tree* t = reinterpret_cast<const Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_tree_near: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (ptr) std::copy(t->near_ptr.begin(), t->near_ptr.end(), ptr);
+  if (idx) std::copy(t->near_idx.begin(), t->near_idx.end(), idx);
   return OCCK_OK;
 }
 
@@ -343,6 +356,45 @@ int32_t occk_far_J(occk_tree* tree, const double* D, int64_t ldd, double* J, int
   OCCK_GUARD_BEGIN
   return far_J(t, D, ldd, J, ldj, accumulate, hip_stream);
   OCCK_GUARD_END
+}
+
+int32_t occk_near_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc, double* K, int64_t ldk,
+                    int32_t accumulate, void* hip_stream) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_near_K: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!C || !K || nocc <= 0 || ldc < nocc || ldk < nocc || (accumulate != 0 && accumulate != 1)) {
+    set_error("occk_near_K: C and K non-NULL, nocc > 0, ldc and ldk >= nocc, accumulate 0 or 1");
+    return OCCK_EINVAL;
+  }
+  if ((reinterpret_cast<uintptr_t>(C) | reinterpret_cast<uintptr_t>(K)) & 7) {
+    set_error("occk_near_K: C and K must be 8-byte aligned");
+    return OCCK_EINVAL;
+  }
+  {
+    const uintptr_t c0 = reinterpret_cast<uintptr_t>(C), c1 = c0 + uintptr_t(t->nbasis) * uintptr_t(ldc) * 8;
+    const uintptr_t k0 = reinterpret_cast<uintptr_t>(K), k1 = k0 + uintptr_t(t->nbasis) * uintptr_t(ldk) * 8;
+    if (c0 < k1 && k0 < c1) {
+      set_error("occk_near_K: K overlaps C");
+      return OCCK_EINVAL;
+    }
+  }
+  OCCK_GUARD_BEGIN
+  return near_K(t, C, ldc, nocc, K, ldk, accumulate, hip_stream);
+  OCCK_GUARD_END
+}
+
+int32_t occk_near_info(occk_tree* tree, int64_t* tasks, int64_t* quartets) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_near_info: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  const int32_t rc = near_K_counts(t, tasks, quartets);
+  if (rc != OCCK_OK) set_error("occk_near_info: no occk_near_K call on this handle yet");
+  return rc;
 }
 
 int32_t occk_tree_flops_J(const occk_tree* tree, occk_jflops_t* out) {

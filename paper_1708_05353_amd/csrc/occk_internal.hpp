@@ -21,6 +21,7 @@ struct Func {
   double exp;
   double norm;
   int pw[3];   // Cartesian powers (0/1)
+  int32_t shell;
 };
 
 // One screened ordered AO function pair.
@@ -40,6 +41,7 @@ struct OpDesc {
 
 struct DeviceState;   // defined in the HIP translation unit
 struct JState;        // device state of the Coulomb path (far_j.hip)
+struct NState;        // device state of the near-field exchange (near_k.hip)
 
 struct Tree {
   uint32_t magic = kTreeMagic;
@@ -54,6 +56,9 @@ struct Tree {
   std::vector<std::unordered_map<int64_t, int32_t>> index;
   // interaction lists per level: CSR over the boxes of that level
   std::vector<std::vector<int32_t>> il_ptr, il_idx;
+  // leaves near each leaf (itself included): the near field, CSR over the leaves
+  std::vector<int32_t> near_ptr, near_idx;
+  std::vector<int32_t> shell_first, shell_l;   // first function and l of every shell
   // leaves
   std::vector<std::vector<int32_t>> leaf_funcs;   // sorted function indices
   std::vector<std::vector<int32_t>> leaf_pairs;   // indices into pairs
@@ -67,6 +72,7 @@ struct Tree {
 
   DeviceState* dev = nullptr;
   JState* jdev = nullptr;     // device state of the Coulomb path (far_j.hip)
+  NState* ndev = nullptr;     // device state of the near-field path (near_k.hip)
   int profile = 0;
 
   double h(int level) const { return W / double(int64_t(1) << level); }
@@ -101,6 +107,10 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
 int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, int32_t i1,
                       int32_t j0, int32_t j1, const occk_far_opts* opts, double* K, int64_t ldk, void* stream);
 void jstate_free(Tree* t);
+void nstate_free(Tree* t);
+int32_t near_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, double* K, int64_t ldk, int32_t accumulate,
+               void* stream);
+int32_t near_K_counts(Tree* t, int64_t* tasks, int64_t* quartets);
 int32_t far_J(Tree* t, const double* D, int64_t ldd, double* J, int64_t ldj, int32_t accumulate, void* stream);
 int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);
 int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);

@@ -286,6 +286,14 @@ static void extent_lists(Tree& t, const std::vector<std::array<int32_t, 3>>& pc)
     }
     near_prev.swap(near_cur);
   }
+  // near_prev holds the leaf level's near lists: the near field
+  t.near_ptr.assign(1, 0);
+  t.near_idx.clear();
+  for (auto& v : near_prev) {
+    std::sort(v.begin(), v.end());
+    t.near_idx.insert(t.near_idx.end(), v.begin(), v.end());
+    t.near_ptr.push_back(int32_t(t.near_idx.size()));
+  }
 }
 
 Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
@@ -330,10 +338,13 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
         f.exp = e;
         if (sys->shell_l[s] == 1) f.pw[k] = 1;
         f.norm = std::pow(2.0 * e / M_PI, 0.75) * (sys->shell_l[s] == 1 ? 2.0 * std::sqrt(e) : 1.0);
+        f.shell = s;
         t.funcs.push_back(f);
       }
     }
     t.nbasis = int(t.funcs.size());
+    t.shell_first.assign(first.begin(), first.end() - 1);
+    t.shell_l.assign(sys->shell_l, sys->shell_l + sys->nshell);
     // screened ordered shell pairs -> function pairs
     const double thr = p->pair_log_thresh;
     const bool finite = std::isfinite(thr);
@@ -457,6 +468,31 @@ Tree* build_tree(const occk_system* sys, const occk_tree_params* p) {
         t.il_ptr[lev][b + 1] = int32_t(t.il_idx[lev].size());
       }
     }
+    }
+    if (p->near_rule != OCCK_NEAR_EXTENT) {   // near field of the box-index rule: leaves within ws
+      const int ws = p->ws;
+      const auto& lv = t.boxes[D];
+      t.near_ptr.assign(1, 0);
+      t.near_idx.clear();
+      for (size_t b = 0; b < lv.size(); ++b) {
+        const size_t e0 = t.near_idx.size();
+        for (int dz = -ws; dz <= ws; ++dz)
+          for (int dy = -ws; dy <= ws; ++dy)
+            for (int dx = -ws; dx <= ws; ++dx) {
+              const int32_t c[3] = {lv[b][0] + dx, lv[b][1] + dy, lv[b][2] + dz};
+              bool out = false;
+              for (int d = 0; d < 3; ++d) {
+                if (c[d] < 0 || c[d] >= nside) out = true;
+                if (!((p->split_mask >> d) & 1) && c[d] != 0) out = true;
+              }
+              if (out) continue;
+              auto it = t.index[D].find(coord_key(c[0], c[1], c[2]));
+              if (it == t.index[D].end()) continue;
+              t.near_idx.push_back(it->second);
+            }
+        std::sort(t.near_idx.begin() + int64_t(e0), t.near_idx.end());
+        t.near_ptr.push_back(int32_t(t.near_idx.size()));
+      }
     }
     for (int lev = 0; lev <= D; ++lev)
       if (t.lmin < 0 && !t.il_idx[lev].empty()) t.lmin = lev;

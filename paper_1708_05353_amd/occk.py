@@ -44,7 +44,7 @@ class _Info(ct.Structure):
                 ("n_edges", ct.c_int64), ("npairs", ct.c_int64), ("sum_nb", ct.c_int64),
                 ("sum_nb2", ct.c_int64), ("max_nb", ct.c_int32), ("n_ops", ct.c_int32),
                 ("m2m_nnz", ct.c_int64), ("lo", ct.c_double * 3), ("width", ct.c_double),
-                ("mid", ct.c_double * 3)]
+                ("mid", ct.c_double * 3), ("n_near", ct.c_int64)]
 
 
 class _Flops(ct.Structure):
@@ -70,6 +70,10 @@ EXPORTS = {
     "occk_tree_flops_J": (ct.c_int32, [ct.c_void_p, ct.POINTER(_JFlops)]),
     "occk_far_J": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_void_p, ct.c_int64, ct.c_int32,
                                 ct.c_void_p]),
+    "occk_near_K": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_int64, ct.c_int32, ct.c_void_p, ct.c_int64,
+                                 ct.c_int32, ct.c_void_p]),
+    "occk_near_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)]),
+    "occk_tree_near": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "occk_tree_export": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p]),
     "occk_tree_leaf": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.c_void_p,
@@ -168,6 +172,7 @@ class TreeInfo:
     lo: tuple
     width: float
     mid: tuple
+    n_near: int
 
 
 class Tree:
@@ -195,7 +200,7 @@ class Tree:
         return TreeInfo(inf.nbasis, inf.lmax, inf.ncomp, inf.depth, inf.lmin, inf.nleaf, inf.nbox,
                         list(inf.boxes_per_level)[: inf.depth + 1], list(inf.il_per_level)[: inf.depth + 1],
                         inf.n_il, inf.n_edges, inf.npairs, inf.sum_nb, inf.sum_nb2, inf.max_nb, inf.n_ops,
-                        inf.m2m_nnz, tuple(inf.lo), inf.width, tuple(inf.mid))
+                        inf.m2m_nnz, tuple(inf.lo), inf.width, tuple(inf.mid), inf.n_near)
 
     @property
     def handle(self):
@@ -211,6 +216,14 @@ class Tree:
         _check(lib().occk_tree_export(self._h, leaf.ctypes.data, lev.ctypes.data, tgt.ctypes.data,
                                       src.ctypes.data, pl.ctypes.data))
         return leaf, lev, tgt, src, pl
+
+    def near(self):
+        """The near field: for every leaf, the sorted list of leaves near it."""
+        inf = self.info
+        ptr = np.zeros(inf.nleaf + 1, np.int32)
+        idx = np.zeros(max(1, inf.n_near), np.int32)
+        _check(lib().occk_tree_near(self._h, ptr.ctypes.data, idx.ctypes.data))
+        return [idx[ptr[b]:ptr[b + 1]].tolist() for b in range(inf.nleaf)]
 
     def leaf(self, b: int):
         nb = ct.c_int32()
@@ -334,6 +347,27 @@ def far_J(tree: Tree, D, J, accumulate: bool = False, stream=None):
         stream = torch.cuda.current_stream(D.device)
     _check(lib().occk_far_J(tree.handle, ct.c_void_p(D.data_ptr()), int(D.stride(0)), ct.c_void_p(J.data_ptr()),
                             int(J.stride(0)), int(bool(accumulate)), ct.c_void_p(stream.cuda_stream)))
+
+
+def near_K(tree: Tree, C, K, accumulate: bool = False, stream=None):
+    """K (+)= K^nf of the occupied orbitals C on the GPU (occk_near_K).  C, K:
+    row-major float64 CUDA tensors (nbasis, ld); asynchronous on ``stream``."""
+    import torch
+    for t in (C, K):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.dim() == 2 and t.stride(1) == 1):
+            raise ValueError("C and K must be row-major 2-D float64 CUDA tensors")
+    if stream is None:
+        stream = torch.cuda.current_stream(C.device)
+    _check(lib().occk_near_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), int(C.shape[1]),
+                             ct.c_void_p(K.data_ptr()), int(K.stride(0)), int(bool(accumulate)),
+                             ct.c_void_p(stream.cuda_stream)))
+
+
+def near_info(tree: Tree) -> tuple:
+    """(wave tasks, shell quartets) of one occk_near_K call on the tree."""
+    a, b = ct.c_int64(), ct.c_int64()
+    _check(lib().occk_near_info(tree.handle, ct.byref(a), ct.byref(b)))
+    return a.value, b.value
 
 
 def debug_mfma_probe(kind: int, ia: int, ka: int, jb: int) -> np.ndarray:

@@ -14,6 +14,9 @@ static int32_t no_gpu() {
 
 void device_free(Tree*) {}
 void jstate_free(Tree*) {}
+void nstate_free(Tree*) {}
+int32_t near_K(Tree*, const double*, int64_t, int32_t, double*, int64_t, int32_t, void*) { return no_gpu(); }
+int32_t near_K_counts(Tree*, int64_t*, int64_t*) { return no_gpu(); }
 int32_t far_J(Tree*, const double*, int64_t, double*, int64_t, int32_t, void*) { return no_gpu(); }
 int32_t far_K(Tree*, const double*, int64_t, int32_t, int32_t, int32_t, int32_t, int32_t, const occk_far_opts*,
               double*, int64_t, void*) { return no_gpu(); }

@@ -97,6 +97,28 @@ def test_extent_rule_lists_match_oracle(case, ws):
     tr.free()
 
 
+@pytest.mark.parametrize("case,rule", [("chain", 0), ("sheet", 0), ("water", 0), ("chain", 1), ("sheet", 1),
+                                       ("water", 1)])
+def test_near_field_lists_match_oracle(case, rule):
+    """The leaf-level near relation (the near field) of both rules: library
+    against the oracle tree."""
+    from scipy.special import erfcinv
+    from oracle.basis import Functions, function_pairs
+    from oracle.tree import Tree as OTree
+    wl = {"chain": workloads.tiny_chain, "sheet": lambda: workloads.graphene_flake(n=3, nocc=20, depth=4),
+          "water": lambda: workloads.water_cluster(20, 40)}[case]()
+    p = with_params(wl, near_rule=rule, ext_ws=0.0, ext_tau=1e-8)
+    tr = occk.Tree(wl.system, p)
+    fn = Functions(wl.system)
+    r, s, P = function_pairs(wl.system, fn, p.pair_log_thresh)
+    ext = erfcinv(1e-8) / np.sqrt(fn.exp[r] + fn.exp[s]) if rule == 1 else None
+    ot = OTree(P, p.split_mask, p.depth, 0.0 if rule == 1 else p.ws, extents=ext)
+    got = tr.near()
+    assert got == [ot.near_leaves(b) for b in range(len(ot.boxes[ot.depth]))]
+    assert tr.info.n_near == sum(len(v) for v in got)
+    tr.free()
+
+
 def test_info_counts_tiny_chain():
     wl = workloads.tiny_chain()
     tr = occk.Tree(wl.system, wl.params)

@@ -21,7 +21,7 @@ import pytest
 import workloads
 from oracle import fmm
 from oracle.basis import Functions, ao_multipoles
-from oracle.eri import all_K, eri, near_K
+from oracle.eri import all_K, eri, near_K, near_K_rows
 from oracle.exact import eri_s
 
 from conftest import rel, with_params
@@ -144,3 +144,13 @@ def test_near_plus_far_is_the_whole_exchange():
     assert np.abs(Kf).max() > 1e-6 * np.abs(Ka).max()    # the far field is not empty
     assert rel(Kn + Kf, Ka) <= 1e-7
     assert rel(Kn, Ka) > 1e-5                             # the near field alone is not the whole
+
+
+def test_sampled_rows_equal_the_full_near_field():
+    from oracle.fmm import Setup
+    wl = workloads.sp_chain(n=8)
+    st = Setup(wl.system, with_params(wl, lmax=0))
+    C = wl.orbitals()
+    K = near_K(st, C)
+    rows = [0, 7, 21, 39]
+    assert rel(near_K_rows(st, C, rows), K[rows]) <= 1e-13
