@@ -211,6 +211,39 @@ def bench_coulomb(wl, Cd, args, stream):
             "tree_build_s": round(t_tree, 2), "first_call_s": round(t_first, 2)}
 
 
+def bench_near(wl, Cd, args, stream):
+    """Near-field exchange of the same workload with exact s/p integrals
+    (occk_near_K, FP64): the near leaf pairs of the tree, all occupied
+    orbitals, one call per step.  Reported: time, shell quartets per second,
+    and the two dense GEMMs (D = 2 C C^T, K = X C) that bracket the integrals."""
+    import torch
+    from paper_1708_05353_amd import occk
+    tree = occk.Tree(wl.system, wl.params)
+    K = torch.zeros((wl.system.nbasis, Cd.shape[1]), dtype=torch.float64, device=Cd.device)
+    call = lambda: occk.near_K(tree, Cd, K, stream=stream)
+    t0 = time.perf_counter()
+    call()                       # builds the shell-pair tables
+    torch.cuda.synchronize()
+    t_first = time.perf_counter() - t0
+    for _ in range(args.warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    tasks, quartets = occk.near_info(tree)
+    n, no = wl.system.nbasis, Cd.shape[1]
+    gemm = 2 * 2 * n * n * no
+    tree.free()
+    return {"ms_per_step": round(ms, 3), "shell_quartets": quartets, "wave_tasks": tasks,
+            "Gquartets/s": round(quartets / (ms * 1e-3) / 1e9, 2), "gemm_flops": gemm,
+            "first_call_s": round(t_first, 2)}
+
+
 def cpu_model() -> str:
     """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -715,6 +748,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 mixed-path comparison")
     ap.add_argument("--no-coulomb", action="store_true", help="skip the far-field Coulomb J leg")
+    ap.add_argument("--no-near", action="store_true", help="skip the near-field exchange leg")
     ap.add_argument("--cpu-sample-j", type=int, default=16)
     ap.add_argument("--cpu-repeats", type=int, default=2)
     args = ap.parse_args()
@@ -890,6 +924,9 @@ def main():
                         "speedup_vs_fp64": round(ms / ms_m, 3), "rel_err_vs_fp64": err, "bound": 1e-6}
         print(f"[bench] mixed fp32 {ms_m:.2f} ms/step, x{ms / ms_m:.2f}, rel err {err:.2e}", file=sys.stderr,
               flush=True)
+    if args.precision == "fp64" and not args.no_near:
+        out["near_K"] = bench_near(wl, Cd, args, stream)
+        print(f"[bench] near-field K {out['near_K']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
     if args.precision == "fp64" and not args.no_coulomb:
         out["far_J"] = bench_coulomb(wl, Cd, args, stream)
         print(f"[bench] far-field J (L^J=10) {out['far_J']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
