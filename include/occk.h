@@ -138,6 +138,22 @@ typedef struct occk_far_opts {
   const occk_selector* selector;
   int32_t jblock;              /* occupied j columns per batch, 0 = automatic */
   int32_t accumulate;          /* 0: K[:, i0:i1] = K^ff, 1: K[:, i0:i1] += K^ff */
+  double pair_thresh;          /* occupied-pair screening for localised orbitals
+                                  (Conclusion: localised orbitals and screening of
+                                  occupied pairs), 0 = off.  With n_Ai the sum of
+                                  |C_ti| over the functions t centred in leaf A
+                                  and W_AA' the largest Gaussian product factor
+                                  exp(-ab/(a+b)|A-B|^2) of a screened function
+                                  pair with one function centred in A and the
+                                  other in A', the pair (i, j) is kept when
+                                  b_ij = sum_(A,A') n_Aj W_AA' n_A'i >= pair_thresh
+                                  (b_ij bounds sum over screened pairs (t, u) of
+                                  their factor times |C_tj| |C_ui|).  A j batch
+                                  then carries i only up to the last kept i of
+                                  its j (orbitals ordered along the system make
+                                  this a band), so every pair inside the band is
+                                  evaluated, kept or not.  Needs i0 == j0 and
+                                  i1 == j1; synchronises the stream once per call */
 } occk_far_opts;
 
 /* Returns OCCK_ABI_VERSION. */
@@ -308,6 +324,17 @@ typedef struct occk_jflops_t {
   int64_t dens, m2m, m2l, l2l, pair, total;
 } occk_jflops_t;
 int32_t occk_tree_flops_J(const occk_tree* tree, occk_jflops_t* out);
+
+/* The band of the handle's last occk_far_K with pair_thresh > 0 (host only):
+ * *carried = the (j, i) columns it carried through the translations,
+ * *jblock = its j batch width, *nband = its number of j batches, and
+ * band_end[k] (k < min(cap, *nband)) = the end (exclusive, relative to i0)
+ * of the i range carried by batch k, whose j are [k jblock, (k+1) jblock)
+ * relative to j0.  Zeros before such a call.  band_end may be NULL when
+ * cap is 0; the other pointers must be valid.  OCCK_EINVAL for a NULL
+ * pointer or negative cap. */
+int32_t occk_pair_screen_info(occk_tree* tree, int64_t* carried, int32_t* jblock, int32_t* band_end, int32_t cap,
+                              int32_t* nband);
 
 /* Workspace of the handle's last occk_far_K: the j batch width used (-1
  * before the first call) and the device bytes held by the handle.  Either

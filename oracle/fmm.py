@@ -12,6 +12,12 @@ Steps, in the paper's order:
   6. K^ff_ri = 2 sum_X sum_j sum_lm O^{rj,X}_{lm} Mloc^{ij}_{lm}(X), Eq. (18) with the
      factor 2 of Eq. (5) and the sum over leaf boxes X made explicit.
 
+``pair_bound`` / ``pair_screen`` give the occupied-pair screening for
+localised orbitals (the Conclusion's proposal): keep (i, j) when the bound
+b_ij on sum_(t,u) K_tu |C_tj| |C_ui| over the screened pairs reaches the
+threshold; ``band_ends`` / ``band_mask`` give the pairs a banded j-batch
+schedule evaluates, and ``far_K(pair_mask=...)`` the far field of a pair set.
+
 ``far_J`` is the far-field Coulomb matrix through the same tree and
 translations, with one density-contracted column (the Coulomb passage of the
 Theory section, Eq. 10).
@@ -255,11 +261,14 @@ def far_J_direct(setup: Setup, Dm: np.ndarray, nquad=None):
 
 
 def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int = 64,
-          return_imag: bool = False, m2l_rank=None):
+          return_imag: bool = False, m2l_rank=None, pair_mask=None):
     """K^ff[:, i0:i1] = 2 sum_{j in [j0,j1)} (rj|ji)_ff by the hierarchical FMM.
 
     m2l_rank: optional int p (0 <= p <= L) applied to every interaction-list
-    translation (l, l' <= p), the uniform version of a per-interaction rank."""
+    translation (l, l' <= p), the uniform version of a per-interaction rank.
+    pair_mask: optional boolean (nocc, nocc) array, symmetric: only the
+    occupied pairs (i, j) it keeps contribute (occupied-pair screening; the
+    pair's multipoles, and so everything translated from them, are dropped)."""
     t, L = setup.tree, setup.L
     nocc = C.shape[1]
     i0, i1, j0, j1 = _ranges(nocc, i_range, j_range)
@@ -275,7 +284,10 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
         for b in range(setup.nleaf):
             h = setup.half(b, C[:, jb0:jb1])                                     # O^{rj}_q = O^{rs}_q C_sj
             Hb.append(h)
-            Om[D].append(np.matmul(C[setup.leaf_funcs[b], i0:i1].T, h))          # O^{ij}_q = sum_r C_ri O^{rj}_q
+            om = np.matmul(C[setup.leaf_funcs[b], i0:i1].T, h)                   # O^{ij}_q = sum_r C_ri O^{rj}_q
+            if pair_mask is not None:
+                om = om * pair_mask[i0:i1, jb0:jb1][None]
+            Om[D].append(om)
         # Step 3: upward
         for lev in range(D - 1, t.lmin - 1, -1):
             acc = [np.zeros_like(Om[D][0]) for _ in t.boxes[lev]]
@@ -303,6 +315,72 @@ def far_K(setup: Setup, C: np.ndarray, i_range=None, j_range=None, jblock: int =
     if return_imag:
         return K.real, float(np.abs(K.imag).max())
     return K.real
+
+
+def pair_bound(setup: Setup, C: np.ndarray) -> np.ndarray:
+    """Bound b_ij for occupied-pair screening with localised orbitals
+    (Conclusion: localised orbitals and the screening of occupied pairs).
+
+    Every function has a home leaf, the leaf holding its centre (that of its
+    pair with itself).  With n_Ai = sum of |C_ti| over the functions t of home
+    leaf A, and W_AA' = the largest Gaussian product factor
+    K_tu = exp(-a_t a_u / (a_t + a_u) |A_t - A_u|^2) over the screened pairs
+    (t, u) with t at home in A and u in A',
+
+        b_ij = sum_(A, A') n_Aj W_AA' n_A'i  >=  sum_(t,u) K_tu |C_tj| |C_ui|,
+
+    the sum on the right running over the screened pairs."""
+    fn, r, s = setup.fn, setup.r, setup.s
+    nl = setup.nleaf
+    home = np.full(setup.nbasis, -1, dtype=np.int64)
+    self_pair = r == s
+    home[r[self_pair]] = setup.tree.pair_leaf[self_pair]
+    if (home < 0).any():
+        raise ValueError("a function without its pair with itself")
+    a, b = fn.exp[r], fn.exp[s]
+    Ktu = np.exp(-(a * b / (a + b)) * ((fn.center[r] - fn.center[s]) ** 2).sum(1))
+    W = np.zeros((nl, nl))
+    np.maximum.at(W, (home[r], home[s]), Ktu)
+    N = np.zeros((nl, C.shape[1]))
+    np.add.at(N, home, np.abs(C))
+    return N.T @ W @ N          # [j, i]
+
+
+def pair_screen(setup: Setup, C: np.ndarray, thresh: float) -> np.ndarray:
+    """Occupied-pair mask: (i, j) kept when b_ij >= thresh or b_ji >= thresh
+    (pair_bound)."""
+    B = pair_bound(setup, C)
+    return (B >= thresh) | (B.T >= thresh)
+
+
+def band_ends(setup: Setup, C: np.ndarray, thresh: float, jblock: int) -> np.ndarray:
+    """i end (exclusive) of every j batch of a banded schedule: batch k,
+    j in [k jblock, (k+1) jblock), carries every i below one past the last
+    i > j whose pair bound b_ji (pair_bound) reaches thresh, and at least
+    up to its own last j."""
+    B = pair_bound(setup, C)
+    n = C.shape[1]
+    ends = []
+    for j0 in range(0, n, jblock):
+        j1 = min(n, j0 + jblock)
+        e = j1
+        for j in range(j0, j1):
+            kept = np.nonzero(B[j, j + 1:] >= thresh)[0]
+            if kept.size:
+                e = max(e, j + 1 + int(kept[-1]) + 1)
+        ends.append(e)
+    return np.array(ends, dtype=np.int64)
+
+
+def band_mask(nocc: int, jblock: int, band_end) -> np.ndarray:
+    """The (i, j) pairs a banded schedule evaluates: j batch k = [k jblock,
+    (k+1) jblock) carries i < band_end[k], and the pair (i, j) is evaluated
+    once, by the batch of min(i, j)."""
+    m = np.zeros((nocc, nocc), dtype=bool)
+    for k, e in enumerate(band_end):
+        j0, j1 = k * jblock, min(nocc, (k + 1) * jblock)
+        m[j0:j1, j0:int(e)] = True
+    return m | m.T
 
 
 def far_K_direct(setup: Setup, C: np.ndarray, i_range=None, j_range=None, nquad=None):

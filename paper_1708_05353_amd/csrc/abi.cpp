@@ -296,6 +296,11 @@ static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc
     set_error(f + ": jblock must be >= 0");
     return OCCK_EINVAL;
   }
+  if (!(o.pair_thresh >= 0.0) || !std::isfinite(o.pair_thresh) ||
+      (o.pair_thresh > 0.0 && (i0 != j0 || i1 != j1))) {
+    set_error(f + ": pair_thresh must be finite and >= 0, and screening needs i0 == j0 and i1 == j1");
+    return OCCK_EINVAL;
+  }
   return OCCK_OK;
 }
 
@@ -320,8 +325,8 @@ int32_t occk_far_K_noalloc(occk_tree* tree, const double* C, int64_t ldc, int32_
   occk_far_opts o{};
   const int32_t rc = check_far_K("occk_far_K_noalloc", t, C, ldc, nocc, i0, i1, j0, j1, opts, K, ldk, o);
   if (rc != OCCK_OK) return rc;
-  if (o.precision != OCCK_PREC_FP64 || o.rank_mode != OCCK_RANK_FIXED) {
-    set_error("occk_far_K_noalloc: only FP64 with fixed rank");
+  if (o.precision != OCCK_PREC_FP64 || o.rank_mode != OCCK_RANK_FIXED || o.pair_thresh != 0.0) {
+    set_error("occk_far_K_noalloc: only FP64 with fixed rank and no pair screening");
     return OCCK_EINVAL;
   }
   OCCK_GUARD_BEGIN
@@ -384,6 +389,20 @@ int32_t occk_near_K(occk_tree* tree, const double* C, int64_t ldc, int32_t nocc,
   OCCK_GUARD_BEGIN
   return near_K(t, C, ldc, nocc, K, ldk, accumulate, hip_stream);
   OCCK_GUARD_END
+}
+
+int32_t occk_pair_screen_info(occk_tree* tree, int64_t* carried, int32_t* jblock, int32_t* band_end, int32_t cap,
+                              int32_t* nband) {
+  Tree* t = reinterpret_cast<Tree*>(tree);
+  if (!live(t)) {
+    set_error("occk_pair_screen_info: handle is not live");
+    return OCCK_EHANDLE;
+  }
+  if (!carried || !jblock || !nband || cap < 0 || (cap > 0 && !band_end)) {
+    set_error("occk_pair_screen_info: NULL pointer or negative cap");
+    return OCCK_EINVAL;
+  }
+  return pair_screen_info(t, carried, jblock, band_end, cap, nband);
 }
 
 int32_t occk_near_info(occk_tree* tree, int64_t* tasks, int64_t* quartets) {
@@ -492,8 +511,8 @@ int32_t occk_batch_create(int32_t nsys, occk_tree* const* trees, const int32_t* 
     set_error("occk_batch_create: unknown precision");
     return OCCK_EINVAL;
   }
-  if (o.rank_mode != OCCK_RANK_FIXED) {
-    set_error("occk_batch_create: only fixed ranks are batched");
+  if (o.rank_mode != OCCK_RANK_FIXED || o.pair_thresh != 0.0) {
+    set_error("occk_batch_create: only fixed ranks without pair screening are batched");
     return OCCK_EINVAL;
   }
   if (o.jblock < 0) {

@@ -189,7 +189,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           break;
         case kTTrans: {     // pass a, logical blocks [b, b + trans_group)
           const BPass P = load_const(passes + S.pass0 + tk.a);
-          const ColMap cm{S.ncol, int64_t(n), int64_t(jrel), int64_t(jb) * (n - jrel)};
+          const ColMap cm{S.ncol, int64_t(n), int64_t(jrel), int64_t(jb) * (n - jrel), 0};
           const int64_t nct = (cm.nvalid + trans_block_cols(S.Q) - 1) / trans_block_cols(S.Q);
           const int64_t nblocks = nct * P.ntgt;
           const int64_t e1 = (nblocks < int64_t(tk.b) + trans_group) ? nblocks : int64_t(tk.b) + trans_group;

@@ -177,6 +177,16 @@ struct DeviceState {
   std::vector<int> ev_class;
   std::vector<size_t> ev_idx;       // first event of each recorded pair (scopes may nest)
   std::vector<int64_t> launches;
+  // occupied-pair screening
+  DevBuf<int32_t> home_off, home_fn;   // CSR: the functions centred in each leaf (home leaf)
+  DevBuf<int32_t> hw_ptr, hw_idx;      // CSR: leaves joined to each leaf by a screened pair
+  DevBuf<double> hw_val;               // largest Gaussian product factor over those pairs
+  DevBuf<double> band_nrm;        // [nleaf][ni] l1 norms of C over the home functions
+  DevBuf<double> band_spread;     // [nleaf][ni] the same spread over joined leaves
+  DevBuf<int32_t> band_last;      // [ni] last kept i of every j
+  std::vector<int32_t> band_end;  // i end of every j batch in the last screened call
+  int32_t band_jb = 0;            // its j batch width
+  int64_t last_band_cols = 0;     // carried columns of the last screened call
   // learned ranks
   DevBuf<float> box_norm;         // [nbox][L+1] multipole norms of the current batch
   DevBuf<int64_t> rank_hist;      // M2L entries per chosen rank (accumulated)

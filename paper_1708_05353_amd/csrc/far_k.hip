@@ -653,6 +653,156 @@ int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
   return std::max(1, jb);
 }
 
+// Occupied-pair screening (localised orbitals).  With n_Ai the l1 norm of
+// orbital i over the functions centred in leaf A (its home leaf) and
+// W_AA' the largest Gaussian product factor exp(-ab/(a+b)|A-B|^2) of a
+// screened function pair joining the two, the bound
+//   b_ij = sum_(A,A') n_Aj W_AA' n_A'i >= sum_(t,u) K_tu |C_tj| |C_ui|
+// holds over every screened pair (t, u); (i, j) is carried when b_ij >= tau.
+// nrm[A][i] = n_Ai.
+static __global__ void homenorm_kernel(const double* __restrict__ C, int64_t ldc, int i0, int ni,
+                                       const int32_t* __restrict__ hfn, const int32_t* __restrict__ hoff,
+                                       double* __restrict__ nrm) {
+  const int a = blockIdx.y;
+  const int i = int(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= ni) return;
+  double s = 0.0;
+  for (int e = hoff[a]; e < hoff[a + 1]; ++e) s += fabs(C[int64_t(hfn[e]) * ldc + i0 + i]);
+  nrm[int64_t(a) * ni + i] = s;
+}
+
+// spread[A][i] = sum_A' W_AA' nrm[A'][i].
+static __global__ void homespread_kernel(const double* __restrict__ nrm, int ni, const int32_t* __restrict__ wptr,
+                                         const int32_t* __restrict__ widx, const double* __restrict__ wval,
+                                         double* __restrict__ spread) {
+  const int a = blockIdx.y;
+  const int i = int(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= ni) return;
+  double s = 0.0;
+  for (int e = wptr[a]; e < wptr[a + 1]; ++e) s = fma(wval[e], nrm[int64_t(widx[e]) * ni + i], s);
+  spread[int64_t(a) * ni + i] = s;
+}
+
+// last[j] = the largest i > j with b_ij = sum_A nrm[A][j] spread[A][i] >= thresh,
+// j itself when none; one block per j.
+static __global__ __launch_bounds__(256) void pairband_kernel(const double* __restrict__ nrm,
+                                                              const double* __restrict__ spread, int nleaf, int ni,
+                                                              double thresh, int32_t* __restrict__ last) {
+  __shared__ double nj[1024];
+  __shared__ int32_t best[256];
+  const int j = blockIdx.x;
+  const int nchunk = (nleaf + 1023) / 1024;
+  int32_t mine = j;
+  // i strides over the threads; each i sums every leaf chunk before its test
+  if (nchunk == 1) {
+    for (int a = threadIdx.x; a < nleaf; a += 256) nj[a] = nrm[int64_t(a) * ni + j];
+    __syncthreads();
+  }
+  for (int ib = j + 1; ib < ni; ib += 256) {
+    const int i = ib + int(threadIdx.x);
+    double b = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+      const int a0 = c * 1024;
+      const int na = min(1024, nleaf - a0);
+      if (nchunk > 1) {
+        __syncthreads();
+        for (int a = threadIdx.x; a < na; a += 256) nj[a] = nrm[int64_t(a0 + a) * ni + j];
+        __syncthreads();
+      }
+      if (i < ni)
+        for (int a = 0; a < na; ++a) b = fma(nj[a], spread[int64_t(a0 + a) * ni + i], b);
+    }
+    if (i < ni && b >= thresh) mine = i;
+  }
+  best[threadIdx.x] = mine;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) best[threadIdx.x] = max(best[threadIdx.x], best[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) last[j] = best[0];
+}
+
+static __global__ void zero_kernel(double* __restrict__ x, int64_t count) {
+  for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < count; e += int64_t(gridDim.x) * blockDim.x)
+    x[e] = 0.0;
+}
+
+// Host tables of the screening bound: the home leaf of every function (the
+// leaf of its pair with itself, which sits on its centre) and the leaf-leaf
+// factors W_AA'.
+static void upload_home_tables(Tree* t, DeviceState* ds) {
+  const int nl = t->nleaf();
+  std::vector<int32_t> home(t->funcs.size(), -1);
+  for (const Pair& p : t->pairs)
+    if (p.r == p.s) home[size_t(p.r)] = p.leaf;
+  std::vector<int32_t> hoff(size_t(nl) + 1, 0), hfn(t->funcs.size());
+  for (size_t f = 0; f < home.size(); ++f) {
+    if (home[f] < 0) throw std::runtime_error("pair screening: a function has no pair with itself");
+    ++hoff[size_t(home[f]) + 1];
+  }
+  for (int a = 0; a < nl; ++a) hoff[size_t(a) + 1] += hoff[size_t(a)];
+  std::vector<int32_t> fill(hoff.begin(), hoff.end() - 1);
+  for (size_t f = 0; f < home.size(); ++f) hfn[size_t(fill[size_t(home[f])]++)] = int32_t(f);
+  std::vector<std::unordered_map<int32_t, double>> w(static_cast<size_t>(nl));
+  for (const Pair& p : t->pairs) {
+    const Func& fr = t->funcs[size_t(p.r)];
+    const Func& fs = t->funcs[size_t(p.s)];
+    double d2 = 0.0;
+    for (int d = 0; d < 3; ++d) d2 += (fr.c[d] - fs.c[d]) * (fr.c[d] - fs.c[d]);
+    const double k = std::exp(-fr.exp * fs.exp / (fr.exp + fs.exp) * d2);
+    double& e = w[size_t(home[size_t(p.r)])][home[size_t(p.s)]];
+    e = std::max(e, k);
+  }
+  std::vector<int32_t> wptr(size_t(nl) + 1, 0), widx;
+  std::vector<double> wval;
+  for (int a = 0; a < nl; ++a) {
+    std::vector<std::pair<int32_t, double>> row(w[size_t(a)].begin(), w[size_t(a)].end());
+    std::sort(row.begin(), row.end());
+    for (const auto& e : row) {
+      widx.push_back(e.first);
+      wval.push_back(e.second);
+    }
+    wptr[size_t(a) + 1] = int32_t(widx.size());
+  }
+  ds->home_off.upload(hoff);
+  ds->home_fn.upload(hfn);
+  ds->hw_ptr.upload(wptr);
+  ds->hw_idx.upload(widx);
+  ds->hw_val.upload(wval);
+}
+
+// The i end of every j batch under occupied-pair screening: the largest
+// carried i of the batch's j (at least the batch's own end).  Copies ni
+// integers to the host (the call synchronises its stream here).
+static std::vector<int> pair_bands(Tree* t, DeviceState* ds, const double* C, int64_t ldc, int i0, int ni, int jb,
+                                   double thresh, hipStream_t st) {
+  const int nl = t->nleaf();
+  if (!ds->home_off.p) upload_home_tables(t, ds);
+  ds->band_nrm.alloc(size_t(nl) * size_t(ni));
+  ds->band_spread.alloc(size_t(nl) * size_t(ni));
+  ds->band_last.alloc(size_t(ni));
+  const dim3 grid(unsigned((ni + 255) / 256), unsigned(nl));
+  hipLaunchKernelGGL(homenorm_kernel, grid, dim3(256), 0, st, C, ldc, i0, ni, ds->home_fn.p, ds->home_off.p,
+                     ds->band_nrm.p);
+  hipLaunchKernelGGL(homespread_kernel, grid, dim3(256), 0, st, ds->band_nrm.p, ni, ds->hw_ptr.p, ds->hw_idx.p,
+                     ds->hw_val.p, ds->band_spread.p);
+  hipLaunchKernelGGL(pairband_kernel, dim3(unsigned(ni)), dim3(256), 0, st, ds->band_nrm.p, ds->band_spread.p, nl, ni,
+                     thresh, ds->band_last.p);
+  HIP_OK(hipGetLastError());
+  std::vector<int32_t> last(static_cast<size_t>(ni));
+  HIP_OK(hipMemcpyAsync(last.data(), ds->band_last.p, size_t(ni) * 4, hipMemcpyDeviceToHost, st));
+  HIP_OK(hipStreamSynchronize(st));
+  std::vector<int> band;
+  for (int j0b = 0; j0b < ni; j0b += jb) {
+    const int j1b = std::min(ni, j0b + jb);
+    int e = j1b;
+    for (int j = j0b; j < j1b; ++j) e = std::max(e, int(last[size_t(j)]) + 1);
+    band.push_back(std::min(e, ni));
+  }
+  return band;
+}
+
 // The j batches.  Per batch J = [jstart, jstart + jb): half transform,
 // Omega, upward, downward, L2P.
 //
@@ -668,7 +818,7 @@ int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
 template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
                         int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
-                        bool stop_after_up = false, bool sym = false) {
+                        bool stop_after_up = false, bool sym = false, const std::vector<int>* band = nullptr) {
   using T = typename ModeT<MODE>::T;
   const int Q = t->Q;
   const int64_t ncol = int64_t(jb) * ni;
@@ -692,11 +842,14 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     const int64_t jstart = j0 + jrel;
     const int64_t istart = sym ? jrel : 0;         // first carried i (relative to i0)
     const int jbk = int(std::min<int64_t>(jb, nj - jrel));
+    // occupied-pair screening: the batch carries i in [istart, iend) only
+    const int64_t iend = band ? int64_t((*band)[size_t(kb)]) : int64_t(ni);
     ColMap cm;
     cm.ncol = ncol;
     cm.ni = ni;
     cm.istart = istart;
-    cm.nvalid = int64_t(jb) * (ni - istart);
+    cm.iend = band ? iend : 0;
+    cm.nvalid = int64_t(jb) * (iend - istart);
     const int ct0 = int(istart / 64);              // first column tile touching i >= istart
     {
       ProfScope ps(ds, prof, OCCK_K_HALF, st);
@@ -712,6 +865,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       GemmRun r{};
       r.boff = i0;
       r.blim = i1;
+      r.nhi = band ? int(iend) : 0;
       r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
       r.ntiles = ds->omega_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
       hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
@@ -749,10 +903,11 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       }
     }
     {
-      ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < ni ? 2 : 1);
+      ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < iend ? 2 : 1);
       GemmRun r{};
-      r.accumulate = kb > 0 ? 1 : 0;
+      r.accumulate = (kb > 0 || band) ? 1 : 0;   // with screening KB starts cleared
       r.nlo = int(istart);
+      r.nhi = band ? int(iend) : 0;
       ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, st);
       if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
         r.tile0 = ds->l2pw_nt_start[size_t(ct0 / 4)];
@@ -766,10 +921,11 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
                            ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       }
       ps_d.close();
-      if (sym && jrel + jb < ni) {
+      if (sym && jrel + jb < iend) {
         ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, st);
         GemmRun m{};
         m.accumulate = 1;
+        m.klim = band ? int(iend) : 0;
         m.koff = jrel + jb;
         m.coff = jrel;
         m.mlim = jbk;
@@ -847,14 +1003,28 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       ds->Cf.alloc(size_t(nbasis) * nocc);
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
+    std::vector<int> band;
+    const std::vector<int>* bp = nullptr;
+    if (opts->pair_thresh > 0.0) {   // occupied-pair screening (checked: symmetric ranges)
+      band = pair_bands(t, ds, C, ldc, i0, ni, jb, opts->pair_thresh, st);
+      bp = &band;
+      hipLaunchKernelGGL(zero_kernel, dim3(2048), dim3(256), 0, st, ds->KB.p, int64_t(ds->KB.n));
+      ds->last_band_cols = 0;
+      for (size_t k = 0; k < band.size(); ++k) {
+        const int64_t jlo = int64_t(k) * jb;
+        ds->last_band_cols += (std::min(int64_t(ni), jlo + jb) - jlo) * (band[k] - jlo);
+      }
+      ds->band_end.assign(band.begin(), band.end());
+      ds->band_jb = jb;
+    }
     if (prec == OCCK_PREC_FP64)
-      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
     else if (prec == OCCK_PREC_FP32)
-      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
     else if (prec == OCCK_PREC_BF16X3)
-      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
     else
-      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym);
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
@@ -1101,6 +1271,15 @@ int32_t profile_read(Tree* t, double* ms, int64_t* launches) {
   ds->ev_idx.clear();
   ds->ev_used = 0;
   ds->launches.assign(OCCK_K_NCLASS, 0);
+  return OCCK_OK;
+}
+
+int32_t pair_screen_info(Tree* t, int64_t* carried, int32_t* jblock, int32_t* band_end, int32_t cap, int32_t* nband) {
+  const DeviceState* ds = t->dev;
+  *carried = ds ? ds->last_band_cols : 0;
+  *jblock = ds ? ds->band_jb : 0;
+  *nband = ds ? int32_t(ds->band_end.size()) : 0;
+  for (int32_t k = 0; k < std::min(cap, *nband); ++k) band_end[k] = ds->band_end[size_t(k)];
   return OCCK_OK;
 }
 

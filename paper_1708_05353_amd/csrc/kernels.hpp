@@ -75,6 +75,8 @@ struct GemmRun {
   int32_t accumulate;  // C += A B instead of C = A B
   int32_t tile0;       // the launch computes tiles [tile0, tile0 + ntiles)
   int32_t ntiles;
+  int32_t nhi;         // output columns at or beyond nhi are not written, tiles starting there skipped (0: none)
+  int32_t klim;        // k runs over [koff, min(K, klim)) (0: K)
   int32_t pad;
 };
 struct GemmTile {
@@ -85,12 +87,14 @@ struct GemmTile {
 // i >= istart are carried (the symmetric schedule starts i at the batch's
 // first j); nvalid = jb*(ni - istart) of them, numbered v = j*(ni - istart)
 // + (i - istart).
+// With occupied-pair screening the carried i of a batch end at iend (0: ni),
+// nvalid = jb*(iend - istart), v = j*(iend - istart) + (i - istart).
 struct ColMap {
-  int64_t ncol, ni, istart, nvalid;
+  int64_t ncol, ni, istart, nvalid, iend;
 };
 __host__ __device__ inline int64_t carried_col(const ColMap& cm, int64_t v) {
-  if (cm.istart == 0) return v;
-  const int64_t nk = cm.ni - cm.istart;
+  if (cm.istart == 0 && cm.iend == 0) return v;
+  const int64_t nk = (cm.iend > 0 ? cm.iend : cm.ni) - cm.istart;
   const int64_t j = v / nk;
   return j * cm.ni + cm.istart + (v - j * nk);
 }
@@ -366,7 +370,9 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   constexpr int EA = BM * KT / 256, EB = BN * KT / 256;   // elements per thread per operand tile
   const int64_t boff = run.boff, blim = run.blim, koff = run.koff;   // koff < 2^31
   const int m0 = mt * BM, n0 = nt * BN;
-  const int64_t kseg = int64_t(d.K) - koff;                // terms per segment
+  if (run.nhi > 0 && n0 >= run.nhi) return;   // the whole tile lies past the written columns (uniform)
+  const int kend = run.klim > 0 && run.klim < d.K ? run.klim : d.K;   // k runs over [koff, kend) in every segment
+  const int64_t kseg = int64_t(kend) - koff;                // terms per segment
   const int nseg = d.nseg > 0 ? d.nseg : 1;
   const int kpseg = kseg > 0 ? int((kseg + KT - 1) / KT) : 0;  // K tiles per segment
   const int nsteps = nseg * kpseg;
@@ -415,7 +421,6 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   const int bk = B_W ? tid / 64 : tid / TPRB, bn = B_W ? tid % 64 : (tid % TPRB) * EB;
   // Per-thread operand pointers at k = koff of segment 0; a K tile advances
   // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
-  const int kend = d.K;                       // k runs over [koff, K) in every segment
   const int kfirst = int(koff);
   const int M = d.M, N = d.N;
   const int64_t sam = d.sam, sak = d.sak, sa_seg = d.sa_seg, ldb = d.ldb, sb_seg = d.sb_seg;
@@ -655,7 +660,7 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   for (int i = 0; i < TM; ++i)
     for (int j = 0; j < TN; ++j) {
       const int col = n0 + wn + j * 16 + (lane & 15);
-      if (col >= d.N || col < run.nlo) continue;
+      if (col >= d.N || col < run.nlo || (run.nhi > 0 && col >= run.nhi)) continue;
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + wm + i * 16 + acc_row<Acc>(lane >> 4, r);
         if (row >= mend) continue;

@@ -116,6 +116,7 @@ int32_t debug_mfma_probe(int kind, int ia, int ka, int jb, double* host_out);
 int32_t debug_buffer(Tree* t, int which, double* host, int64_t* count);
 int32_t profile_read(Tree* t, double* ms, int64_t* launches);
 int32_t workspace_info(Tree* t, int32_t* jblock, int64_t* bytes);
+int32_t pair_screen_info(Tree* t, int64_t* carried, int32_t* jblock, int32_t* band_end, int32_t cap, int32_t* nband);
 int32_t batch_create(int nsys, Tree* const* trees, const int32_t* nocc, int prec, int jblock, void** out);
 int32_t batch_run(void* plan, const double* const* C, const int64_t* ldc, double* const* K, const int64_t* ldk,
                   void* stream);

@@ -57,7 +57,7 @@ class _JFlops(ct.Structure):
 
 class _Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
-                ("jblock", ct.c_int32), ("accumulate", ct.c_int32)]
+                ("jblock", ct.c_int32), ("accumulate", ct.c_int32), ("pair_thresh", ct.c_double)]
 
 
 EXPORTS = {
@@ -74,6 +74,8 @@ EXPORTS = {
                                  ct.c_int32, ct.c_void_p]),
     "occk_near_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int64)]),
     "occk_tree_near": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "occk_pair_screen_info": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int64), ct.POINTER(ct.c_int32),
+                                           ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32)]),
     "occk_tree_export": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                       ct.c_void_p]),
     "occk_tree_leaf": (ct.c_int32, [ct.c_void_p, ct.c_int32, ct.POINTER(ct.c_int32), ct.c_void_p,
@@ -295,7 +297,7 @@ class Tree:
 
 
 def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,
-          jblock: int = 0, accumulate: bool = False, stream=None, selector=None):
+          jblock: int = 0, accumulate: bool = False, stream=None, selector=None, pair_thresh: float = 0.0):
     """K[:, i0:i1] (+)= 2 sum_{j in [j0,j1)} (rj|ji)_ff on the GPU.
 
     C: torch.float64 CUDA tensor (nbasis, ldc) row-major; K: torch.float64 CUDA
@@ -311,7 +313,8 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
     if stream is None:
         stream = torch.cuda.current_stream(C.device)
     opts = _Opts(int(precision), RANK_FIXED if selector is None else RANK_LEARNED,
-                 None if selector is None else selector.handle.value, int(jblock), int(bool(accumulate)))
+                 None if selector is None else selector.handle.value, int(jblock), int(bool(accumulate)),
+                 float(pair_thresh))
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))
@@ -361,6 +364,18 @@ def near_K(tree: Tree, C, K, accumulate: bool = False, stream=None):
     _check(lib().occk_near_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), int(C.shape[1]),
                              ct.c_void_p(K.data_ptr()), int(K.stride(0)), int(bool(accumulate)),
                              ct.c_void_p(stream.cuda_stream)))
+
+
+def pair_screen_info(tree: Tree) -> tuple:
+    """(carried (j, i) columns, j batch width, i end of every j batch) of the
+    handle's last screened occk_far_K call."""
+    n, jb, nb = ct.c_int64(), ct.c_int32(), ct.c_int32()
+    _check(lib().occk_pair_screen_info(tree.handle, ct.byref(n), ct.byref(jb), None, 0, ct.byref(nb)))
+    ends = np.zeros(nb.value, dtype=np.int32)
+    if nb.value:
+        _check(lib().occk_pair_screen_info(tree.handle, ct.byref(n), ct.byref(jb), ends.ctypes.data, nb.value,
+                                           ct.byref(nb)))
+    return n.value, jb.value, ends
 
 
 def near_info(tree: Tree) -> tuple:

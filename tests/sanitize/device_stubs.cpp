@@ -30,6 +30,12 @@ int32_t workspace_info(Tree*, int32_t* jblock, int64_t* bytes) {
   if (bytes) *bytes = 0;
   return OCCK_OK;
 }
+int32_t pair_screen_info(Tree*, int64_t* carried, int32_t* jblock, int32_t*, int32_t, int32_t* nband) {
+  *carried = 0;
+  *jblock = 0;
+  *nband = 0;
+  return OCCK_OK;
+}
 int32_t batch_create(int, Tree* const*, const int32_t*, int, int, void**) { return no_gpu(); }
 int32_t batch_run(void*, const double* const*, const int64_t*, double* const*, const int64_t*, void*) {
   return no_gpu();

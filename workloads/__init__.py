@@ -373,3 +373,44 @@ def occupied_orbitals(sysm: System, seed: int, nocc: int | None = None) -> np.nd
         Q, _ = np.linalg.qr(G)
         C = X @ Q
     return np.ascontiguousarray(C)
+
+
+def localized_orbitals(sysm: System, seed: int, nocc: int | None = None) -> np.ndarray:
+    """Occupied orbitals localised by construction (input for occupied-pair
+    screening): the nocc orbitals are dealt to the sites in proportion to
+    their function counts, each a seeded N(0,1) combination of its own site's
+    functions (orthonormalised within the site); the columns are then
+    orthonormalised symmetrically in the overlap metric,
+    C = G (G^T S G)^{-1/2}, which keeps every orbital on its site up to tails
+    that decay with distance.  Columns are ordered along the system's longest
+    direction."""
+    nocc = sysm.nocc if nocc is None else nocc
+    rng = np.random.default_rng([seed, 3])
+    S = overlap_matrix(sysm)
+    xyz = sysm.xyz
+    axis = int(np.argmax(xyz.max(0) - xyz.min(0)))
+    order = np.argsort(xyz[:, axis], kind="stable")
+    funcs = [[] for _ in range(len(xyz))]
+    f = 0
+    for sh in range(sysm.nshell):
+        nf = 1 if sysm.shell_l[sh] == 0 else 3
+        funcs[int(sysm.shell_atom[sh])].extend(range(f, f + nf))
+        f += nf
+    total = sum(len(v) for v in funcs)
+    share = np.array([len(funcs[a]) * nocc / total for a in order])
+    count = np.floor(share).astype(int)
+    for a in np.argsort(-(share - count), kind="stable")[: nocc - count.sum()]:
+        count[a] += 1
+    G = np.zeros((S.shape[0], nocc))
+    k = 0
+    for a, m in zip(order, count):
+        if m == 0:
+            continue
+        rows = np.array(funcs[a])
+        Q, _ = np.linalg.qr(rng.standard_normal((len(rows), m)))
+        G[rows, k:k + m] = Q
+        k += m
+    M = G.T @ S @ G
+    w, U = np.linalg.eigh(M)
+    C = G @ (U / np.sqrt(w)) @ U.T
+    return np.ascontiguousarray(C)
