@@ -377,6 +377,18 @@ int32_t occk_batch_run(occk_batch* plan, const double* const* C, const int64_t* 
 int32_t occk_batch_tune(occk_batch* plan, const double* const* C, const int64_t* ldc, double* const* K,
                         const int64_t* ldk, void* hip_stream, int32_t* choice);
 
+/* The one-call form of a plan (the batched entry point of the hot path):
+ * occk_batch_create, occk_batch_run and occk_batch_free in turn, so K[k]
+ * (columns 0..nocc[k]-1, overwritten) holds K^ff of system k when it
+ * returns (it synchronises the device when freeing the plan).  Arguments as
+ * for occk_batch_create and occk_batch_run; the I/O arrays are checked
+ * before any plan is made.  A caller that runs the same systems again keeps
+ * a plan instead: this call rebuilds the tables, the operators and the
+ * workspaces every time. */
+int32_t occk_far_K_batched(int32_t nsys, occk_tree* const* trees, const double* const* C, const int64_t* ldc,
+                           const int32_t* nocc, const occk_far_opts* opts, double* const* K, const int64_t* ldk,
+                           void* hip_stream);
+
 /* nsys and the first cap nocc values of the plan. */
 int32_t occk_batch_shape(const occk_batch* plan, int32_t* nsys, int32_t* nocc, int32_t cap);
 
@@ -514,7 +526,9 @@ int32_t occk_debug_mfma_probe(int32_t kind, int32_t ia, int32_t ka, int32_t jb, 
 
 /* Copies a workspace buffer of the handle's last occk_far_K call to host
  * memory after a device synchronisation: which = 0 translation operators,
- * 1 half-transformed multipoles H, 2 box data (Omega then Mloc; where the
+ * 1 half-transformed multipoles H of the last j batch (empty when the i and
+ * j ranges coincide: that schedule reads each batch's H out of the
+ * all-column half transform), 2 box data (Omega then Mloc; where the
  * downward pass ran as a subtree walk, the Mloc of the boxes below the walk's
  * roots and above the leaves are not written), 3 per-leaf K partials.
  * *count receives the element count; host may be NULL to query it.

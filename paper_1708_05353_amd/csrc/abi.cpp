@@ -658,6 +658,26 @@ int32_t occk_batch_free(occk_batch* plan) {
   return batch_free(plan);
 }
 
+int32_t occk_far_K_batched(int32_t nsys, occk_tree* const* trees, const double* const* C, const int64_t* ldc,
+                           const int32_t* nocc, const occk_far_opts* opts, double* const* K, const int64_t* ldk,
+                           void* hip_stream) {
+  if (nsys >= 1 && nsys <= 4096 && trees && nocc) {   // the I/O arrays are checked before any plan is made
+    const int32_t rc = check_io(nsys, C, ldc, K, ldk);
+    if (rc != OCCK_OK) return rc;
+  }
+  occk_batch* plan = nullptr;
+  int32_t rc = occk_batch_create(nsys, trees, nocc, opts, &plan);
+  if (rc != OCCK_OK) return rc;
+  rc = occk_batch_run(plan, C, ldc, K, ldk, hip_stream);
+  std::string msg = rc != OCCK_OK ? occk_last_error() : "";
+  const int32_t rf = occk_batch_free(plan);   // synchronises the device: the launch has finished
+  if (rc != OCCK_OK) {
+    set_error(msg);
+    return rc;
+  }
+  return rf;
+}
+
 int32_t occk_selector_create(int32_t seed, occk_selector** out) {
   if (!out) {
     set_error("occk_selector_create: out is NULL");

@@ -196,7 +196,7 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
           const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(S.ops) : reinterpret_cast<const T*>(S.opsf);
           for (int64_t lb = tk.b; lb < e1; ++lb) {
             if constexpr (QV > 0)
-              translate_vec_tile<T, QV, kVecCols, false>(static_cast<T*>(S.data), S.box_stride, cm, S.KS, P.tgt_box,
+              translate_vec_tile<T, QV, kVecCols, 0, false>(static_cast<T*>(S.data), S.box_stride, cm, S.KS, P.tgt_box,
                                                   P.src_ptr, P.src_box, P.src_op, S.ops, int(lb % P.ntgt), lb / P.ntgt);
             else
               translate_tile<T, MT, (sizeof(BatchSmem<MODE>) >= sizeof(T) * MT * 4 * MT * 64)>(
@@ -360,7 +360,7 @@ static void prepare(BatchPlan& bp, hipStream_t st) {
     if (mixed) launch_to_float(ds->ops.p, 0, ds->opsf.p, 0, 1, int64_t(ds->ops.n), st);
     const int n = bp.nocc[k];
     const int jb = bp.jblock > 0 ? std::min(bp.jblock, n) : auto_jblock(t, n, n, es, true);
-    setup_workspace(t, jb, n, bp.prec, true);
+    setup_workspace(t, jb, n, bp.prec, kWsSym);
     if (mixed) ds->Cf.alloc(size_t(t->nbasis) * n);
     bp.ws_gen[size_t(k)] = ds->ws_gen;
     bp.jb[size_t(k)] = jb;
@@ -536,7 +536,7 @@ static void revalidate(BatchPlan& bp) {
   for (int k = 0; k < bp.nsys; ++k) {
     const DeviceState* ds = bp.trees[k]->dev;
     if (!ds || ds->ws_jb != bp.jb[size_t(k)] || ds->ws_ni != bp.nocc[k] || ds->ws_prec != bp.prec ||
-        ds->ws_sym != 1 || ds->ws_gen != bp.ws_gen[size_t(k)] ||
+        ds->ws_sym != kWsSym || ds->ws_gen != bp.ws_gen[size_t(k)] ||
         (bp.prec != OCCK_PREC_FP64 && ds->Cf.p != bp.host_sys[k].Cf))
       stale = true;
   }

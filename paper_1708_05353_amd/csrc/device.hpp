@@ -127,13 +127,20 @@ struct DeviceState {
   DevBuf<OpParam> opparam;
   DevBuf<double> ops;             // FP64 operators (always generated in FP64)
   DevBuf<float> opsf;             // rounded copy for the mixed paths
+  int op_sym = 0;                 // structural zeros of the operators (real_class): 0 none, 1 x axis, 2 xy plane
   std::vector<Pass> up, down;     // up[k]: level depth-1-k ; down[k]: level lmin+k
   DevBuf<int32_t> occ_ptr, occ_row;
   int nbox = 0;                    // boxes on levels lmin..depth
   std::vector<int32_t> leaf_box;   // leaf -> box slot
   // per workspace shape (j batch, n_i, precision, symmetric schedule)
-  int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;
+  int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;   // ws_sym: kWsPlain, kWsSym, kWsSymHT
   uint64_t ws_gen = 0;            // incremented whenever the workspace buffers are rebuilt
+  // two-stream schedule (symmetric, downward walks): the L2P of j batch k on
+  // st2 while batch k+1's Omega and translations run on the caller's stream;
+  // the leaf Mloc of odd batches go to nleaf extra box rows after the Mloc
+  bool ws_pipe = false;           // the box data have those extra rows
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_mloc[2] = {nullptr, nullptr}, ev_l2p[2] = {nullptr, nullptr}, ev_join = nullptr;
   DevBuf<char> H, data;           // element type of the precision (double / float)
   DevBuf<char> HT;                // symmetric schedule: H for every column, [leaf][q][i][t]
   DevBuf<double> KB;              // per-leaf K partials, always FP64
@@ -231,7 +238,11 @@ struct ProfScope {   // records a start/end event pair around a group of launche
 size_t device_cap();
 void upload_tree(Tree* t);
 // arena != nullptr: place every buffer and table in that region (no allocation)
-void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym = false, ScratchArena* arena = nullptr);
+// Workspace layouts: plain (all columns), symmetric with a per-batch half
+// transform beside HT (the persistent batch kernel), symmetric with the
+// batch's half transform read out of HT (occk_far_K).
+enum { kWsPlain = 0, kWsSym = 1, kWsSymHT = 2 };
+void setup_workspace(Tree* t, int jb, int ni, int prec, int sym_mode = kWsPlain, ScratchArena* arena = nullptr);
 // largest j batch width (<= 256) whose workspace fits min(cap/2, 32 GiB)
 int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym);
 void ensure_mixed_operands(Tree* t, hipStream_t st);

@@ -94,6 +94,14 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     for (int d = 0; d < 3; ++d) op[k].d[d] = t->ops[k].d[d];
   }
   ds->opparam.upload(op);
+  // structural zeros of the translation operators: every displacement on
+  // the x axis (1) or in the xy plane (2), else none (0)
+  bool xaxis = true, xyplane = true;
+  for (const OpParam& o : op) {
+    xaxis = xaxis && o.d[1] == 0.0 && o.d[2] == 0.0;
+    xyplane = xyplane && o.d[2] == 0.0;
+  }
+  ds->op_sym = xaxis ? 1 : xyplane ? 2 : 0;
   ds->ops.alloc(op.size() * size_t(opsize_of(Q)));
   // box slots on levels lmin..D
   const int lmin = t->lmin;
@@ -310,10 +318,13 @@ static std::vector<int32_t> chunked_tile_lists(std::vector<GemmTile>& tiles, Key
 static inline unsigned gemm_grid(int n) { return unsigned(((n + 7) / 8) * 8); }
 
 // Device bytes of one workspace shape (box data, H, HT, KB).
-static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni, size_t es, bool sym) {
+// extra_rows: box rows beyond Omega and Mloc (the second leaf Mloc region of
+// the two-stream schedule).
+static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni, size_t es, bool sym,
+                             int64_t extra_rows = 0) {
   const int64_t ncol = int64_t(jb) * ni;
-  return size_t(sum_nb) * Q * jb * es + size_t(2) * nbox * Q * size_t(ncol) * es + size_t(sum_nb) * ni * 8 +
-         (sym ? size_t(sum_nb) * Q * ni * es : 0);
+  return size_t(sum_nb) * Q * jb * es + size_t(2 * nbox + extra_rows) * Q * size_t(ncol) * es +
+         size_t(sum_nb) * ni * 8 + (sym ? size_t(sum_nb) * Q * ni * es : 0);
 }
 
 // Buffers and GEMM descriptors of one workspace shape.  Box data of a batch:
@@ -321,17 +332,26 @@ static size_t workspace_need(int64_t sum_nb, int Q, int64_t nbox, int jb, int ni
 //   half   H^B[t][q][j] = sum_s O^B_q[t, s] C[s, jstart + j]           (ld Q*jb)
 //   omega  Omega^B[(q, j), i] = sum_t H^B[t][(q, j)] C[t, i0 + i]
 //   l2p    KB[r, i] (+)= sum_(q,j) H^B[r][(q, j)] Mloc^B[(q, j), i]
-// symmetric schedule (sym) in addition:
+// symmetric schedule (sym_mode kWsSym, kWsSymHT) in addition:
 //   ht     HT^B[q][i][t] = sum_s O^B_q[t, s] C[s, i0 + i]  for every column i
 //   l2pt   KB[r, jstart + j] += sum_q sum_(i >= koff) HT^B[q][i][r] Mloc^B[(q, j), i]
-void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* arena) {
+// kWsSymHT reads the batch's H out of HT (no H buffer, no per-batch half):
+//   omega  Omega^B[(q, j), i] = sum_t HT^B[q][jstart + j][t] C[t, i0 + i]   (per leaf and q)
+//   l2p    KB[r, i] (+)= sum_q sum_j HT^B[q][jstart + j][r] Mloc^B[(q, j), i]   (K segments q)
+void setup_workspace(Tree* t, int jb, int ni, int prec, int sym_mode, ScratchArena* arena) {
   DeviceState* ds = t->dev;
-  if (!arena && ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec && ds->ws_sym == int(sym)) return;
+  if (!arena && ds->ws_jb == jb && ds->ws_ni == ni && ds->ws_prec == prec && ds->ws_sym == sym_mode) return;
+  const bool sym = sym_mode != kWsPlain, from_ht = sym_mode == kWsSymHT;
   const int Q = t->Q, nl = t->nleaf();
   const size_t es = prec == OCCK_PREC_FP64 ? 8 : 4;
   const int64_t sum_nb = ds->f_off[nl];
   const int64_t ncol = int64_t(jb) * ni;
-  const size_t need = workspace_need(sum_nb, Q, ds->nbox, jb, ni, es, sym);
+  // the two-stream schedule (occk_far_K, symmetric, downward walks; not in
+  // the fixed scratch region) keeps the leaf Mloc of odd batches in nleaf
+  // extra box rows
+  const bool pipe = from_ht && !arena && ds->dnw_nroots > 0;
+  const int64_t extra = pipe ? nl : 0;
+  const size_t need = workspace_need(sum_nb, Q, ds->nbox, jb, ni, es, sym, extra);
   if (!arena && need + ds->bytes > device_cap()) throw std::bad_alloc();
   // buffers and tables: allocated, or placed in the arena
   auto alloc = [arena](auto& buf, size_t count) {
@@ -351,8 +371,9 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* 
   ds->HT.free();
   ds->data.free();
   ds->KB.free();
-  alloc(ds->H, size_t(sum_nb) * Q * jb * es);
-  alloc(ds->data, size_t(2) * ds->nbox * Q * size_t(ncol) * es);
+  if (!from_ht) alloc(ds->H, size_t(sum_nb) * Q * jb * es);
+  alloc(ds->data, size_t(2 * ds->nbox + extra) * Q * size_t(ncol) * es);
+  ds->ws_pipe = pipe;
   alloc(ds->KB, size_t(sum_nb) * ni);
   if (sym) alloc(ds->HT, size_t(sum_nb) * Q * ni * es);
   const int64_t box_stride = int64_t(Q) * ncol;
@@ -374,13 +395,15 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* 
       d.sam = nb;
       d.sak = 1;
       d.gidx = g;
-      d.C = ds->H.p + (hoff + int64_t(q) * jb) * es;
+      d.C = from_ht ? nullptr : ds->H.p + (hoff + int64_t(q) * jb) * es;
       d.ldc = int64_t(Q) * jb;
       d.M = nb;
       d.N = jb;
       d.K = nb;
-      tiles_for<GemmRows48>(th, int(dh.size()), d.M, d.N);
-      dh.push_back(d);
+      if (!from_ht) {
+        tiles_for<GemmRows48>(th, int(dh.size()), d.M, d.N);
+        dh.push_back(d);
+      }
       if (sym) {   // HT_q[i][t], column-major store
         GemmDesc e = d;
         e.C = ds->HT.p + (ds->f_off[b] * Q * ni + int64_t(q) * ni * nb) * es;
@@ -391,7 +414,22 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* 
         dht.push_back(e);
       }
     }
-    {  // Omega[(q,j), i] = sum_t H[t][(q,j)] C[f(t), i0+i]
+    if (from_ht) {  // Omega[(q,j), i] = sum_t HT_q[jstart + j][t] C[f(t), i0+i], one problem per q
+      for (int q = 0; q < Q; ++q) {
+        GemmDesc d{};
+        d.A = ds->HT.p + (ds->f_off[b] * Q * ni + int64_t(q) * ni * nb) * es;
+        d.sam = nb;
+        d.sak = 1;
+        d.gidx = g;
+        d.C = ds->data.p + (int64_t(ds->leaf_box[b]) * box_stride + int64_t(q) * jb * ni) * es;
+        d.ldc = ni;
+        d.M = jb;
+        d.N = ni;
+        d.K = nb;
+        tiles_for(tom, int(dom.size()), d.M, d.N);
+        dom.push_back(d);
+      }
+    } else {  // Omega[(q,j), i] = sum_t H[t][(q,j)] C[f(t), i0+i]
       GemmDesc d{};
       d.A = ds->H.p + hoff * es;
       d.sam = 1;
@@ -405,7 +443,25 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* 
       tiles_for(tom, int(dom.size()), d.M, d.N);
       dom.push_back(d);
     }
-    {  // KB[r, i] (+)= sum_(q,j) H[r][(q,j)] Mloc[(q,j), i]
+    if (from_ht) {  // KB[r, i] (+)= sum_q sum_j HT_q[jstart + j][r] Mloc[(q,j), i]: K segments q
+      GemmDesc d{};
+      d.A = ds->HT.p + ds->f_off[b] * Q * ni * es;
+      d.sam = 1;
+      d.sak = nb;
+      d.sa_seg = int64_t(ni) * nb;
+      d.B = mloc;
+      d.ldb = ni;
+      d.sb_seg = int64_t(jb) * ni;
+      d.nseg = Q;
+      d.C = ds->KB.p + ds->f_off[b] * ni;
+      d.ldc = ni;
+      d.M = nb;
+      d.N = ni;
+      d.K = jb;
+      tiles_for<GemmRows48>(tl2, int(dl.size()), d.M, d.N);
+      tiles_for<GemmRows144>(tl2w, int(dl.size()), d.M, d.N);
+      dl.push_back(d);
+    } else {  // KB[r, i] (+)= sum_(q,j) H[r][(q,j)] Mloc[(q,j), i]
       GemmDesc d{};
       d.A = ds->H.p + hoff * es;
       d.sam = int64_t(Q) * jb;
@@ -494,7 +550,7 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, bool sym, ScratchArena* 
   ds->ws_jb = jb;
   ds->ws_ni = ni;
   ds->ws_prec = prec;
-  ds->ws_sym = int(sym);
+  ds->ws_sym = sym_mode;
 }
 
 template <class T>
@@ -508,15 +564,23 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
     const int64_t nblocks = ((cm.nvalid + 256 * NC - 1) / (256 * NC)) * ps.ntgt;
     const int64_t grid = ((nblocks + 7) / 8) * 8;
     if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_TV(QQ)                                                                                            \
-  hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NC>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
-                     cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops64, ps.ntgt, nblocks)
+#define OCCK_TV(QQ, SY)                                                                                         \
+  hipLaunchKernelGGL((translate_vec_kernel<T, QQ, NC, SY>), dim3(unsigned(grid)), dim3(256), 0, st, data,         \
+                     box_stride, cm, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops64, ps.ntgt,   \
+                     nblocks)
+#define OCCK_TVQ(QQ)                        \
+  switch (t->dev->op_sym) {                 \
+    case 1: OCCK_TV(QQ, 1); break;          \
+    case 2: OCCK_TV(QQ, 2); break;          \
+    default: OCCK_TV(QQ, 0); break;         \
+  }
     switch (Q) {
-      case 1: OCCK_TV(1); break;
-      case 4: OCCK_TV(4); break;
-      case 9: OCCK_TV(9); break;
+      case 1: OCCK_TV(1, 0); break;
+      case 4: OCCK_TVQ(4); break;
+      case 9: OCCK_TVQ(9); break;
       default: throw std::invalid_argument("unsupported Q");
     }
+#undef OCCK_TVQ
 #undef OCCK_TV
     HIP_OK(hipGetLastError());
     return;
@@ -545,19 +609,27 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
 // (setup built the programs)
 template <class T>
 void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int nroots, int nlv, bool up, T* data,
-                 int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st) {
+                 int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st, int64_t store_shift = 0) {
   if (cm.nvalid <= 0 || nroots == 0) return;
   const int Q = t->Q, KS = ksteps_of(Q);
   const int64_t nblocks = ((cm.nvalid + 255) / 256) * nroots;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_W(QQ, NL)                                                                                          \
-  if (up)                                                                                                        \
-    hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,    \
-                       cm, KS, pptr, prog, ops, nroots, nblocks);                                                \
-  else                                                                                                           \
-    hipLaunchKernelGGL((down_walk_kernel<T, QQ, NL>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,  \
-                       cm, KS, pptr, prog, ops, nroots, nblocks)
+  // chain-like trees: the x-axis structural zeros, or none
+  const bool xaxis = t->dev->op_sym == 1;
+#define OCCK_WS(QQ, NL, SY)                                                                                        \
+  if (up)                                                                                                          \
+    hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL, SY>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,  \
+                       cm, KS, pptr, prog, ops, nroots, nblocks);                                                  \
+  else                                                                                                             \
+    hipLaunchKernelGGL((down_walk_kernel<T, QQ, NL, SY>), dim3(unsigned(grid)), dim3(256), 0, st, data,            \
+                       box_stride, cm, KS, pptr, prog, ops, nroots, nblocks, store_shift)
+#define OCCK_W(QQ, NL)          \
+  if (xaxis && QQ > 1) {        \
+    OCCK_WS(QQ, NL, 1);         \
+  } else {                      \
+    OCCK_WS(QQ, NL, 0);         \
+  }
 #define OCCK_WQ(QQ)                                                        \
   switch (nlv) {                                                           \
     case 1: OCCK_W(QQ, 1); break;                                          \
@@ -576,6 +648,7 @@ void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int n
   }
 #undef OCCK_WQ
 #undef OCCK_W
+#undef OCCK_WS
   HIP_OK(hipGetLastError());
 }
 
@@ -610,6 +683,9 @@ void device_free(Tree* t) {
 static void free_state(DeviceState* ds) {
   for (hipEvent_t e : ds->ev_pool) (void)hipEventDestroy(e);
   ds->ev_pool.clear();
+  for (hipEvent_t e : {ds->ev_mloc[0], ds->ev_mloc[1], ds->ev_l2p[0], ds->ev_l2p[1], ds->ev_join})
+    if (e) (void)hipEventDestroy(e);
+  if (ds->st2) (void)hipStreamDestroy(ds->st2);
   ds->Of.free();
   ds->opsf.free();
   ds->Cf.free();
@@ -814,7 +890,8 @@ static std::vector<int> pair_bands(Tree* t, DeviceState* ds, const double* C, in
 // i >= jstart, and the mirrored l2pt, K[r, j] += sum_q sum_(i >= jstart+jb)
 // H_q[r, i] Mloc[(q,j), i] for j in J, which supplies the pairs (i, j) whose
 // i lies in an earlier batch.  The diagonal block (i, j both in J) is
-// carried in full and counted once.
+// carried in full and counted once.  H of the batch is not formed again:
+// HT, formed once per call for every column, holds it (rows jstart + j).
 template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
                         int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
@@ -827,6 +904,22 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops.p) : reinterpret_cast<const T*>(ds->opsf.p);
   const int nj = j1 - j0;
   const int nblk = (nj + jb - 1) / jb;
+  // Two streams (symmetric schedule with downward walks): the L2P of batch
+  // k runs on st2 while batch k+1's Omega and translations run on st.  The
+  // leaf Mloc of odd batches go to the extra rows after the Mloc; st waits
+  // for the L2P of batch k-2 before its downward walk overwrites that
+  // region, st2 for the walk of batch k before its L2P, and st for st2's
+  // last L2P before the reduction.
+  const bool pipe = sym && !sel && !stop_after_up && ds->ws_pipe && ds->dnw_nroots > 0 && nblk > 1;
+  hipStream_t stl = st;   // the L2P's stream
+  if (pipe) {
+    if (!ds->st2) {
+      HIP_OK(hipStreamCreateWithFlags(&ds->st2, hipStreamNonBlocking));   // default priority
+      for (hipEvent_t* e : {&ds->ev_mloc[0], &ds->ev_mloc[1], &ds->ev_l2p[0], &ds->ev_l2p[1], &ds->ev_join})
+        HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    stl = ds->st2;
+  }
   if (sym) {   // HT for every column, once per call
     ProfScope ps(ds, prof, OCCK_K_HALF, st);
     ProfScope ps_ht(ds, prof, OCCK_K_HT, st);
@@ -842,6 +935,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     const int64_t jstart = j0 + jrel;
     const int64_t istart = sym ? jrel : 0;         // first carried i (relative to i0)
     const int jbk = int(std::min<int64_t>(jb, nj - jrel));
+    const int buf = pipe ? (kb & 1) : 0;                  // leaf Mloc region of the batch
+    const int64_t lshift = buf ? int64_t(t->nleaf()) : 0;   // its offset in box rows
     // occupied-pair screening: the batch carries i in [istart, iend) only
     const int64_t iend = band ? int64_t((*band)[size_t(kb)]) : int64_t(ni);
     ColMap cm;
@@ -849,9 +944,11 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     cm.ni = ni;
     cm.istart = istart;
     cm.iend = band ? iend : 0;
-    cm.nvalid = int64_t(jb) * (iend - istart);
+    // the symmetric schedule carries the batch's own j only (the last batch
+    // may be short: its Omega rows past jbk are not formed)
+    cm.nvalid = int64_t(sym ? jbk : jb) * (iend - istart);
     const int ct0 = int(istart / 64);              // first column tile touching i >= istart
-    {
+    if (!sym) {   // the symmetric schedule reads the batch's H out of HT
       ProfScope ps(ds, prof, OCCK_K_HALF, st);
       GemmRun r{};
       r.boff = jstart;
@@ -868,8 +965,15 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.nhi = band ? int(iend) : 0;
       r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
       r.ntiles = ds->omega_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-      hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                         ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
+      if (sym) {   // per (leaf, q): rows j of HT_q from the batch's first j
+        r.amoff = int32_t(jrel);
+        r.mlim = jbk;
+        hipLaunchKernelGGL((omega_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+                           ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
+      } else {
+        hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
+                           ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
+      }
     }
     {
       ProfScope ps(ds, prof, OCCK_K_UP, st,
@@ -897,50 +1001,74 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       for (size_t k = 0; k < k1; ++k)
         launch_translate<T>(t, ds->down[k], data, box_stride, cm, ops, st, sel ? ds->down[k].rank.p : nullptr);
       if (walk) {
+        if (pipe && kb >= 2) HIP_OK(hipStreamWaitEvent(st, ds->ev_l2p[buf], 0));   // batch kb-2 has read it
         ProfScope ps_w(ds, prof, OCCK_K_DOWN_WALK, st);
         launch_walk<T>(t, ds->dnw_ptr.p, ds->dnw_prog.p, ds->dnw_nroots, ds->dnw_nlv, false, data, box_stride, cm,
-                       ops, st);
+                       ops, st, lshift);
       }
     }
+    if (pipe) {
+      HIP_OK(hipEventRecord(ds->ev_mloc[buf], st));
+      HIP_OK(hipStreamWaitEvent(stl, ds->ev_mloc[buf], 0));
+    }
     {
-      ProfScope ps(ds, prof, OCCK_K_L2P, st, sym && jrel + jb < iend ? 2 : 1);
+      ProfScope ps(ds, prof, OCCK_K_L2P, stl, sym && jrel + jb < iend ? 2 : 1);
       GemmRun r{};
       r.accumulate = (kb > 0 || band) ? 1 : 0;   // with screening KB starts cleared
       r.nlo = int(istart);
       r.nhi = band ? int(iend) : 0;
-      ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, st);
+      r.bptr = lshift * box_stride;              // B: the batch's leaf Mloc
+      ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, stl);
+      if (sym) {   // K segments q, k = j over the batch's own j, A out of HT
+        r.akoff = int32_t(jrel);
+        r.klim = jbk;
+      }
       if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
         r.tile0 = ds->l2pw_nt_start[size_t(ct0 / 4)];
         r.ntiles = ds->l2pw_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-        hipLaunchKernelGGL((l2p_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                           ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
+        if (sym)
+          hipLaunchKernelGGL((l2p_ht_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
+                             ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
+        else
+          hipLaunchKernelGGL((l2p_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
+                             ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
       } else {
         r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
         r.ntiles = ds->l2p_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-        hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                           ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
+        if (sym)
+          hipLaunchKernelGGL((l2p_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
+                             ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
+        else
+          hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
+                             ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
       }
       ps_d.close();
       if (sym && jrel + jb < iend) {
-        ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, st);
+        ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, stl);
         GemmRun m{};
         m.accumulate = 1;
         m.klim = band ? int(iend) : 0;
         m.koff = jrel + jb;
+        m.aptr = lshift * box_stride;            // A: the batch's leaf Mloc
         m.coff = jrel;
         m.mlim = jbk;
         if (MODE <= kModeF32 && ds->n_l2ptw > 0) {   // the split-BF16 modes would need 256+ VGPRs
           m.ntiles = ds->n_l2ptw;
-          hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
+          hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, stl,
                              ds->d_l2pt.p, ds->t_l2ptw.p, Cg, ldcg, m);
         } else {
           m.ntiles = ds->n_l2pt;
-          hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, st,
+          hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, stl,
                              ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
         }
       }
     }
+    if (pipe) HIP_OK(hipEventRecord(ds->ev_l2p[buf], stl));
     HIP_OK(hipGetLastError());
+  }
+  if (pipe) {   // the caller's stream resumes after the last L2P
+    HIP_OK(hipEventRecord(ds->ev_join, stl));
+    HIP_OK(hipStreamWaitEvent(st, ds->ev_join, 0));
   }
 }
 
@@ -982,13 +1110,14 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
         sum_nb2 += int64_t(f.size()) * int64_t(f.size());
       }
       for (int lev = t->lmin; lev <= t->params.depth; ++lev) nbox += int64_t(t->boxes[lev].size());
-      const size_t need = size_t(sum_nb2) * size_t(t->Q) * 8 + workspace_need(sum_nb, t->Q, nbox, jb, ni, es, sym);
+      const size_t need = size_t(sum_nb2) * size_t(t->Q) * 8 +
+                          workspace_need(sum_nb, t->Q, nbox, jb, ni, es, sym, sym ? t->nleaf() : 0);
       if (need > device_cap()) throw std::bad_alloc();
     }
     if (!t->dev) upload_tree(t);
     DeviceState* ds = t->dev;
     if (mixed) ensure_mixed_operands(t, st);
-    setup_workspace(t, jb, ni, prec, sym);
+    setup_workspace(t, jb, ni, prec, sym ? kWsSymHT : kWsPlain);
     const int Q = t->Q;
     const bool prof = t->profile != 0;
     {
@@ -1070,6 +1199,7 @@ static char* scratch_base(int dev) {
 struct WorkspaceStash {
   int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;
   uint64_t ws_gen = 0;
+  bool ws_pipe = false;
   DevBuf<char> H, data, HT;
   DevBuf<double> KB;
   DevBuf<GemmDesc> d_half, d_omega, d_l2p, d_ht, d_l2pt;
@@ -1082,6 +1212,7 @@ static void swap_workspace(DeviceState* ds, WorkspaceStash& w) {
   using std::swap;
   swap(ds->ws_jb, w.ws_jb); swap(ds->ws_ni, w.ws_ni); swap(ds->ws_prec, w.ws_prec); swap(ds->ws_sym, w.ws_sym);
   swap(ds->ws_gen, w.ws_gen);
+  swap(ds->ws_pipe, w.ws_pipe);
   swap(ds->H, w.H); swap(ds->data, w.data); swap(ds->HT, w.HT); swap(ds->KB, w.KB);
   swap(ds->d_half, w.d_half); swap(ds->d_omega, w.d_omega); swap(ds->d_l2p, w.d_l2p); swap(ds->d_ht, w.d_ht);
   swap(ds->d_l2pt, w.d_l2pt);
@@ -1134,7 +1265,7 @@ int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32
     for (;;) {
       ScratchArena arena{base, size_t(OCCK_NOALLOC_SCRATCH_BYTES), 0};
       try {
-        setup_workspace(t, jb, ni, OCCK_PREC_FP64, sym, &arena);
+        setup_workspace(t, jb, ni, OCCK_PREC_FP64, sym ? kWsSymHT : kWsPlain, &arena);
         break;
       } catch (const ScratchFull& e) {
         if (opts->jblock > 0 || jb == 1) {

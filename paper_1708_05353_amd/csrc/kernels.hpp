@@ -71,13 +71,15 @@ struct GemmRun {
   int64_t koff;        // every segment contracts k in [koff, K)
   int64_t coff;        // output pointer offset (elements)
   int32_t nlo;         // output columns below nlo are not written
-  int32_t mlim;        // output rows at or beyond mlim are not written (0: no limit)
+  int32_t mlim;        // rows at or beyond mlim are neither read from A (zero) nor written (0: no limit)
   int32_t accumulate;  // C += A B instead of C = A B
   int32_t tile0;       // the launch computes tiles [tile0, tile0 + ntiles)
   int32_t ntiles;
   int32_t nhi;         // output columns at or beyond nhi are not written, tiles starting there skipped (0: none)
   int32_t klim;        // k runs over [koff, min(K, klim)) (0: K)
-  int32_t pad;
+  int32_t amoff;       // A is read at row m + amoff (the rows of B and C are not shifted)
+  int32_t akoff;       // A is read at column k + akoff (the k of B is not shifted)
+  int64_t aptr, bptr;  // element offsets added to the A and (plain) B pointers of every problem
 };
 struct GemmTile {
   int32_t prob, mt, nt, pad;
@@ -422,13 +424,14 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // Per-thread operand pointers at k = koff of segment 0; a K tile advances
   // them by KT rows of k, a new segment moves them by sa_seg / sb_seg.
   const int kfirst = int(koff);
-  const int M = d.M, N = d.N;
+  const int M = run.mlim > 0 && run.mlim < d.M ? run.mlim : d.M;   // rows of A read (the rest read as zero)
+  const int N = d.N;
   const int64_t sam = d.sam, sak = d.sak, sa_seg = d.sa_seg, ldb = d.ldb, sb_seg = d.sb_seg;
   const bool a_row_ok = A_KCONTIG ? (m0 + am < M) : true;
-  const gbl<const T>* A0 = as_global(static_cast<const T*>(d.A));
-  const gbl<const T>* pa = A0 + int64_t(m0 + am) * sam + int64_t(kfirst + ak) * sak;
+  const gbl<const T>* A0 = as_global(static_cast<const T*>(d.A)) + run.aptr;
+  const gbl<const T>* pa = A0 + int64_t(m0 + am + run.amoff) * sam + int64_t(kfirst + ak + run.akoff) * sak;
   const gbl<const T>* cu = as_global(Cuser);
-  const gbl<const T>* B0 = GATHER ? cu : as_global(static_cast<const T*>(d.B));
+  const gbl<const T>* B0 = GATHER ? cu : as_global(static_cast<const T*>(d.B)) + run.bptr;
   const gbl<const T>* pb = GATHER ? cu : B0 + int64_t(kfirst + bk) * ldb + (n0 + bn);
   int kt_in_seg = 0;                          // K tile index within the current segment (next load)
   int seg_loaded = 0;
@@ -697,6 +700,8 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 //   l2p_kernel    K partials from the carried columns (Eq. 18)
 //   l2pt_kernel   K partials from the mirrored columns (Eq. 18, symmetric schedule)
 //   l2p_wide_kernel, l2pt_wide_kernel  the same with a whole leaf per tile
+//   omega_ht_kernel, l2p_ht_kernel, l2p_ht_wide_kernel  Omega and L2P with
+//                 the batch's H read out of HT (symmetric schedule)
 #define OCCK_GEMM_KERNEL(NAME, AK, GA, OUT, SHAPE, NB, DEPTH)                                                  \
   template <int MODE>                                                                                          \
   __global__ __launch_bounds__(256) void NAME(const GemmDesc* __restrict__ descs,                              \
@@ -716,6 +721,13 @@ OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48, 2, 2)
 OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48, 2, 1)
 OCCK_GEMM_KERNEL(l2pt_wide_kernel, true, false, double, GemmCols144, 2, 1)
 OCCK_GEMM_KERNEL(l2p_wide_kernel, true, false, double, GemmRows144, 2, 1)
+// The symmetric schedule reads the half transform of a j batch out of HT
+// (formed once per call for every column) instead of forming it per batch:
+// A is HT^B_q[i][t] (t contiguous), Omega per (leaf, q) with rows j, and the
+// direct L2P over K segments q with k = j.
+OCCK_GEMM_KERNEL(omega_ht_kernel, true, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
+OCCK_GEMM_KERNEL(l2p_ht_kernel, false, false, double, GemmRows48, 2, 2)
+OCCK_GEMM_KERNEL(l2p_ht_wide_kernel, false, false, double, GemmRows144, 2, 1)
 #undef OCCK_GEMM_KERNEL
 
 // --------------------------------------------------------------------------
@@ -840,6 +852,33 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
 }
 
 // --------------------------------------------------------------------------
+// Structural zeros of axis-aligned translations.  A box centre takes the
+// root's midpoint in every unsplit dimension, so on a tree split along x
+// only, every translation displacement lies on the x axis, and on a tree
+// not split along z, in the xy plane.  Such a displacement is unchanged by
+// the reflection z -> -z, under which a real component (l, m, Re|Im) picks
+// up (-1)^(l+m), and the x-axis one also by y -> -y, which flips the sign of
+// the Im components only.  The translation operators (Eqs. 11-13) commute
+// with these reflections, so T[q][q'] vanishes unless q and q' have the same
+// signs; the recurrences of the harmonics produce those zeros exactly (a
+// zero y or z propagates as an exact zero), so skipping them changes no
+// result.  SYM 0: dense; 1: displacements on the x axis (four classes,
+// 25 of the 81 entries at L = 2); 2: displacements in the xy plane (two
+// classes, 45 of 81).
+// --------------------------------------------------------------------------
+__host__ __device__ constexpr int real_class(int q, int sym) {
+  int l = 0;
+  while ((l + 1) * (l + 1) <= q) ++l;
+  const int k = q - l * l;
+  const int m = (k + 1) / 2;
+  const int im = (k != 0 && (k & 1) == 0) ? 1 : 0;
+  return sym == 1 ? 2 * im + ((l + m) & 1) : sym == 2 ? ((l + m) & 1) : 0;
+}
+__host__ __device__ constexpr bool op_entry_live(int i, int k, int sym) {
+  return real_class(i, sym) == real_class(k, sym);
+}
+
+// --------------------------------------------------------------------------
 // Exact-size translations for Q <= 9 (L <= 2) on the vector ALU.  On gfx950
 // the FP64 MFMA peak equals the FP64 vector FMA peak, and a 9x9 operator
 // padded to 16x12 MFMA tiles issues 2.4x the useful products, so small
@@ -852,7 +891,7 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
 // --------------------------------------------------------------------------
 // PIPE: the next source's column values are loaded while the current one's
 // products are formed (two register sets); without it, one source at a time.
-template <class T, int Q, int NC, bool PIPE = true>
+template <class T, int Q, int NC, int SYM, bool PIPE = true>
 __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int KS,
                                    const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                    const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
@@ -892,8 +931,11 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
     double xd[NC][Q];
     for (int c = 0; c < NC; ++c)
       for (int k = 0; k < Q; ++k) xd[c][k] = double(x[c][k]);
+#pragma unroll
     for (int i = 0; i < Q; ++i)
+#pragma unroll
       for (int k = 0; k < Q; ++k) {
+        if (!op_entry_live(i, k, SYM)) continue;   // a structural zero
         const double a = A[(k >> 2) * 64 + i + 16 * (k & 3)];   // T[i][k]
         for (int c = 0; c < NC; ++c) acc[c][i] = fma(a, xd[c][k], acc[c][i]);
       }
@@ -919,7 +961,7 @@ __device__ void translate_vec_tile(T* __restrict__ data, int64_t box_stride, con
       for (int i = 0; i < Q; ++i) store_stream(Y + int64_t(i) * ncol + col[c], T(acc[c][i]));
 }
 
-template <class T, int Q, int NC>
+template <class T, int Q, int NC, int SYM>
 __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
                                                             int KS, const int32_t* __restrict__ tgt_box,
                                                             const int32_t* __restrict__ src_ptr,
@@ -929,7 +971,7 @@ __global__ __launch_bounds__(256) void translate_vec_kernel(T* __restrict__ data
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
-  translate_vec_tile<T, Q, NC>(data, box_stride, cm, KS, tgt_box, src_ptr, src_box, src_op, ops,
+  translate_vec_tile<T, Q, NC, SYM>(data, box_stride, cm, KS, tgt_box, src_ptr, src_box, src_op, ops,
                                int(logical % ntgt), logical / ntgt);
 }
 
@@ -954,7 +996,7 @@ struct WalkStep {   // one step of an upward or downward walk program
 enum { UP_LEAF = 0, UP_CLOSE = 1 };
 constexpr int kUpWalkLevels = 6;   // accumulator levels (below the walk's root level) held in registers
 
-template <class T, int Q, int NLV>
+template <class T, int Q, int NLV, int SYM>
 __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                       const int32_t* __restrict__ prog_ptr,
                                                       const WalkStep* __restrict__ prog, const T* __restrict__ ops,
@@ -982,8 +1024,11 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
   // y += T_op x, in the order of the level-by-level kernel
   auto apply = [&](T (&y)[Q], const T (&x)[Q], int op) {
     const cst<T>* A = as_const(ops) + int64_t(op) * opsz;
+#pragma unroll
     for (int i = 0; i < Q; ++i)
-      for (int k = 0; k < Q; ++k) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (op_entry_live(i, k, SYM)) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
   };
   auto next_leaf = [&](int s) {
     while (s < p1 && pg[s].kind != UP_LEAF) ++s;
@@ -1034,11 +1079,14 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
 enum { DN_BEGIN = 0, DN_SRC = 1, DN_STORE = 2 };
 constexpr int kDownWalkLevels = 2;   // accumulator levels (root level..D) held in registers
 
-template <class T, int Q, int NLV>
+// store_shift: box slots added to every stored leaf (a second leaf Mloc
+// region, so that the next j batch's walk can run while the L2P of this one
+// still reads the first).
+template <class T, int Q, int NLV, int SYM>
 __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                         const int32_t* __restrict__ prog_ptr,
                                                         const WalkStep* __restrict__ prog, const T* __restrict__ ops,
-                                                        int nroots, int64_t nblocks) {
+                                                        int nroots, int64_t nblocks, int64_t store_shift) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
@@ -1061,8 +1109,11 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
     for (int i = 0; i < Q; ++i) acc[l][i] = T(0);
   auto apply = [&](T (&y)[Q], const T (&x)[Q], int op) {   // y += T_op x, as the level-by-level kernel
     const cst<T>* A = as_const(ops) + int64_t(op) * opsz;
+#pragma unroll
     for (int i = 0; i < Q; ++i)
-      for (int k = 0; k < Q; ++k) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
+#pragma unroll
+      for (int k = 0; k < Q; ++k)
+        if (op_entry_live(i, k, SYM)) y[i] = fma(A[(k >> 2) * 64 + i + 16 * (k & 3)], x[k], y[i]);
   };
   auto next_src = [&](int s) {
     while (s < p1 && pg[s].kind != DN_SRC) ++s;
@@ -1093,7 +1144,7 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
           if (l > 0 && in.op >= 0) apply(acc[l], acc[l > 0 ? l - 1 : 0], in.op);
         }
     } else {
-      gbl<T>* Y = as_global(data) + int64_t(in.box) * box_stride;
+      gbl<T>* Y = as_global(data) + (int64_t(in.box) + store_shift) * box_stride;
 #pragma unroll
       for (int l = 0; l < NLV; ++l)
         if (l == in.level && ok)

@@ -91,6 +91,8 @@ EXPORTS = {
     "occk_batch_create": (ct.c_int32, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.POINTER(_Opts),
                                        ct.POINTER(ct.c_void_p)]),
     "occk_batch_run": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p]),
+    "occk_far_K_batched": (ct.c_int32, [ct.c_int32, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.c_void_p, ct.c_void_p, ct.c_void_p]),
     "occk_batch_tune": (ct.c_int32, [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                      ct.c_void_p]),
     "occk_batch_shape": (ct.c_int32, [ct.c_void_p, ct.POINTER(ct.c_int32), ct.c_void_p, ct.c_int32]),
@@ -455,6 +457,27 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+def far_K_batched(trees, Cs, Ks, precision: int = PREC_FP32, jblock: int = 0, stream=None):
+    """K^ff of every system in one persistent launch (occk_far_K_batched: a
+    plan made, run and freed in one call; returns after the launch)."""
+    import torch
+    n = len(trees)
+    if not (len(Cs) == len(Ks) == n):
+        raise ValueError("one C and one K per tree")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    th = (ct.c_void_p * n)(*[t.handle.value for t in trees])
+    cp = (ct.c_void_p * n)(*[c.data_ptr() for c in Cs])
+    kp = (ct.c_void_p * n)(*[k.data_ptr() for k in Ks])
+    ldc = np.array([c.stride(0) for c in Cs], np.int64)
+    ldk = np.array([k.stride(0) for k in Ks], np.int64)
+    no = np.array([c.shape[1] for c in Cs], np.int32)
+    opts = _Opts(int(precision), RANK_FIXED, None, int(jblock), 0)
+    _check(lib().occk_far_K_batched(n, ct.cast(th, ct.c_void_p), ct.cast(cp, ct.c_void_p), ldc.ctypes.data,
+                                    no.ctypes.data, ct.byref(opts), ct.cast(kp, ct.c_void_p), ldk.ctypes.data,
+                                    ct.c_void_p(stream.cuda_stream)))
 
 
 class Selector:

@@ -201,3 +201,21 @@ def test_walks_equal_level_passes_bitwise():
     b.free()
     tr.free()
     assert np.array_equal(K1.cpu().numpy(), K2.cpu().numpy())
+
+
+def test_one_call_batched_equals_the_plan(systems):
+    """occk_far_K_batched (plan made, run and freed in one call) gives the
+    plan's result bit for bit."""
+    import torch
+    from paper_1708_05353_amd import occk
+    trees = [tr for _, _, tr in systems]
+    Cs, Ks = _io(systems)
+    b = occk.Batch(trees, [C.shape[1] for _, C, _ in systems], occk.PREC_FP32)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    b.free()
+    _, K1 = _io(systems)
+    occk.far_K_batched(trees, Cs, K1, precision=occk.PREC_FP32)
+    torch.cuda.synchronize()
+    for a, c in zip(Ks, K1):
+        assert torch.equal(a, c)

@@ -225,6 +225,33 @@ def test_far_K_validates_before_device_work():
     assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(learned), K, 20, None) == occk.ESTATE
     neg = occk._Opts(0, 0, None, -4, 0)
     assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(neg), K, 20, None) == occk.EINVAL
+    # occupied-pair screening: a finite threshold >= 0, and only over coinciding i and j ranges
+    for tau in (-1e-3, float("nan"), float("inf")):
+        assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(occk._Opts(0, 0, None, 0, 0, tau)), K, 20, None) == occk.EINVAL
+    scr = occk._Opts(0, 0, None, 0, 0, 1e-6)
+    assert f(C, 20, 20, 0, 10, 0, 20, ct.byref(scr), K, 20, None) == occk.EINVAL
+    assert "pair_thresh" in occk.lib().occk_last_error().decode()
+
+
+def test_batched_one_call_validates_before_device_work():
+    """occk_far_K_batched rejects bad counts and NULL or misaligned I/O arrays
+    on the host, before any plan is made (this runs without a GPU)."""
+    wl = workloads.tiny_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    L = occk.lib()
+    th = (ct.c_void_p * 1)(tr.handle.value)
+    no = np.array([20], np.int32)
+    ld = np.array([20], np.int64)
+    opts = occk._Opts(1, 0, None, 0, 0)
+    good = (ct.c_void_p * 1)(0x100000)
+    odd = (ct.c_void_p * 1)(0x100004)
+    f = L.occk_far_K_batched
+    assert f(0, ct.cast(th, ct.c_void_p), ct.cast(good, ct.c_void_p), ld.ctypes.data, no.ctypes.data,
+             ct.byref(opts), ct.cast(good, ct.c_void_p), ld.ctypes.data, None) == occk.EINVAL
+    assert f(1, ct.cast(th, ct.c_void_p), None, ld.ctypes.data, no.ctypes.data, ct.byref(opts),
+             ct.cast(good, ct.c_void_p), ld.ctypes.data, None) == occk.EINVAL
+    assert f(1, ct.cast(th, ct.c_void_p), ct.cast(odd, ct.c_void_p), ld.ctypes.data, no.ctypes.data,
+             ct.byref(opts), ct.cast(good, ct.c_void_p), ld.ctypes.data, None) == occk.EINVAL
 
 
 def test_device_byte_cap_gives_enomem_before_device_work(monkeypatch):

@@ -176,3 +176,27 @@ def test_m2l_potential_of_point_charges():
             assert err < prev
         prev = err
     assert prev < 1e-6
+
+
+@pytest.mark.parametrize("L", [2, 4])
+def test_axis_aligned_translations_are_block_diagonal(L):
+    """A displacement on the x axis is unchanged by the reflections y -> -y
+    and z -> -z, one in the xy plane by z -> -z.  The translation operators
+    commute with them, so for x-axis displacements every M2M, M2L and L2L
+    matrix is real and couples (l, m) to (l', m') only when l + m and l' + m'
+    have the same parity; for xy-plane displacements the parity rule holds.
+    The zeros are exact (a zero y or z stays zero through the harmonics'
+    recurrences), which is what lets the library skip them."""
+    Q = H.ncomp(L)
+    par = np.array([(l + m) & 1 for l in range(L + 1) for m in range(-l, l + 1)])
+    cross = par[:, None] != par[None, :]
+    for d in ([2.7, 0.0, 0.0], [-5.1, 0.0, 0.0], [3.3, -1.9, 0.0], [0.0, 4.2, 0.0]):
+        d = np.array(d)
+        for T in (m2m_matrix(L, d), l2l_matrix(L, d), m2l_matrix(L, 4.0 * d)):
+            assert T.shape == (Q, Q)
+            assert np.all(T[cross] == 0), d
+            if d[1] == 0.0:
+                assert np.all(T.imag == 0), d
+    # a generic displacement has no such zeros
+    T = m2l_matrix(L, np.array([2.1, -1.3, 0.7]))
+    assert np.count_nonzero(T[cross]) == np.count_nonzero(cross)
