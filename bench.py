@@ -6,12 +6,16 @@ translations, L2P and the K reduction) for all occupied i and j, on the
 alkane-chain workload (C400H802 stand-in: nbasis 9610, nocc 1601, 1-D tree of
 depth 8, ws 2, L = 2), inputs resident in HBM.  Prints one JSON line.
 
-value = algorithmic flops of one call / measured time (GFLOP/s).  The
-roofline object reports the dominant kernel class, timed with HIP events on
-the library's stream inside the timed region.  The "mixed" object times the
-FP32 path on the same inputs and gives its error against the FP64 result.  cpu_baseline times the FP64
-oracle on a bounded j sample of the same workload and scales it linearly in
-the number of j columns.
+value = algorithmic flops of one call / measured time (GFLOP/s), in the
+library's default schedule (the L2P of a j batch on a second stream,
+overlapping the next batch's translations).  The kernels and the roofline
+object come from the same calls timed again in the one-stream schedule, where
+every kernel runs alone, with HIP events on the library's stream (the
+kernel with the largest time per call is the roofline's).  The "mixed"
+object times the FP32 path on the same inputs and gives its error against
+the FP64 result.  hbm_copy is the rate of a plain device copy on the box.
+cpu_baseline times the FP64 oracle on a bounded j sample of the same
+workload and scales it linearly in the number of j columns.
 """
 from __future__ import annotations
 
@@ -792,6 +796,8 @@ def main():
     ap.add_argument("--lmax", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--jblock", type=int, default=0)
+    ap.add_argument("--one-stream", action="store_true",
+                    help="time the one-stream schedule (every kernel alone; for kernel traces and counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 mixed-path comparison")
     ap.add_argument("--no-coulomb", action="store_true", help="skip the far-field Coulomb J leg")
@@ -842,33 +848,44 @@ def main():
     Cd = torch.from_numpy(C).to(dev)
     K = torch.zeros((wl.system.nbasis, nocc), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream(dev)
-    call = lambda: occk.far_K(tree, Cd, K, precision=prec, jblock=args.jblock, stream=stream)
+    call = lambda one: occk.far_K(tree, Cd, K, precision=prec, jblock=args.jblock, stream=stream, one_stream=one)
     t0 = time.perf_counter()
-    call()                      # uploads the tree and allocates the workspace
+    call(args.one_stream)       # uploads the tree and allocates the workspace
     torch.cuda.synchronize()
     t_first = time.perf_counter() - t0
     print(f"[bench] orbitals {t_orb:.1f}s tree {t_tree:.1f}s first call {t_first:.1f}s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        call()
+        call(args.one_stream)
     torch.cuda.synchronize()
     jb = tree.workspace_jblock()
-    tree.profile(True)
-    tree.profile_read()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        call()
+        call(args.one_stream)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    # Kernel timings: the same calls in the one-stream schedule, where every
+    # kernel runs alone (in the default schedule the L2P of a batch overlaps
+    # the next batch's translations, and a kernel's events then span both).
+    tree.profile(True)
+    tree.profile_read()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        call(True)
+    e1.record(stream)
+    torch.cuda.synchronize()
     prof = tree.profile_read()
     tree.profile(False)
-    ms = ev0.elapsed_time(ev1) / args.steps
+    ms_one = e0.elapsed_time(e1) / args.steps
     fl = tree.flops(nocc, nocc, symmetric=True)
     value = fl["total"] / (ms * 1e-3) / 1e9
-    print(f"[bench] {ms:.2f} ms/step, {value:.0f} GFLOP/s", file=sys.stderr, flush=True)
+    print(f"[bench] {ms:.2f} ms/step, {value:.0f} GFLOP/s ({ms_one:.2f} ms/step in one stream)", file=sys.stderr,
+          flush=True)
 
     costs = class_costs(tree.info, nocc, jb, args.precision)
     breakdown = {}
@@ -959,7 +976,10 @@ def main():
                    "precision": args.precision, "jblock": jb, "flops_per_step": fl["total"],
                    "flops_per_step_all_columns": tree.flops(nocc, nocc)["total"],
                    "pct_peak": round(100 * value * 1e9 / PEAK_FLOPS[args.precision], 2),
-                   "tree_build_s": round(t_tree, 2), "wall_s_timed": round(wall, 3)},
+                   "tree_build_s": round(t_tree, 2), "wall_s_timed": round(wall, 3),
+                   "schedule": "one stream" if args.one_stream else "two streams (L2P of a j batch overlapping the "
+                                                                     "next batch's translations)",
+                   "ms_per_step_one_stream": round(ms_one, 3)},
         "roofline": roof,
         "kernels": kernels,
         "breakdown": breakdown,
@@ -971,7 +991,8 @@ def main():
         # FP64 operators and K accumulation; error against this FP64 result
         K64 = K.clone()
         Km = torch.zeros_like(K)
-        mcall = lambda: occk.far_K(tree, Cd, Km, precision=occk.PREC_FP32, jblock=args.jblock, stream=stream)
+        mcall = lambda: occk.far_K(tree, Cd, Km, precision=occk.PREC_FP32, jblock=args.jblock, stream=stream,
+                                   one_stream=args.one_stream)
         mcall()
         for _ in range(args.warmup):
             mcall()

@@ -154,6 +154,14 @@ typedef struct occk_far_opts {
                                   this a band), so every pair inside the band is
                                   evaluated, kept or not.  Needs i0 == j0 and
                                   i1 == j1; synchronises the stream once per call */
+  int32_t one_stream;          /* 0: when the i and j ranges coincide and the tree
+                                  runs its downward translations as walks, the
+                                  L2P of each j batch runs on a second stream of
+                                  the library, overlapping the next batch's Omega
+                                  and translations (the call still completes in
+                                  order on hip_stream); 1: everything on
+                                  hip_stream, one kernel at a time (kernel
+                                  timings, profiles) */
 } occk_far_opts;
 
 /* Returns OCCK_ABI_VERSION. */

@@ -296,6 +296,10 @@ static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc
     set_error(f + ": jblock must be >= 0");
     return OCCK_EINVAL;
   }
+  if (o.one_stream != 0 && o.one_stream != 1) {
+    set_error(f + ": one_stream must be 0 or 1");
+    return OCCK_EINVAL;
+  }
   if (!(o.pair_thresh >= 0.0) || !std::isfinite(o.pair_thresh) ||
       (o.pair_thresh > 0.0 && (i0 != j0 || i1 != j1))) {
     set_error(f + ": pair_thresh must be finite and >= 0, and screening needs i0 == j0 and i1 == j1");

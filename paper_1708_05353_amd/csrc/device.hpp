@@ -135,12 +135,13 @@ struct DeviceState {
   // per workspace shape (j batch, n_i, precision, symmetric schedule)
   int ws_jb = -1, ws_ni = -1, ws_prec = -1, ws_sym = -1;   // ws_sym: kWsPlain, kWsSym, kWsSymHT
   uint64_t ws_gen = 0;            // incremented whenever the workspace buffers are rebuilt
-  // two-stream schedule (symmetric, downward walks): the L2P of j batch k on
-  // st2 while batch k+1's Omega and translations run on the caller's stream;
-  // the leaf Mloc of odd batches go to nleaf extra box rows after the Mloc
+  // two-stream schedule (symmetric, both walks): Omega and the L2P on st2,
+  // the translations on the caller's stream; the leaf Mloc and the leaf
+  // Omega of odd batches go to 2 nleaf extra box rows after the Mloc
   bool ws_pipe = false;           // the box data have those extra rows
   hipStream_t st2 = nullptr;
-  hipEvent_t ev_mloc[2] = {nullptr, nullptr}, ev_l2p[2] = {nullptr, nullptr}, ev_join = nullptr;
+  hipEvent_t ev_mloc[2] = {nullptr, nullptr}, ev_l2p[2] = {nullptr, nullptr}, ev_omega[2] = {nullptr, nullptr};
+  hipEvent_t ev_start = nullptr, ev_join = nullptr;
   DevBuf<char> H, data;           // element type of the precision (double / float)
   DevBuf<char> HT;                // symmetric schedule: H for every column, [leaf][q][i][t]
   DevBuf<double> KB;              // per-leaf K partials, always FP64

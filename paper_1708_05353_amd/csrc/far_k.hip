@@ -349,8 +349,8 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, int sym_mode, ScratchAre
   // the two-stream schedule (occk_far_K, symmetric, downward walks; not in
   // the fixed scratch region) keeps the leaf Mloc of odd batches in nleaf
   // extra box rows
-  const bool pipe = from_ht && !arena && ds->dnw_nroots > 0;
-  const int64_t extra = pipe ? nl : 0;
+  const bool pipe = from_ht && !arena && ds->dnw_nroots > 0 && ds->upw_nroots > 0;
+  const int64_t extra = pipe ? 2 * nl : 0;   // second leaf Mloc rows, then second leaf Omega rows
   const size_t need = workspace_need(sum_nb, Q, ds->nbox, jb, ni, es, sym, extra);
   if (!arena && need + ds->bytes > device_cap()) throw std::bad_alloc();
   // buffers and tables: allocated, or placed in the arena
@@ -607,9 +607,13 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
 
 // the upward (up) or downward walk over every subtree below level lmin
 // (setup built the programs)
+// store_shift (downward): box rows added to every stored leaf; load_shift:
+// box rows added to every leaf read (upward) or to every source read whose
+// box lies in [src_lo, src_hi) (downward)
 template <class T>
 void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int nroots, int nlv, bool up, T* data,
-                 int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st, int64_t store_shift = 0) {
+                 int64_t box_stride, const ColMap& cm, const T* ops, hipStream_t st, int64_t store_shift = 0,
+                 int64_t load_shift = 0, int32_t src_lo = 0, int32_t src_hi = 0) {
   if (cm.nvalid <= 0 || nroots == 0) return;
   const int Q = t->Q, KS = ksteps_of(Q);
   const int64_t nblocks = ((cm.nvalid + 255) / 256) * nroots;
@@ -620,10 +624,11 @@ void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int n
 #define OCCK_WS(QQ, NL, SY)                                                                                        \
   if (up)                                                                                                          \
     hipLaunchKernelGGL((up_walk_kernel<T, QQ, NL, SY>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride,  \
-                       cm, KS, pptr, prog, ops, nroots, nblocks);                                                  \
+                       cm, KS, pptr, prog, ops, nroots, nblocks, load_shift);                                      \
   else                                                                                                             \
     hipLaunchKernelGGL((down_walk_kernel<T, QQ, NL, SY>), dim3(unsigned(grid)), dim3(256), 0, st, data,            \
-                       box_stride, cm, KS, pptr, prog, ops, nroots, nblocks, store_shift)
+                       box_stride, cm, KS, pptr, prog, ops, nroots, nblocks, store_shift, load_shift, src_lo,  \
+                       src_hi)
 #define OCCK_W(QQ, NL)          \
   if (xaxis && QQ > 1) {        \
     OCCK_WS(QQ, NL, 1);         \
@@ -683,7 +688,8 @@ void device_free(Tree* t) {
 static void free_state(DeviceState* ds) {
   for (hipEvent_t e : ds->ev_pool) (void)hipEventDestroy(e);
   ds->ev_pool.clear();
-  for (hipEvent_t e : {ds->ev_mloc[0], ds->ev_mloc[1], ds->ev_l2p[0], ds->ev_l2p[1], ds->ev_join})
+  for (hipEvent_t e : {ds->ev_mloc[0], ds->ev_mloc[1], ds->ev_l2p[0], ds->ev_l2p[1], ds->ev_omega[0],
+                       ds->ev_omega[1], ds->ev_start, ds->ev_join})
     if (e) (void)hipEventDestroy(e);
   if (ds->st2) (void)hipStreamDestroy(ds->st2);
   ds->Of.free();
@@ -892,10 +898,24 @@ static std::vector<int> pair_bands(Tree* t, DeviceState* ds, const double* C, in
 // i lies in an earlier batch.  The diagonal block (i, j both in J) is
 // carried in full and counted once.  H of the batch is not formed again:
 // HT, formed once per call for every column, holds it (rows jstart + j).
+//
+// Two streams (symmetric schedule with both walks, two_streams): the MFMA
+// contractions (Omega, L2P) run on the library's stream st2 and the
+// translations, bound by memory traffic, on the caller's stream, so that
+// Omega of batch k+1 and the L2P of batch k overlap the translations of
+// batch k+1.  Odd batches keep their leaf Omega and leaf Mloc in the extra
+// box rows after the Mloc (nleaf rows each), so that two batches are in
+// flight.  Order: st waits for Omega of batch k before its upward walk and
+// for the L2P of batch k-2 before its downward walk writes that batch's
+// leaf Mloc rows; st2 waits for the downward walk of batch k before its
+// L2P (which also frees the leaf Omega rows of batch k for batch k+2's
+// Omega, issued after it on st2); st waits for st2's last L2P before the
+// reduction.
 template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
                         int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
-                        bool stop_after_up = false, bool sym = false, const std::vector<int>* band = nullptr) {
+                        bool stop_after_up = false, bool sym = false, const std::vector<int>* band = nullptr,
+                        bool two_streams = false) {
   using T = typename ModeT<MODE>::T;
   const int Q = t->Q;
   const int64_t ncol = int64_t(jb) * ni;
@@ -904,22 +924,171 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops.p) : reinterpret_cast<const T*>(ds->opsf.p);
   const int nj = j1 - j0;
   const int nblk = (nj + jb - 1) / jb;
-  // Two streams (symmetric schedule with downward walks): the L2P of batch
-  // k runs on st2 while batch k+1's Omega and translations run on st.  The
-  // leaf Mloc of odd batches go to the extra rows after the Mloc; st waits
-  // for the L2P of batch k-2 before its downward walk overwrites that
-  // region, st2 for the walk of batch k before its L2P, and st for st2's
-  // last L2P before the reduction.
-  const bool pipe = sym && !sel && !stop_after_up && ds->ws_pipe && ds->dnw_nroots > 0 && nblk > 1;
-  hipStream_t stl = st;   // the L2P's stream
+  const bool pipe = two_streams && sym && !sel && !stop_after_up && ds->ws_pipe && ds->dnw_nroots > 0 &&
+                    ds->upw_nroots > 0 && nblk > 1;
+  hipStream_t stg = st;   // the stream of Omega and the L2P
   if (pipe) {
     if (!ds->st2) {
       HIP_OK(hipStreamCreateWithFlags(&ds->st2, hipStreamNonBlocking));   // default priority
-      for (hipEvent_t* e : {&ds->ev_mloc[0], &ds->ev_mloc[1], &ds->ev_l2p[0], &ds->ev_l2p[1], &ds->ev_join})
+      for (hipEvent_t* e : {&ds->ev_mloc[0], &ds->ev_mloc[1], &ds->ev_l2p[0], &ds->ev_l2p[1], &ds->ev_omega[0],
+                            &ds->ev_omega[1], &ds->ev_start, &ds->ev_join})
         HIP_OK(hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
-    stl = ds->st2;
+    stg = ds->st2;
   }
+  // box rows of the second leaf Omega and leaf Mloc regions (odd batches)
+  const int nl = t->nleaf();
+  const int32_t leaf0 = ds->leaf_box.empty() ? 0 : ds->leaf_box[0];   // first leaf box slot
+  const int64_t omega_shift = int64_t(2) * ds->nbox + nl - leaf0;     // leaf Omega rows -> the second region
+  const int64_t mloc_shift = nl;                                      // leaf Mloc rows -> the second region
+
+  struct Batch {
+    int64_t jrel, jstart, istart, iend;
+    int jbk, ct0;
+    bool odd;
+    ColMap cm;
+  };
+  auto batch = [&](int kb) {
+    Batch b;
+    b.jrel = int64_t(kb) * jb;                      // first j of the batch, relative to j0
+    b.jstart = j0 + b.jrel;
+    b.istart = sym ? b.jrel : 0;                    // first carried i (relative to i0)
+    b.jbk = int(std::min<int64_t>(jb, nj - b.jrel));
+    b.odd = pipe && (kb & 1);
+    // occupied-pair screening: the batch carries i in [istart, iend) only
+    b.iend = band ? int64_t((*band)[size_t(kb)]) : int64_t(ni);
+    b.cm.ncol = ncol;
+    b.cm.ni = ni;
+    b.cm.istart = b.istart;
+    b.cm.iend = band ? b.iend : 0;
+    // the symmetric schedule carries the batch's own j only (the last batch
+    // may be short: its Omega rows past jbk are not formed)
+    b.cm.nvalid = int64_t(sym ? b.jbk : jb) * (b.iend - b.istart);
+    b.ct0 = int(b.istart / 64);                     // first column tile touching i >= istart
+    return b;
+  };
+
+  // half transform (all-column schedule only) and Omega, on stream s
+  auto omega = [&](int kb, const Batch& b, hipStream_t s) {
+    if (!sym) {   // the symmetric schedule reads the batch's H out of HT
+      ProfScope ps(ds, prof, OCCK_K_HALF, s);
+      GemmRun r{};
+      r.boff = b.jstart;
+      r.blim = j1;
+      r.ntiles = ds->n_half;
+      hipLaunchKernelGGL((half_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_half.p,
+                         ds->t_half.p, Cg, ldcg, r);
+    }
+    ProfScope ps(ds, prof, OCCK_K_OMEGA, s);
+    GemmRun r{};
+    r.boff = i0;
+    r.blim = i1;
+    r.nhi = band ? int(b.iend) : 0;
+    r.tile0 = ds->omega_nt_start[size_t(b.ct0 / 4)];
+    r.ntiles = ds->omega_nt_start[size_t(b.ct0 / 4) + 1] - r.tile0;
+    if (sym) {   // per (leaf, q): rows j of HT_q from the batch's first j
+      r.amoff = int32_t(b.jrel);
+      r.mlim = b.jbk;
+      r.coff = b.odd ? omega_shift * box_stride : 0;   // the batch's leaf Omega rows
+      hipLaunchKernelGGL((omega_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_omega.p,
+                         ds->t_omega.p, Cg, ldcg, r);
+    } else {
+      hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_omega.p,
+                         ds->t_omega.p, Cg, ldcg, r);
+    }
+    (void)kb;
+  };
+
+  // upward passes on stream s
+  auto upward = [&](const Batch& b, hipStream_t s) {
+    ProfScope ps(ds, prof, OCCK_K_UP, s, ds->upw_nroots > 0 ? 1 + ds->upw_lroot - t->lmin : int(ds->up.size()));
+    // ds->up holds levels D-1 down to lmin; the walk covers those at or below its root level
+    size_t k0 = 0;
+    if (ds->upw_nroots > 0) {
+      ProfScope ps_w(ds, prof, OCCK_K_UP_WALK, s);
+      launch_walk<T>(t, ds->upw_ptr.p, ds->upw_prog.p, ds->upw_nroots, ds->upw_nlv, true, data, box_stride, b.cm,
+                     ops, s, 0, b.odd ? omega_shift : 0, 0, 0);
+      k0 = size_t(t->params.depth - ds->upw_lroot);
+    }
+    for (size_t k = k0; k < ds->up.size(); ++k) launch_translate<T>(t, ds->up[k], data, box_stride, b.cm, ops, s);
+  };
+
+  // learned ranks and downward passes on stream s; wait_before_walk is
+  // called just before the downward walk
+  auto downward = [&](const Batch& b, hipStream_t s, auto&& wait_before_walk) {
+    if (sel) {
+      ProfScope ps(ds, prof, OCCK_K_SELECT, s, 1 + int(ds->down.size()));
+      learned_ranks<T>(t, ds, sel, data, box_stride, b.cm, s);
+    }
+    // ds->down holds levels lmin..D; the walk covers those at or below its root level
+    const bool walk = !sel && ds->dnw_nroots > 0;
+    const size_t k1 = walk ? size_t(ds->dnw_lroot - t->lmin) : ds->down.size();
+    ProfScope ps(ds, prof, OCCK_K_DOWN, s, int(k1) + (walk ? 1 : 0));
+    for (size_t k = 0; k < k1; ++k)
+      launch_translate<T>(t, ds->down[k], data, box_stride, b.cm, ops, s, sel ? ds->down[k].rank.p : nullptr);
+    if (walk) {
+      wait_before_walk();
+      ProfScope ps_w(ds, prof, OCCK_K_DOWN_WALK, s);
+      launch_walk<T>(t, ds->dnw_ptr.p, ds->dnw_prog.p, ds->dnw_nroots, ds->dnw_nlv, false, data, box_stride, b.cm,
+                     ops, s, b.odd ? mloc_shift : 0, b.odd ? omega_shift : 0, leaf0, leaf0 + nl);
+    }
+  };
+
+  // direct and mirrored L2P on stream s
+  auto l2p = [&](int kb, const Batch& b, hipStream_t s) {
+    const int64_t mshift = b.odd ? mloc_shift * box_stride : 0;   // the batch's leaf Mloc rows
+    ProfScope ps(ds, prof, OCCK_K_L2P, s, sym && b.jrel + jb < b.iend ? 2 : 1);
+    GemmRun r{};
+    r.accumulate = (kb > 0 || band) ? 1 : 0;   // with screening KB starts cleared
+    r.nlo = int(b.istart);
+    r.nhi = band ? int(b.iend) : 0;
+    r.bptr = mshift;
+    ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, s);
+    if (sym) {   // K segments q, k = j over the batch's own j, A out of HT
+      r.akoff = int32_t(b.jrel);
+      r.klim = b.jbk;
+    }
+    if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
+      r.tile0 = ds->l2pw_nt_start[size_t(b.ct0 / 4)];
+      r.ntiles = ds->l2pw_nt_start[size_t(b.ct0 / 4) + 1] - r.tile0;
+      if (sym)
+        hipLaunchKernelGGL((l2p_ht_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_l2p.p,
+                           ds->t_l2pw.p, Cg, ldcg, r);
+      else
+        hipLaunchKernelGGL((l2p_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_l2p.p,
+                           ds->t_l2pw.p, Cg, ldcg, r);
+    } else {
+      r.tile0 = ds->l2p_nt_start[size_t(b.ct0 / 4)];
+      r.ntiles = ds->l2p_nt_start[size_t(b.ct0 / 4) + 1] - r.tile0;
+      if (sym)
+        hipLaunchKernelGGL((l2p_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_l2p.p,
+                           ds->t_l2p.p, Cg, ldcg, r);
+      else
+        hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, s, ds->d_l2p.p,
+                           ds->t_l2p.p, Cg, ldcg, r);
+    }
+    ps_d.close();
+    if (sym && b.jrel + jb < b.iend) {
+      ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, s);
+      GemmRun m{};
+      m.accumulate = 1;
+      m.klim = band ? int(b.iend) : 0;
+      m.koff = b.jrel + jb;
+      m.aptr = mshift;
+      m.coff = b.jrel;
+      m.mlim = b.jbk;
+      if (MODE <= kModeF32 && ds->n_l2ptw > 0) {   // the split-BF16 modes would need 256+ VGPRs
+        m.ntiles = ds->n_l2ptw;
+        hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, s, ds->d_l2pt.p,
+                           ds->t_l2ptw.p, Cg, ldcg, m);
+      } else {
+        m.ntiles = ds->n_l2pt;
+        hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, s, ds->d_l2pt.p,
+                           ds->t_l2pt.p, Cg, ldcg, m);
+      }
+    }
+  };
+
   if (sym) {   // HT for every column, once per call
     ProfScope ps(ds, prof, OCCK_K_HALF, st);
     ProfScope ps_ht(ds, prof, OCCK_K_HT, st);
@@ -930,146 +1099,43 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     hipLaunchKernelGGL((half_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_ht.p,
                        ds->t_ht.p, Cg, ldcg, r);
   }
+  if (!pipe) {
+    for (int kb = 0; kb < nblk; ++kb) {
+      const Batch b = batch(kb);
+      omega(kb, b, st);
+      upward(b, st);
+      if (stop_after_up) return;
+      downward(b, st, [] {});
+      l2p(kb, b, st);
+      HIP_OK(hipGetLastError());
+    }
+    return;
+  }
+  // two streams; every wait below is issued after the record it waits for
+  HIP_OK(hipEventRecord(ds->ev_start, st));          // HT (and any earlier work on st) before Omega
+  HIP_OK(hipStreamWaitEvent(stg, ds->ev_start, 0));
+  omega(0, batch(0), stg);
+  HIP_OK(hipEventRecord(ds->ev_omega[0], stg));
   for (int kb = 0; kb < nblk; ++kb) {
-    const int64_t jrel = int64_t(kb) * jb;          // first j of the batch, relative to j0
-    const int64_t jstart = j0 + jrel;
-    const int64_t istart = sym ? jrel : 0;         // first carried i (relative to i0)
-    const int jbk = int(std::min<int64_t>(jb, nj - jrel));
-    const int buf = pipe ? (kb & 1) : 0;                  // leaf Mloc region of the batch
-    const int64_t lshift = buf ? int64_t(t->nleaf()) : 0;   // its offset in box rows
-    // occupied-pair screening: the batch carries i in [istart, iend) only
-    const int64_t iend = band ? int64_t((*band)[size_t(kb)]) : int64_t(ni);
-    ColMap cm;
-    cm.ncol = ncol;
-    cm.ni = ni;
-    cm.istart = istart;
-    cm.iend = band ? iend : 0;
-    // the symmetric schedule carries the batch's own j only (the last batch
-    // may be short: its Omega rows past jbk are not formed)
-    cm.nvalid = int64_t(sym ? jbk : jb) * (iend - istart);
-    const int ct0 = int(istart / 64);              // first column tile touching i >= istart
-    if (!sym) {   // the symmetric schedule reads the batch's H out of HT
-      ProfScope ps(ds, prof, OCCK_K_HALF, st);
-      GemmRun r{};
-      r.boff = jstart;
-      r.blim = j1;
-      r.ntiles = ds->n_half;
-      hipLaunchKernelGGL((half_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st, ds->d_half.p,
-                         ds->t_half.p, Cg, ldcg, r);
+    const Batch b = batch(kb);
+    const int p = kb & 1;
+    HIP_OK(hipStreamWaitEvent(st, ds->ev_omega[p], 0));
+    upward(b, st);
+    downward(b, st, [&] {
+      if (kb >= 2) HIP_OK(hipStreamWaitEvent(st, ds->ev_l2p[p], 0));   // batch kb-2 has read these Mloc rows
+    });
+    HIP_OK(hipEventRecord(ds->ev_mloc[p], st));
+    if (kb + 1 < nblk) {   // its leaf Omega rows were last read by batch kb-1, whose L2P precedes on st2
+      omega(kb + 1, batch(kb + 1), stg);
+      HIP_OK(hipEventRecord(ds->ev_omega[p ^ 1], stg));
     }
-    {
-      ProfScope ps(ds, prof, OCCK_K_OMEGA, st);
-      GemmRun r{};
-      r.boff = i0;
-      r.blim = i1;
-      r.nhi = band ? int(iend) : 0;
-      r.tile0 = ds->omega_nt_start[size_t(ct0 / 4)];
-      r.ntiles = ds->omega_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-      if (sym) {   // per (leaf, q): rows j of HT_q from the batch's first j
-        r.amoff = int32_t(jrel);
-        r.mlim = jbk;
-        hipLaunchKernelGGL((omega_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                           ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
-      } else {
-        hipLaunchKernelGGL((omega_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, st,
-                           ds->d_omega.p, ds->t_omega.p, Cg, ldcg, r);
-      }
-    }
-    {
-      ProfScope ps(ds, prof, OCCK_K_UP, st,
-                   ds->upw_nroots > 0 ? 1 + ds->upw_lroot - t->lmin : int(ds->up.size()));
-      // ds->up holds levels D-1 down to lmin; the walk covers those at or below its root level
-      size_t k0 = 0;
-      if (ds->upw_nroots > 0) {
-        ProfScope ps_w(ds, prof, OCCK_K_UP_WALK, st);
-        launch_walk<T>(t, ds->upw_ptr.p, ds->upw_prog.p, ds->upw_nroots, ds->upw_nlv, true, data, box_stride, cm,
-                       ops, st);
-        k0 = size_t(t->params.depth - ds->upw_lroot);
-      }
-      for (size_t k = k0; k < ds->up.size(); ++k) launch_translate<T>(t, ds->up[k], data, box_stride, cm, ops, st);
-    }
-    if (stop_after_up) return;
-    if (sel) {
-      ProfScope ps(ds, prof, OCCK_K_SELECT, st, 1 + int(ds->down.size()));
-      learned_ranks<T>(t, ds, sel, data, box_stride, cm, st);
-    }
-    {
-      // ds->down holds levels lmin..D; the walk covers those at or below its root level
-      const bool walk = !sel && ds->dnw_nroots > 0;
-      const size_t k1 = walk ? size_t(ds->dnw_lroot - t->lmin) : ds->down.size();
-      ProfScope ps(ds, prof, OCCK_K_DOWN, st, int(k1) + (walk ? 1 : 0));
-      for (size_t k = 0; k < k1; ++k)
-        launch_translate<T>(t, ds->down[k], data, box_stride, cm, ops, st, sel ? ds->down[k].rank.p : nullptr);
-      if (walk) {
-        if (pipe && kb >= 2) HIP_OK(hipStreamWaitEvent(st, ds->ev_l2p[buf], 0));   // batch kb-2 has read it
-        ProfScope ps_w(ds, prof, OCCK_K_DOWN_WALK, st);
-        launch_walk<T>(t, ds->dnw_ptr.p, ds->dnw_prog.p, ds->dnw_nroots, ds->dnw_nlv, false, data, box_stride, cm,
-                       ops, st, lshift);
-      }
-    }
-    if (pipe) {
-      HIP_OK(hipEventRecord(ds->ev_mloc[buf], st));
-      HIP_OK(hipStreamWaitEvent(stl, ds->ev_mloc[buf], 0));
-    }
-    {
-      ProfScope ps(ds, prof, OCCK_K_L2P, stl, sym && jrel + jb < iend ? 2 : 1);
-      GemmRun r{};
-      r.accumulate = (kb > 0 || band) ? 1 : 0;   // with screening KB starts cleared
-      r.nlo = int(istart);
-      r.nhi = band ? int(iend) : 0;
-      r.bptr = lshift * box_stride;              // B: the batch's leaf Mloc
-      ProfScope ps_d(ds, prof, OCCK_K_L2P_DIRECT, stl);
-      if (sym) {   // K segments q, k = j over the batch's own j, A out of HT
-        r.akoff = int32_t(jrel);
-        r.klim = jbk;
-      }
-      if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
-        r.tile0 = ds->l2pw_nt_start[size_t(ct0 / 4)];
-        r.ntiles = ds->l2pw_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-        if (sym)
-          hipLaunchKernelGGL((l2p_ht_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
-        else
-          hipLaunchKernelGGL((l2p_wide_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2p.p, ds->t_l2pw.p, Cg, ldcg, r);
-      } else {
-        r.tile0 = ds->l2p_nt_start[size_t(ct0 / 4)];
-        r.ntiles = ds->l2p_nt_start[size_t(ct0 / 4) + 1] - r.tile0;
-        if (sym)
-          hipLaunchKernelGGL((l2p_ht_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
-        else
-          hipLaunchKernelGGL((l2p_kernel<MODE>), dim3(gemm_grid(r.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2p.p, ds->t_l2p.p, Cg, ldcg, r);
-      }
-      ps_d.close();
-      if (sym && jrel + jb < iend) {
-        ProfScope ps_m(ds, prof, OCCK_K_L2P_MIRROR, stl);
-        GemmRun m{};
-        m.accumulate = 1;
-        m.klim = band ? int(iend) : 0;
-        m.koff = jrel + jb;
-        m.aptr = lshift * box_stride;            // A: the batch's leaf Mloc
-        m.coff = jrel;
-        m.mlim = jbk;
-        if (MODE <= kModeF32 && ds->n_l2ptw > 0) {   // the split-BF16 modes would need 256+ VGPRs
-          m.ntiles = ds->n_l2ptw;
-          hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2pt.p, ds->t_l2ptw.p, Cg, ldcg, m);
-        } else {
-          m.ntiles = ds->n_l2pt;
-          hipLaunchKernelGGL((l2pt_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, stl,
-                             ds->d_l2pt.p, ds->t_l2pt.p, Cg, ldcg, m);
-        }
-      }
-    }
-    if (pipe) HIP_OK(hipEventRecord(ds->ev_l2p[buf], stl));
+    HIP_OK(hipStreamWaitEvent(stg, ds->ev_mloc[p], 0));
+    l2p(kb, b, stg);
+    HIP_OK(hipEventRecord(ds->ev_l2p[p], stg));
     HIP_OK(hipGetLastError());
   }
-  if (pipe) {   // the caller's stream resumes after the last L2P
-    HIP_OK(hipEventRecord(ds->ev_join, stl));
-    HIP_OK(hipStreamWaitEvent(st, ds->ev_join, 0));
-  }
+  HIP_OK(hipEventRecord(ds->ev_join, stg));   // the caller's stream resumes after the last L2P
+  HIP_OK(hipStreamWaitEvent(st, ds->ev_join, 0));
 }
 
 // half transform, Omega and the upward passes of one FP64 j batch [j0, j1)
@@ -1111,7 +1177,7 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       }
       for (int lev = t->lmin; lev <= t->params.depth; ++lev) nbox += int64_t(t->boxes[lev].size());
       const size_t need = size_t(sum_nb2) * size_t(t->Q) * 8 +
-                          workspace_need(sum_nb, t->Q, nbox, jb, ni, es, sym, sym ? t->nleaf() : 0);
+                          workspace_need(sum_nb, t->Q, nbox, jb, ni, es, sym, sym ? 2 * t->nleaf() : 0);
       if (need > device_cap()) throw std::bad_alloc();
     }
     if (!t->dev) upload_tree(t);
@@ -1132,6 +1198,7 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       ds->Cf.alloc(size_t(nbasis) * nocc);
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
+    const bool two = opts->one_stream == 0;   // the L2P may overlap the next batch on a second stream
     std::vector<int> band;
     const std::vector<int>* bp = nullptr;
     if (opts->pair_thresh > 0.0) {   // occupied-pair screening (checked: symmetric ranges)
@@ -1147,13 +1214,13 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       ds->band_jb = jb;
     }
     if (prec == OCCK_PREC_FP64)
-      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
     else if (prec == OCCK_PREC_FP32)
-      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
     else if (prec == OCCK_PREC_BF16X3)
-      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
     else
-      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp);
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,

@@ -996,11 +996,13 @@ struct WalkStep {   // one step of an upward or downward walk program
 enum { UP_LEAF = 0, UP_CLOSE = 1 };
 constexpr int kUpWalkLevels = 6;   // accumulator levels (below the walk's root level) held in registers
 
+// load_shift: box rows added to every leaf read (a second leaf Omega region,
+// so that the next j batch's Omega can be formed while this walk runs).
 template <class T, int Q, int NLV, int SYM>
 __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                       const int32_t* __restrict__ prog_ptr,
                                                       const WalkStep* __restrict__ prog, const T* __restrict__ ops,
-                                                      int nroots, int64_t nblocks) {
+                                                      int nroots, int64_t nblocks, int64_t load_shift) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
@@ -1036,7 +1038,7 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
   };
   T xn[Q];
   auto fetch = [&](int s) {   // column values of the leaf of step s (s < p1)
-    const gbl<const T>* X = base + int64_t(pg[s].box) * box_stride;
+    const gbl<const T>* X = base + (int64_t(pg[s].box) + load_shift) * box_stride;
     for (int k = 0; k < Q; ++k) xn[k] = X[int64_t(k) * ncol + col];
   };
   int nl = next_leaf(p0);
@@ -1079,14 +1081,15 @@ __global__ __launch_bounds__(256) void up_walk_kernel(T* __restrict__ data, int6
 enum { DN_BEGIN = 0, DN_SRC = 1, DN_STORE = 2 };
 constexpr int kDownWalkLevels = 2;   // accumulator levels (root level..D) held in registers
 
-// store_shift: box slots added to every stored leaf (a second leaf Mloc
-// region, so that the next j batch's walk can run while the L2P of this one
-// still reads the first).
+// store_shift: box rows added to every stored leaf; src_shift: box rows
+// added to every source in [src_lo, src_hi) (second leaf Mloc and leaf
+// Omega regions, so that two j batches can be in flight).
 template <class T, int Q, int NLV, int SYM>
 __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm, int KS,
                                                         const int32_t* __restrict__ prog_ptr,
                                                         const WalkStep* __restrict__ prog, const T* __restrict__ ops,
-                                                        int nroots, int64_t nblocks, int64_t store_shift) {
+                                                        int nroots, int64_t nblocks, int64_t store_shift,
+                                                        int64_t src_shift, int32_t src_lo, int32_t src_hi) {
   const int64_t per = (int64_t(gridDim.x) + 7) / 8;
   const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (logical >= nblocks) return;
@@ -1121,7 +1124,8 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
   };
   T xn[Q];
   auto fetch = [&](int s) {   // column values of the source of step s (s < p1)
-    const gbl<const T>* X = base + int64_t(pg[s].box) * box_stride;
+    const int32_t box = pg[s].box;
+    const gbl<const T>* X = base + (int64_t(box) + (box >= src_lo && box < src_hi ? src_shift : 0)) * box_stride;
     for (int k = 0; k < Q; ++k) xn[k] = X[int64_t(k) * ncol + col];
   };
   int ns = next_src(p0);

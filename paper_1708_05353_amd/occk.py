@@ -57,7 +57,8 @@ class _JFlops(ct.Structure):
 
 class _Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
-                ("jblock", ct.c_int32), ("accumulate", ct.c_int32), ("pair_thresh", ct.c_double)]
+                ("jblock", ct.c_int32), ("accumulate", ct.c_int32), ("pair_thresh", ct.c_double),
+                ("one_stream", ct.c_int32)]
 
 
 EXPORTS = {
@@ -299,7 +300,8 @@ class Tree:
 
 
 def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,
-          jblock: int = 0, accumulate: bool = False, stream=None, selector=None, pair_thresh: float = 0.0):
+          jblock: int = 0, accumulate: bool = False, stream=None, selector=None, pair_thresh: float = 0.0,
+          one_stream: bool = False):
     """K[:, i0:i1] (+)= 2 sum_{j in [j0,j1)} (rj|ji)_ff on the GPU.
 
     C: torch.float64 CUDA tensor (nbasis, ldc) row-major; K: torch.float64 CUDA
@@ -316,7 +318,7 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
         stream = torch.cuda.current_stream(C.device)
     opts = _Opts(int(precision), RANK_FIXED if selector is None else RANK_LEARNED,
                  None if selector is None else selector.handle.value, int(jblock), int(bool(accumulate)),
-                 float(pair_thresh))
+                 float(pair_thresh), int(bool(one_stream)))
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))
