@@ -678,9 +678,10 @@ def _classify_last_call(names, info):
             kind[i] = "half" if seen_half else "ht"
             seen_half = True
             continue
-        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("omega_kernel", "omega"),
+        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("omega_kernel", "omega"), ("omega_ht_kernel", "omega"),
                        ("l2pt_kernel", "l2p_mirror"), ("l2pt_wide_kernel", "l2p_mirror"),
-                       ("l2p_kernel", "l2p_direct"), ("l2p_wide_kernel", "l2p_direct")):
+                       ("l2p_kernel", "l2p_direct"), ("l2p_wide_kernel", "l2p_direct"),
+                       ("l2p_ht_kernel", "l2p_direct"), ("l2p_ht_wide_kernel", "l2p_direct")):
             if key in k:
                 kind[i] = c
                 break
@@ -779,6 +780,57 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
                                         "per_launch_bytes": {k: round(v) for k, v in per_launch.items()}}) + " -->")
 
 
+SQ_COUNTERS = ["SQ_WAVE_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
+               "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
+               "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VALU", "SQ_INSTS_SALU"]
+
+
+def sq_summary(dirs, cmds):
+    """Per-kernel MFMA, wait-state and LDS counters of the last occk_far_K
+    call recorded by rocprofv3 --pmc runs of 'bench.py --steps 1 --warmup 0
+    --one-stream' (summed over the call's dispatches of each kernel class);
+    prints markdown."""
+    import workloads
+    from paper_1708_05353_amd import occk
+    per = {}
+    names = {}
+    for d in dirs:
+        for c in SQ_COUNTERS:
+            rows = _pmc_rows(d, c)
+            for i, (k, v) in rows.items():
+                names[i] = k
+                per.setdefault(c, {})[i] = v
+    wl = workloads.alkane_chain()
+    tr = occk.Tree(wl.system, wl.params)
+    kind = _classify_last_call(names, tr.info)
+    tot = {}
+    for i, cls in kind.items():
+        t = tot.setdefault(cls, {c: 0.0 for c in SQ_COUNTERS})
+        for c in SQ_COUNTERS:
+            t[c] += per.get(c, {}).get(i, 0.0)
+    print("# MFMA, wait-state and LDS counters per kernel: alkane chain, L = 2, FP64 (one occk_far_K call, one stream)\n")
+    print("Commands (repository root, one MI355X, `export TMPDIR=/tmp`; two passes of at most 8 SQ counters):\n\n```")
+    for c in cmds:
+        print(c)
+    print("```\n")
+    print("Sums over the last call's dispatches of each kernel.  MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / "
+          "(4 SQ_BUSY_CU_CYCLES) (the MFMA counter summed over the 4 SIMDs of a CU); waits are fractions of "
+          "SQ_WAVE_CYCLES; LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.\n")
+    print("| kernel | MFMA busy | wait on dependencies (WAIT_INST_ANY) | wait any | LDS wait | LDS conflict | "
+          "VALU instr | SALU instr | VMEM reads | LDS instr | F64 MFMA ops |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
+    for cls in KERNELS:
+        if cls not in tot:
+            continue
+        t = tot[cls]
+        wc = max(t["SQ_WAVE_CYCLES"], 1.0)
+        busy = t["SQ_VALU_MFMA_BUSY_CYCLES"] / max(4 * t["SQ_BUSY_CU_CYCLES"], 1.0)
+        conf = t["SQ_LDS_BANK_CONFLICT"] / max(t["SQ_LDS_IDX_ACTIVE"], 1.0)
+        print(f"| {cls} | {busy:.2f} | {t['SQ_WAIT_INST_ANY'] / wc:.2f} | {t['SQ_WAIT_ANY'] / wc:.2f} | "
+              f"{t['SQ_WAIT_INST_LDS'] / wc:.3f} | {conf:.3f} | {t['SQ_INSTS_VALU']:.3g} | {t['SQ_INSTS_SALU']:.3g} | "
+              f"{t['SQ_INSTS_VMEM_RD']:.3g} | {t['SQ_INSTS_LDS']:.3g} | {t['SQ_INSTS_VALU_MFMA_MOPS_F64']:.3g} |")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="alkane", choices=["alkane", "batch16", "protein-learned", "graphene-sweep"])
@@ -787,6 +839,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="summarise rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs (CPU only)")
     ap.add_argument("--pmc-copy-mib", type=int, default=1024)
+    ap.add_argument("--sq-summary", nargs="+", metavar="PMC_DIR",
+                    help="summarise rocprofv3 --pmc SQ counter runs (CPU only)")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
                     help="print per-class launch times of a rocprofv3 --kernel-trace run of this bench (--no-mixed)")
     ap.add_argument("--pmc-commands", nargs="*", default=[])
@@ -818,6 +872,9 @@ def main():
         return
     if args.trace_summary:
         trace_summary(args.trace_summary)
+        return
+    if args.sq_summary:
+        sq_summary(args.sq_summary, args.pmc_commands)
         return
     if args.workload == "batch16":
         bench_batch(args)
