@@ -48,30 +48,62 @@ struct NTask {
 };
 
 // ---------------------------------------------------------------------------
-// Boys function F_n(T), n = 0..N: for T < 12 the series
-// F_N(T) = e^-T sum_k (2T)^k / ((2N+1)(2N+3)...(2N+2k+1)), then the downward
-// recurrence F_n = (2T F_{n+1} + e^-T)/(2n+1); for larger T,
-// F_0 = (1/2) sqrt(pi/T) erf(sqrt(T)) and the upward recurrence
-// F_{n+1} = ((2n+1) F_n - e^-T)/(2T), which loses nothing there.
+// Boys function F_n(T) = int_0^1 t^(2n) exp(-T t^2) dt, n = 0..N.
+// T < kBoysTmax: F_N by its Taylor series about the nearest point T_g of a
+// grid of step kBoysStep, F_N(T) = sum_k F_(N+k)(T_g) (T_g - T)^k / k!
+// (dF_n/dT = -F_(n+1); |T_g - T| <= 0.05 and kBoysTerms terms leave a
+// remainder below 1e-17 relative), from a table of F_m(T_g) formed once on
+// the host; then the downward recurrence F_n = (2T F_(n+1) + e^-T)/(2n+1),
+// which is stable.  T >= kBoysTmax: F_0 = (1/2) sqrt(pi/T) erf(sqrt(T)) and
+// the upward recurrence F_(n+1) = ((2n+1) F_n - e^-T)/(2T), which loses
+// nothing there.
+constexpr int kBoysNmax = 4;                       // (pp|pp) needs F_0..F_4
+constexpr int kBoysTerms = 9;                      // Taylor terms k = 0..8
+constexpr int kBoysM = kBoysNmax + kBoysTerms;     // table columns m = 0..12
+constexpr double kBoysTmax = 12.0, kBoysStep = 0.1;
+constexpr int kBoysRows = 121;                     // T_g = 0, 0.1, ..., 12.0
+__host__ __device__ constexpr double inv_int(int k) { return 1.0 / double(k); }
+
 template <int N>
-__device__ inline void boys(double T, double (&F)[N + 1]) {
+__device__ inline void boys(double T, double (&F)[N + 1], const double* __restrict__ tab) {
+  static_assert(N <= kBoysNmax, "table columns");
   const double e = exp(-T);
-  if (T < 12.0) {
-    double term = 1.0 / (2 * N + 1), sum = term;
-    for (int k = 1; k < 120; ++k) {
-      term *= 2.0 * T / double(2 * N + 2 * k + 1);
-      sum += term;
-      if (term < 1e-17 * sum) break;
-    }
-    F[N] = e * sum;
+  if (T < kBoysTmax) {
+    const int g = int(T * (1.0 / kBoysStep) + 0.5);   // nearest grid point, 0..120
+    const double d = double(g) * kBoysStep - T;       // T_g - T
+    const double* row = tab + int64_t(g) * kBoysM + N;
+    double s = row[kBoysTerms - 1];
 #pragma unroll
-    for (int n = N - 1; n >= 0; --n) F[n] = (2.0 * T * F[n + 1] + e) / double(2 * n + 1);
+    for (int k = kBoysTerms - 2; k >= 0; --k) s = fma(s, d * inv_int(k + 1), row[k]);
+    F[N] = s;
+#pragma unroll
+    for (int n = N - 1; n >= 0; --n) F[n] = fma(2.0 * T, F[n + 1], e) * inv_int(2 * n + 1);
   } else {
     const double st = sqrt(T);
     F[0] = 0.886226925452758014 * erf(st) / st;   // sqrt(pi)/2
+    const double h = 0.5 / T;
 #pragma unroll
-    for (int n = 0; n < N; ++n) F[n + 1] = (double(2 * n + 1) * F[n] - e) / (2.0 * T);
+    for (int n = 0; n < N; ++n) F[n + 1] = (double(2 * n + 1) * F[n] - e) * h;
   }
+}
+
+// Host table of the Boys function for boys(): F_m(T_g), g < kBoysRows,
+// m < kBoysM, by the series F_m(T) = e^-T sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1))
+// in long double (all terms positive).
+static std::vector<double> boys_table() {
+  std::vector<double> tab(size_t(kBoysRows) * kBoysM);
+  for (int g = 0; g < kBoysRows; ++g) {
+    const long double T = (long double)g * (long double)kBoysStep;
+    for (int m = 0; m < kBoysM; ++m) {
+      long double term = 1.0L / (2 * m + 1), sum = term;
+      for (int k = 1; k < 400 && term > 1e-24L * sum; ++k) {
+        term *= 2.0L * T / (long double)(2 * m + 2 * k + 1);
+        sum += term;
+      }
+      tab[size_t(g) * kBoysM + m] = double(expl(-T) * sum);
+    }
+  }
+  return tab;
 }
 
 // Hermite coefficients of one Cartesian direction for powers i, j <= 1:
@@ -93,9 +125,9 @@ struct RTable {
 };
 
 template <int L>
-__device__ inline void hermite_r(double alpha, const double (&rpq)[3], RTable<L>& out) {
+__device__ inline void hermite_r(double alpha, const double (&rpq)[3], RTable<L>& out, const double* __restrict__ btab) {
   double F[L + 1];
-  boys<L>(alpha * (rpq[0] * rpq[0] + rpq[1] * rpq[1] + rpq[2] * rpq[2]), F);
+  boys<L>(alpha * (rpq[0] * rpq[0] + rpq[1] * rpq[1] + rpq[2] * rpq[2]), F, btab);
   // R^n_{tuv} for n from L down to 0; level n needs t + u + v <= L - n
   double Rn[L + 1][L + 1][L + 1][L + 1];
   double m2a = 1.0;
@@ -142,10 +174,11 @@ __host__ __device__ constexpr int pw(int l, int k, int d) { return l == 0 ? 0 : 
 // Hermite coefficients Eb (per direction) and the ket's Ek given.
 template <int LA, int LB, int LC, int LD>
 __device__ inline void quartet(const double (&Eb)[3][2][2][3], const double (&Ek)[3][2][2][3], const double (&rpq)[3],
-                               double alpha, double scale, const double (&D2)[3][3], double (&X)[3][3]) {
+                               double alpha, double scale, const double (&D2)[3][3], double (&X)[3][3],
+                               const double* __restrict__ btab) {
   constexpr int L = LA + LB + LC + LD;
   RTable<L> R;
-  hermite_r<L>(alpha, rpq, R);
+  hermite_r<L>(alpha, rpq, R, btab);
 #pragma unroll
   for (int r = 0; r < 2 * LA + 1; ++r)
 #pragma unroll
@@ -185,7 +218,7 @@ __device__ inline void quartet(const double (&Eb)[3][2][2][3], const double (&Ek
 
 template <int LA, int LB, int LC, int LD>
 __device__ inline void ket_step(const SPair& br, const double (&Eb)[3][2][2][3], const SPair& kt, const double* Dm,
-                                int64_t n, double (&X)[3][3]) {
+                                int64_t n, double (&X)[3][3], const double* __restrict__ btab) {
   double Ek[3][2][2][3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) hermite_e(kt.P[d] - kt.A[d], kt.P[d] - kt.B[d], kt.p, Ek[d]);
@@ -199,7 +232,7 @@ __device__ inline void ket_step(const SPair& br, const double (&Eb)[3][2][2][3],
   for (int s = 0; s < 2 * LB + 1; ++s)
 #pragma unroll
     for (int t = 0; t < 2 * LC + 1; ++t) D2[s][t] = Dm[int64_t(br.fb + s) * n + kt.fa + t];
-  quartet<LA, LB, LC, LD>(Eb, Ek, rpq, alpha, scale, D2, X);
+  quartet<LA, LB, LC, LD>(Eb, Ek, rpq, alpha, scale, D2, X, btab);
 }
 
 // One wave per task.  Lane i takes bra pair bra0 + i (of class LA, LB); the
@@ -209,7 +242,7 @@ __global__ __launch_bounds__(64) void nf_quartet_kernel(const NTask* __restrict_
                                                         const SPair* __restrict__ bra,
                                                         const SPair* __restrict__ ket,
                                                         const double* __restrict__ Dm, int64_t n,
-                                                        double* __restrict__ Xm) {
+                                                        double* __restrict__ Xm, const double* __restrict__ btab) {
   const NTask tk = tasks[blockIdx.x];
   const int lane = threadIdx.x;
   const bool ok = lane < tk.nbra;
@@ -227,11 +260,11 @@ __global__ __launch_bounds__(64) void nf_quartet_kernel(const NTask* __restrict_
     const SPair kt = ket[tk.ket0 + e];
     const int lc = kt.la;
     if (ld == 0) {
-      if (lc == 0) ket_step<LA, LB, 0, 0>(br, Eb, kt, Dm, n, X);
-      else ket_step<LA, LB, 1, 0>(br, Eb, kt, Dm, n, X);
+      if (lc == 0) ket_step<LA, LB, 0, 0>(br, Eb, kt, Dm, n, X, btab);
+      else ket_step<LA, LB, 1, 0>(br, Eb, kt, Dm, n, X, btab);
     } else {
-      if (lc == 0) ket_step<LA, LB, 0, 1>(br, Eb, kt, Dm, n, X);
-      else ket_step<LA, LB, 1, 1>(br, Eb, kt, Dm, n, X);
+      if (lc == 0) ket_step<LA, LB, 0, 1>(br, Eb, kt, Dm, n, X, btab);
+      else ket_step<LA, LB, 1, 1>(br, Eb, kt, Dm, n, X, btab);
     }
   }
   if (!ok) return;
@@ -277,6 +310,7 @@ struct NState {
   DevBuf<NTask> tasks[4];          // per bra class (la, lb) = (0,0), (0,1), (1,0), (1,1)
   int ntask[4] = {0, 0, 0, 0};
   DevBuf<double> D, X, CT;
+  DevBuf<double> boys;             // Boys function table of boys()
   DevBuf<GemmDesc> gdesc;          // D = C CT, K = X C
   DevBuf<GemmTile> gtiles;
   int ntiles_d = 0, ntiles_k = 0;
@@ -370,6 +404,7 @@ static void nstate_build(Tree* t, int64_t nocc) {
     }
     ns->bra.upload(bra);
     ns->ket.upload(ket);
+    ns->boys.upload(boys_table());
     // tasks: every near (leaf, leaf') pair, bra class, chunk of 64 bra pairs, ket run
     for (int cls = 0; cls < 4; ++cls) {
       std::vector<NTask> tl;
@@ -463,16 +498,16 @@ int32_t near_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, double* K, i
     hipLaunchKernelGGL(nf_zero_kernel, dim3(4096), dim3(256), 0, st, ns->X.p, n * n);
     if (ns->ntask[0])
       hipLaunchKernelGGL((nf_quartet_kernel<0, 0>), dim3(unsigned(ns->ntask[0])), dim3(64), 0, st, ns->tasks[0].p,
-                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p);
+                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p, ns->boys.p);
     if (ns->ntask[1])
       hipLaunchKernelGGL((nf_quartet_kernel<0, 1>), dim3(unsigned(ns->ntask[1])), dim3(64), 0, st, ns->tasks[1].p,
-                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p);
+                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p, ns->boys.p);
     if (ns->ntask[2])
       hipLaunchKernelGGL((nf_quartet_kernel<1, 0>), dim3(unsigned(ns->ntask[2])), dim3(64), 0, st, ns->tasks[2].p,
-                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p);
+                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p, ns->boys.p);
     if (ns->ntask[3])
       hipLaunchKernelGGL((nf_quartet_kernel<1, 1>), dim3(unsigned(ns->ntask[3])), dim3(64), 0, st, ns->tasks[3].p,
-                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p);
+                         ns->bra.p, ns->ket.p, ns->D.p, n, ns->X.p, ns->boys.p);
     GemmRun rk{};
     rk.tile0 = ns->ntiles_d;
     rk.ntiles = ns->ntiles_k;
