@@ -46,7 +46,9 @@ enum {
  *   FP64    every contraction on FP64 MFMA
  *   FP32    FP32 operands, FP32 MFMA, FP32 accumulation
  *   BF16X3  half/Omega/L2P as split-BF16 products hi*hi + hi*lo + lo*hi with
- *           FP32 accumulation (~2^-16 per product); translations on FP32 MFMA
+ *           FP32 accumulation (~2^-16 per product); translations on FP32 MFMA.
+ *           Outside the 1e-6 target of the mixed path: its bound is 5e-5
+ *           (normwise errors of 4e-6 to 9e-6 on the test systems)
  *   BF16X6  three-way split, six products (~2^-24 per product); translations
  *           on FP32 MFMA */
 enum { OCCK_PREC_FP64 = 0, OCCK_PREC_FP32 = 1, OCCK_PREC_BF16X3 = 2, OCCK_PREC_BF16X6 = 3 };

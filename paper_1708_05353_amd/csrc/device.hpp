@@ -128,6 +128,12 @@ struct DeviceState {
   DevBuf<double> ops;             // FP64 operators (always generated in FP64)
   DevBuf<float> opsf;             // rounded copy for the mixed paths
   int op_sym = 0;                 // structural zeros of the operators (real_class): 0 none, 1 x axis, 2 xy plane
+  // MFMA translations (Q > 9) of trees with structural zeros: components
+  // grouped by class, the operators generated in that order
+  DevBuf<int32_t> perm;           // [Q] component at each position (empty: none)
+  DevBuf<int8_t> pcls;            // [Q] class of each position, non-decreasing
+  DevBuf<double> ops_perm;        // operators in the permuted order
+  DevBuf<float> opsf_perm;        // rounded copy for the mixed paths
   std::vector<Pass> up, down;     // up[k]: level depth-1-k ; down[k]: level lmin+k
   DevBuf<int32_t> occ_ptr, occ_row;
   int nbox = 0;                    // boxes on levels lmin..depth
@@ -251,7 +257,7 @@ void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int
                      hipStream_t st);
 template <class T>
 void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, const ColMap& cm, const T* ops,
-                      hipStream_t st, const int8_t* src_rank = nullptr);
+                      hipStream_t st, const int8_t* src_rank = nullptr, const T* ops_perm = nullptr);
 template <class T>
 void learned_ranks(Tree* t, DeviceState* ds, const void* sel, const T* data, int64_t box_stride, const ColMap& cm,
                    hipStream_t st);

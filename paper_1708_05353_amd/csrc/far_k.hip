@@ -102,6 +102,18 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     xyplane = xyplane && o.d[2] == 0.0;
   }
   ds->op_sym = xaxis ? 1 : xyplane ? 2 : 0;
+  if (ds->op_sym != 0 && Q > 9) {   // MFMA translations: components grouped by class (stable in q)
+    std::vector<int32_t> perm(static_cast<size_t>(Q));
+    for (int q = 0; q < Q; ++q) perm[size_t(q)] = q;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+      return real_class(a, ds->op_sym) < real_class(b, ds->op_sym);
+    });
+    std::vector<int8_t> cls(static_cast<size_t>(Q));
+    for (int k = 0; k < Q; ++k) cls[size_t(k)] = int8_t(real_class(perm[size_t(k)], ds->op_sym));
+    ds->perm.upload(perm);
+    ds->pcls.upload(cls);
+    ds->ops_perm.alloc(op.size() * size_t(opsize_of(Q)));
+  }
   ds->ops.alloc(op.size() * size_t(opsize_of(Q)));
   // box slots on levels lmin..D
   const int lmin = t->lmin;
@@ -553,9 +565,11 @@ void setup_workspace(Tree* t, int jb, int ni, int prec, int sym_mode, ScratchAre
   ds->ws_sym = sym_mode;
 }
 
+// ops_perm (may be null; not with src_rank): the operators in class order,
+// for the MFMA translations of trees with structural zeros.
 template <class T>
 void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride, const ColMap& cm, const T* ops,
-                      hipStream_t st, const int8_t* src_rank) {
+                      hipStream_t st, const int8_t* src_rank, const T* ops_perm) {
   const int Q = t->Q, KS = ksteps_of(Q);
   if (cm.nvalid <= 0 || ps.ntgt == 0) return;
   if (Q <= 9 && !src_rank) {   // vector ALU, FP64 operators and accumulators in every mode
@@ -589,9 +603,18 @@ void launch_translate(const Tree* t, const Pass& ps, T* data, int64_t box_stride
   const int64_t nblocks = nct * ps.ntgt;
   const int64_t grid = ((nblocks + 7) / 8) * 8;
   if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");
-#define OCCK_TR(MT)                                                                                           \
-  hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, cm, \
-                     Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks, src_rank)
+  const bool permuted = ops_perm && !src_rank && t->dev->perm.p;
+  const T* opsm = permuted ? ops_perm : ops;
+  const int32_t* perm = permuted ? t->dev->perm.p : nullptr;
+  const int8_t* pcls = permuted ? t->dev->pcls.p : nullptr;
+#define OCCK_TR(MT)                                                                                            \
+  if (permuted)                                                                                                \
+    hipLaunchKernelGGL((translate_perm_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, \
+                       cm, Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, opsm, ps.ntgt, nblocks, \
+                       perm, pcls);                                                                            \
+  else                                                                                                         \
+    hipLaunchKernelGGL((translate_kernel<T, MT>), dim3(unsigned(grid)), dim3(256), 0, st, data, box_stride, cm, \
+                       Q, KS, ps.tgt_box.p, ps.src_ptr.p, ps.src_box.p, ps.src_op.p, ops, ps.ntgt, nblocks, src_rank)
   switch (mtiles_of(Q)) {
     case 1: OCCK_TR(1); break;
     case 2: OCCK_TR(2); break;
@@ -658,9 +681,9 @@ void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int n
 }
 
 template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, const ColMap&, const double*,
-                                       hipStream_t, const int8_t*);
+                                       hipStream_t, const int8_t*, const double*);
 template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, const ColMap&, const float*,
-                                      hipStream_t, const int8_t*);
+                                      hipStream_t, const int8_t*, const float*);
 
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st) {
@@ -699,6 +722,10 @@ static void free_state(DeviceState* ds) {
   ds->funcs.free();
   ds->opparam.free();
   ds->ops.free();
+  ds->perm.free();
+  ds->pcls.free();
+  ds->ops_perm.free();
+  ds->opsf_perm.free();
   for (auto& p : ds->up) { p.tgt_box.free(); p.src_ptr.free(); p.src_box.free(); p.src_op.free(); }
   for (auto& p : ds->down) {
     p.tgt_box.free(); p.src_ptr.free(); p.src_box.free(); p.src_op.free(); p.rank.free(); p.ent_tgt.free();
@@ -922,6 +949,11 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
   const int64_t box_stride = int64_t(Q) * ncol;
   T* data = reinterpret_cast<T*>(ds->data.p);
   const T* ops = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops.p) : reinterpret_cast<const T*>(ds->opsf.p);
+  // the MFMA translations of trees with structural zeros (fixed ranks) use the class-ordered operators
+  const T* ops_perm = nullptr;
+  if (ds->perm.p && !sel)
+    ops_perm = MODE == kModeF64 ? reinterpret_cast<const T*>(ds->ops_perm.p)
+                                : reinterpret_cast<const T*>(ds->opsf_perm.p);
   const int nj = j1 - j0;
   const int nblk = (nj + jb - 1) / jb;
   const bool pipe = two_streams && sym && !sel && !stop_after_up && ds->ws_pipe && ds->dnw_nroots > 0 &&
@@ -1010,7 +1042,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
                      ops, s, 0, b.odd ? omega_shift : 0, 0, 0);
       k0 = size_t(t->params.depth - ds->upw_lroot);
     }
-    for (size_t k = k0; k < ds->up.size(); ++k) launch_translate<T>(t, ds->up[k], data, box_stride, b.cm, ops, s);
+    for (size_t k = k0; k < ds->up.size(); ++k)
+      launch_translate<T>(t, ds->up[k], data, box_stride, b.cm, ops, s, nullptr, ops_perm);
   };
 
   // learned ranks and downward passes on stream s; wait_before_walk is
@@ -1025,7 +1058,8 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     const size_t k1 = walk ? size_t(ds->dnw_lroot - t->lmin) : ds->down.size();
     ProfScope ps(ds, prof, OCCK_K_DOWN, s, int(k1) + (walk ? 1 : 0));
     for (size_t k = 0; k < k1; ++k)
-      launch_translate<T>(t, ds->down[k], data, box_stride, b.cm, ops, s, sel ? ds->down[k].rank.p : nullptr);
+      launch_translate<T>(t, ds->down[k], data, box_stride, b.cm, ops, s, sel ? ds->down[k].rank.p : nullptr,
+                          ops_perm);
     if (walk) {
       wait_before_walk();
       ProfScope ps_w(ds, prof, OCCK_K_DOWN_WALK, s);
@@ -1144,6 +1178,9 @@ void run_upward_fp64(Tree* t, DeviceState* ds, const double* C, int64_t ldc, int
                      hipStream_t st) {
   hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p, t->L,
                      t->Q);
+  if (ds->perm.p)
+    hipLaunchKernelGGL(opgen_perm_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p,
+                       ds->ops_perm.p, t->L, t->Q, ds->perm.p);
   HIP_OK(hipGetLastError());
   run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, j1 - j0, i1 - i0, false, st, nullptr, true);
 }
@@ -1190,11 +1227,18 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       ProfScope ps(ds, prof, OCCK_K_OPGEN, st);
       hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p,
                          t->L, Q);
+      if (ds->perm.p && !sel)   // the MFMA translations' operators in class order
+        hipLaunchKernelGGL(opgen_perm_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p,
+                           ds->ops_perm.p, t->L, Q, ds->perm.p);
       HIP_OK(hipGetLastError());
     }
     if (mixed) {
       ProfScope ps(ds, prof, OCCK_K_CONVERT, st, 2);
       launch_to_float(ds->ops.p, 0, ds->opsf.p, 0, 1, int64_t(ds->ops.n), st);
+      if (ds->perm.p && !sel) {
+        ds->opsf_perm.alloc(ds->ops_perm.n);
+        launch_to_float(ds->ops_perm.p, 0, ds->opsf_perm.p, 0, 1, int64_t(ds->ops_perm.n), st);
+      }
       ds->Cf.alloc(size_t(nbasis) * nocc);
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
@@ -1344,6 +1388,9 @@ int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32
     }
     hipLaunchKernelGGL(opgen_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p, ds->ops.p,
                        t->L, t->Q);
+    if (ds->perm.p)
+      hipLaunchKernelGGL(opgen_perm_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p,
+                         ds->ops_perm.p, t->L, t->Q, ds->perm.p);
     HIP_OK(hipGetLastError());
     run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, false, st, nullptr, false, sym);
     hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,

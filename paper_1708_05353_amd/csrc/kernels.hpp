@@ -222,8 +222,10 @@ __device__ inline double l2p_weight(int q) {
 // Generates one operator with nthreads threads (thread index tid); tab is a
 // shared table of at least (2L+1)(2L+2)/2 entries.  The FP64 result is also
 // written rounded to FP32 when outf is non-null.
+// perm (may be null): entry (row, col) of the generated matrix is
+// T[perm[row]][perm[col]] (the components in the order perm lists them).
 static __device__ void opgen_one(const OpParam& p, double* out, float* outf, int L, int Q, Cplx* tab, int tid,
-                          int nthreads) {
+                          int nthreads, const int32_t* perm = nullptr) {
   if (tid == 0) {
     if (p.type == kOpM2L) irregular_table(2 * L, p.d, tab);
     else regular_table(L, p.d, tab);
@@ -237,8 +239,9 @@ static __device__ void opgen_one(const OpParam& p, double* out, float* outf, int
     const int row = mt * 16 + (lane & 15), col = ks * 4 + (lane >> 4);
     double v = 0.0;
     if (row < Q && col < Q) {
-      v = real_entry(p.type, tab, row, col);
-      if (p.weighted) v *= l2p_weight(row);
+      const int r = perm ? perm[row] : row, c = perm ? perm[col] : col;
+      v = real_entry(p.type, tab, r, c);
+      if (p.weighted) v *= l2p_weight(r);
     }
     if (out) as_global(out)[e] = v;
     if (outf) as_global(outf)[e] = float(v);
@@ -251,6 +254,17 @@ static __global__ __launch_bounds__(64) void opgen_kernel(const OpParam* __restr
   __shared__ Cplx tab[(2 * kMaxL + 1) * (2 * kMaxL + 2) / 2];
   const int64_t sz = int64_t(mtiles_of(Q)) * ksteps_of(Q) * 64;
   opgen_one(params[blockIdx.x], ops + int64_t(blockIdx.x) * sz, nullptr, L, Q, tab, threadIdx.x, 64);
+}
+
+// The same operators with their components reordered by perm (the MFMA
+// translations of axis-aligned trees, whose structural zeros then form
+// whole blocks).
+static __global__ __launch_bounds__(64) void opgen_perm_kernel(const OpParam* __restrict__ params,
+                                                        double* __restrict__ ops, int L, int Q,
+                                                        const int32_t* __restrict__ perm) {
+  __shared__ Cplx tab[(2 * kMaxL + 1) * (2 * kMaxL + 2) / 2];
+  const int64_t sz = int64_t(mtiles_of(Q)) * ksteps_of(Q) * 64;
+  opgen_one(params[blockIdx.x], ops + int64_t(blockIdx.x) * sz, nullptr, L, Q, tab, threadIdx.x, 64, perm);
 }
 
 // --------------------------------------------------------------------------
@@ -745,12 +759,19 @@ OCCK_GEMM_KERNEL(l2p_ht_wide_kernel, false, false, double, GemmRows144, 2, 1)
 // four waves read their A fragments from LDS (one global read of the
 // operator per block instead of one per wave).  The block then must call
 // this routine with all its threads.
-template <class T, int MT, bool USE_LDS>
+// perm (may be null; not with src_rank): the operators hold the components
+// in the order perm lists them, grouped by reflection class (pcls: class of
+// each position, non-decreasing).  Source rows are read and target rows
+// written at perm[position], and an operator block (16 rows x one k step of
+// 4) whose row and column classes do not meet is a structural zero: its
+// products are skipped.  perm_lds holds perm for the block.
+template <class T, int MT, bool USE_LDS, bool PERM = false>
 __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const ColMap& cm, int Q, int KS,
                                const int32_t* __restrict__ tgt_box, const int32_t* __restrict__ src_ptr,
                                const int32_t* __restrict__ src_box, const int32_t* __restrict__ src_op,
                                const T* __restrict__ ops, int t, int64_t ct, const int8_t* __restrict__ src_rank,
-                               T* __restrict__ op_lds) {
+                               T* __restrict__ op_lds, const int32_t* __restrict__ perm = nullptr,
+                               const int8_t* __restrict__ pcls = nullptr, int32_t* __restrict__ perm_lds = nullptr) {
   using Acc = typename std::conditional<std::is_same<T, double>::value, d4, f4>::type;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t ncol = cm.ncol;
@@ -769,6 +790,33 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
   const cst<int32_t>* sbox = as_const(src_box);
   const cst<int32_t>* sop = as_const(src_op);
   const int e0 = as_const(src_ptr)[t], e1 = as_const(src_ptr)[t + 1];
+  constexpr bool permuted = PERM;
+  if constexpr (PERM) {
+    for (int q = threadIdx.x; q < Q; q += 256) perm_lds[q] = perm[q];
+    __syncthreads();
+  }
+  // block (row tile i, k step ks) holds nonzero entries (classes of its
+  // rows and columns meet): bit i*KS + ks of a block-uniform mask (MT * KS
+  // <= 6 * 24 = 144 bits), formed once per block
+  uint64_t lmask[3] = {~0ull, ~0ull, ~0ull};
+  if constexpr (PERM) {
+    static_assert(MT * 4 * MT <= 192, "live mask size");
+    lmask[0] = lmask[1] = lmask[2] = 0;
+    const cst<int8_t>* c = as_const(pcls);
+    for (int i = 0; i < MT; ++i)
+      for (int ks = 0; ks < KS; ++ks) {
+        const int r0 = i * 16, r1 = min(r0 + 15, Q - 1), k0 = ks * 4, k1 = min(k0 + 3, Q - 1);
+        if (r0 < Q && c[r0] <= c[k1] && c[k0] <= c[r1]) {
+          const int bit = i * KS + ks;
+          lmask[bit >> 6] |= 1ull << (bit & 63);
+        }
+      }
+  }
+  auto live = [&](int i, int ks) {
+    if constexpr (!PERM) return true;
+    const int bit = i * KS + ks;
+    return ((lmask[bit >> 6] >> (bit & 63)) & 1ull) != 0;
+  };
   for (int e = e0; e < e1; ++e) {
     const gbl<const T>* X = as_global(static_cast<const T*>(data)) + int64_t(sbox[e]) * box_stride;
     const gbl<const T>* Tm = as_global(ops) + int64_t(sop[e]) * opsz;
@@ -783,7 +831,7 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
       __syncthreads();   // every wave is done with the previous operator
       for (int idx = threadIdx.x; idx < MT * KS * 64; idx += 256) {
         const int frag = idx >> 6, i = frag / KS, ks = frag - i * KS;
-        if (i < nfi && ks < kse) op_lds[idx] = Tm[idx];
+        if (i < nfi && ks < kse && live(i, ks)) op_lds[idx] = Tm[idx];
       }
       __syncthreads();
     }
@@ -794,7 +842,8 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
     T bn[4];   // raw values of the next k step (masked when used)
     auto loadb = [&](int ks, T (&b)[4]) {
       const int row = ks * 4 + (lane >> 4);
-      const int rc = row < Q ? row : Q - 1;
+      const int rc0 = row < Q ? row : Q - 1;
+      const int rc = permuted ? perm_lds[rc0] : rc0;
       for (int j = 0; j < 4; ++j) b[j] = X[int64_t(rc) * ncol + cols[j]];
     };
     if (kse > 0) loadb(0, bn);
@@ -819,8 +868,8 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
           if (i * 16 + (lane & 15) >= nq || row >= nq) a[i] = T(0);
       }
 #pragma unroll
-      for (int i = 0; i < MT; ++i)   // row tiles beyond the rank are skipped
-        if (i < nfi)
+      for (int i = 0; i < MT; ++i)   // row tiles beyond the rank, and structural-zero blocks, are skipped
+        if (i < nfi && live(i, ks))
           for (int j = 0; j < 4; ++j) acc[i][j] = mfma4(a[i], b[j], acc[i][j]);
     }
   }
@@ -830,7 +879,7 @@ __device__ void translate_tile(T* __restrict__ data, int64_t box_stride, const C
       if (!ok[j]) continue;
       for (int r = 0; r < 4; ++r) {
         const int row = i * 16 + acc_row<Acc>(lane >> 4, r);
-        if (row < Q) store_stream(Y + int64_t(row) * ncol + cols[j], T(acc[i][j][r]));
+        if (row < Q) store_stream(Y + int64_t(permuted ? perm_lds[row] : row) * ncol + cols[j], T(acc[i][j][r]));
       }
     }
 }
@@ -849,6 +898,26 @@ __global__ __launch_bounds__(256) void translate_kernel(T* __restrict__ data, in
   if (logical >= nblocks) return;   // block-uniform
   translate_tile<T, MT, true>(data, box_stride, cm, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
                               int(logical % ntgt), logical / ntgt, src_rank, op_lds);
+}
+
+// The same with the operators in class order (perm, pcls): structural-zero
+// blocks skipped (fixed ranks only).
+template <class T, int MT>
+__global__ __launch_bounds__(256) void translate_perm_kernel(T* __restrict__ data, int64_t box_stride, ColMap cm,
+                                                             int Q, int KS, const int32_t* __restrict__ tgt_box,
+                                                             const int32_t* __restrict__ src_ptr,
+                                                             const int32_t* __restrict__ src_box,
+                                                             const int32_t* __restrict__ src_op,
+                                                             const T* __restrict__ ops, int ntgt, int64_t nblocks,
+                                                             const int32_t* __restrict__ perm,
+                                                             const int8_t* __restrict__ pcls) {
+  __shared__ T op_lds[MT * 4 * MT * 64];   // KS <= 4 MT
+  __shared__ int32_t perm_lds[MT * 16];
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t logical = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (logical >= nblocks) return;   // block-uniform
+  translate_tile<T, MT, true, true>(data, box_stride, cm, Q, KS, tgt_box, src_ptr, src_box, src_op, ops,
+                                    int(logical % ntgt), logical / ntgt, nullptr, op_lds, perm, pcls, perm_lds);
 }
 
 // --------------------------------------------------------------------------
