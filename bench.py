@@ -54,7 +54,7 @@ def walk_roots(info):
     return lr_up, lr_dn
 
 
-def class_costs(info, n, jb, prec):
+def class_costs(info, n, jb, prec, tree=False):
     """Algorithmic flops and bytes per call of each kernel class, for the full
     call (i and j over all n occupied orbitals, symmetric schedule).
 
@@ -64,7 +64,9 @@ def class_costs(info, n, jb, prec):
     compulsory traffic of the schedule as executed: batch k (first j at
     k*jb) carries jb*(n - k*jb) columns; every box it touches is read once
     and written once per batch (the upward walk reads the leaves and writes
-    the other boxes), operands of the GEMMs are read once."""
+    the other boxes), operands of the GEMMs are read once.  tree: the
+    in-LDS tree kernel runs every translation of a batch in the "down" class,
+    reading the leaf multipoles and writing the leaf local expansions once."""
     Q = info.ncomp
     s = ELEM_BYTES[prec]
     nb = info.boxes_per_level
@@ -86,6 +88,8 @@ def class_costs(info, n, jb, prec):
     else:
         down_boxes = sum(2 * nb[l] + (nb[l - 1] if l > lmin else 0) for l in range(lmin, D + 1))
     z = info.m2m_nnz
+    if tree:
+        up_boxes, down_boxes = 0, 2 * nb[D]
     snb, snb2, nleaf = info.sum_nb, info.sum_nb2, info.nleaf
     half_b = (nblk * (snb2 * Q + snb * jb * (1 + Q)) + snb2 * Q + snb * n * (1 + Q)) * s
     omega_b = sum(snb * Q * jb + snb * nk + nleaf * Q * jb * nk for nk in nks) * s
@@ -94,8 +98,9 @@ def class_costs(info, n, jb, prec):
     return {
         "half": (2 * Q * info.npairs * n, half_b),
         "omega": (Q * n * (n + 1) * snb, omega_b),
-        "up": (2 * z * nc * info.n_edges, up_boxes * Q * nc_exec * s),
-        "down": (2 * Q * Q * nc * info.n_il + 2 * z * nc * info.n_edges, down_boxes * Q * nc_exec * s),
+        "up": (0 if tree else 2 * z * nc * info.n_edges, up_boxes * Q * nc_exec * s),
+        "down": (2 * Q * Q * nc * info.n_il + 2 * z * nc * info.n_edges * (2 if tree else 1),
+                 down_boxes * Q * nc_exec * s),
         "l2p": (2 * Q * n * n * snb, l2p_b),
         "reduce": (0, (snb * n + info.nbasis * n) * 8),
     }
@@ -104,8 +109,9 @@ def class_costs(info, n, jb, prec):
 # kernel -> profile class of the library (occk.KERNEL_CLASSES) whose HIP-event
 # time is that kernel's; "half", "up_pass", "down_pass" are a class minus its
 # nested single-kernel class
-KERNELS = ["ht", "half", "omega", "up_walk", "up_pass", "down_walk", "down_pass", "l2p_direct", "l2p_mirror", "reduce"]
-TRANSLATION_KERNELS = ("up_walk", "up_pass", "down_walk", "down_pass")
+KERNELS = ["ht", "half", "omega", "up_walk", "up_pass", "down_walk", "down_pass", "tree", "l2p_direct", "l2p_mirror",
+           "reduce"]
+TRANSLATION_KERNELS = ("up_walk", "up_pass", "down_walk", "down_pass", "tree")
 
 
 def kernel_times(prof):
@@ -114,7 +120,10 @@ def kernel_times(prof):
         return (prof[a][0] - prof[b][0], prof[a][1] - prof[b][1])
     return {"ht": prof["ht"], "half": sub("half", "ht"), "omega": prof["omega"],
             "up_walk": prof["up_walk"], "up_pass": sub("up", "up_walk"),
-            "down_walk": prof["down_walk"], "down_pass": sub("down", "down_walk"),
+            "down_walk": prof["down_walk"],
+            "down_pass": (prof["down"][0] - prof["down_walk"][0] - prof["tree"][0],
+                          prof["down"][1] - prof["down_walk"][1] - prof["tree"][1]),
+            "tree": prof["tree"],
             "l2p_direct": prof["l2p_direct"], "l2p_mirror": prof["l2p_mirror"], "reduce": prof["reduce"]}
 
 
@@ -142,7 +151,7 @@ def translation_live_entries(Q, split_mask):
     return sum(1 for i in range(Q) for k in range(Q) if cls[i] == cls[k])
 
 
-def kernel_costs(info, n, jb, prec):
+def kernel_costs(info, n, jb, prec, tree=False):
     """Algorithmic flops and bytes per call of each kernel of the full
     symmetric call (i and j over all n orbitals).
 
@@ -154,7 +163,10 @@ def kernel_costs(info, n, jb, prec):
     pairs the direct contraction covers (j in the batch, i from the batch's
     first j on) and the mirrored rest.  Bytes: the compulsory traffic of the
     schedule as executed (every box a kernel touches read or written once per
-    batch, GEMM operands once), as in class_costs."""
+    batch, GEMM operands once), as in class_costs.  tree: the in-LDS tree
+    kernel takes every translation (one launch per reflection class), its
+    bytes one read of the leaf multipoles and one write of the leaf local
+    expansions per batch."""
     Q = info.ncomp
     s = ELEM_BYTES[prec]
     nb, il = info.boxes_per_level, info.il_per_level
@@ -179,7 +191,8 @@ def kernel_costs(info, n, jb, prec):
     dn_walk_boxes = ((sum(nb[l] for l in range(lr_dn, D + 1)) + (nb[lr_dn - 1] if lr_dn > lmin else 0) + nb[D])
                      if lr_dn <= D else 0)
     f_half = 2 * Q * info.npairs * n
-    return {
+    f_tree = f_up(lmin + 1, D + 1) + f_m2l(lmin, D + 1) + f_l2l(lmin, D + 1)
+    out = {
         "ht": (f_half, (snb2 * Q + snb * n * (1 + Q)) * s),
         "half": (f_half, nblk * (snb2 * Q + snb * jb * (1 + Q)) * s),
         "omega": (Q * n * (n + 1) * snb, sum(snb * Q * jb + snb * nk + nleaf * Q * jb * nk for nk in nks) * s),
@@ -187,12 +200,18 @@ def kernel_costs(info, n, jb, prec):
         "up_pass": (f_up(lmin + 1, lr_up + 1), up_pass_boxes * Q * nc_exec * s),
         "down_walk": (f_m2l(lr_dn, D + 1) + f_l2l(lr_dn, D + 1), dn_walk_boxes * Q * nc_exec * s),
         "down_pass": (f_m2l(lmin, lr_dn) + f_l2l(lmin, lr_dn), dn_pass_boxes * Q * nc_exec * s),
+        "tree": (0, 0),
         "l2p_direct": (2 * Q * snb * nc_exec, sum(nleaf * Q * jb * nk * s + snb * nk * 8 for nk in nks)),
         "l2p_mirror": (2 * Q * snb * (n * n - nc_exec),
                        sum((nleaf * Q * jb * max(0, nk - jb) + snb * Q * max(0, nk - jb)) * s + 2 * snb * jb * 8
                            for nk in nks)),
         "reduce": (0, (snb * n + info.nbasis * n) * 8),
     }
+    if tree:
+        for k in ("up_walk", "up_pass", "down_walk", "down_pass"):
+            out[k] = (0, 0)
+        out["tree"] = (f_tree, 2 * nb[D] * Q * nc_exec * s)
+    return out
 
 
 def bench_coulomb(wl, Cd, args, stream):
@@ -667,6 +686,9 @@ def _classify_last_call(names, info):
         if i < start:
             continue
         k = names[i]
+        if "tree_lds_kernel" in k:
+            kind[i] = "tree"
+            continue
         if "up_walk" in k or "down_walk" in k:
             kind[i] = "up_walk" if "up_walk" in k else "down_walk"
             continue
@@ -747,7 +769,7 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
         n, fb, wb = tot.get(c, (0, 0.0, 0.0))
         tot[c] = (n + 1, fb + F[i][1] * 1024 * fetch_scale, wb + W.get(i, ("", 0.0))[1] * 1024 * write_scale)
     jb = 256
-    costs = kernel_costs(info, wl.system.nocc, jb, "fp64")
+    costs = kernel_costs(info, wl.system.nocc, jb, "fp64", tree="tree" in tot)
     b_alg = 8 * (info.ncomp * info.npairs + 2 * info.nbasis * wl.system.nocc)
     print("# HBM traffic per kernel: alkane chain, L = 2, FP64 (one occk_far_K call)\n")
     print("Commands (repository root, one MI355X, `export TMPDIR=/tmp`):\n\n```")
@@ -944,7 +966,8 @@ def main():
     print(f"[bench] {ms:.2f} ms/step, {value:.0f} GFLOP/s ({ms_one:.2f} ms/step in one stream)", file=sys.stderr,
           flush=True)
 
-    costs = class_costs(tree.info, nocc, jb, args.precision)
+    lds_tree = prof["tree"][1] > 0
+    costs = class_costs(tree.info, nocc, jb, args.precision, tree=lds_tree)
     breakdown = {}
     for cls, (flops, nbytes) in costs.items():
         t_ms, nl = prof[cls]
@@ -956,7 +979,7 @@ def main():
                           "GB/s": round(nbytes / (per_call_ms * 1e-3) / 1e9, 1)}
     # single kernels: time from the nested HIP-event scopes, algorithmic flops
     # and bytes per kernel, fraction of the MFMA (or vector) and HBM peaks
-    kcost = kernel_costs(tree.info, nocc, jb, args.precision)
+    kcost = kernel_costs(tree.info, nocc, jb, args.precision, tree=lds_tree)
     ktime = kernel_times(prof)
     pk = PEAK_FLOPS[args.precision]
     Q = tree.info.ncomp

@@ -164,6 +164,15 @@ typedef struct occk_far_opts {
                                   order on hip_stream); 1: everything on
                                   hip_stream, one kernel at a time (kernel
                                   timings, profiles) */
+  int32_t lds_tree;            /* 1: on chains (trees split along x whose levels are
+                                  unbroken rows of boxes, Q = 9) run the
+                                  translations of a j batch (Eqs. 17a-c) as one
+                                  kernel per reflection class that holds the
+                                  whole tree of a group of columns in LDS and
+                                  moves only leaf rows through HBM; other trees
+                                  keep the walks and level passes.  0 (default):
+                                  subtree walks and level-by-level passes, which
+                                  are faster on the chains measured */
 } occk_far_opts;
 
 /* Returns OCCK_ABI_VERSION. */
@@ -513,7 +522,8 @@ enum {
   OCCK_K_DOWN_WALK = 11,  /* downward subtree walk, in DOWN                           */
   OCCK_K_L2P_DIRECT = 12, /* direct L2P GEMM, in L2P                                  */
   OCCK_K_L2P_MIRROR = 13, /* mirrored L2P GEMM of the symmetric schedule, in L2P      */
-  OCCK_K_NCLASS = 14
+  OCCK_K_TREE = 14,       /* whole tree of a column group in LDS, in DOWN             */
+  OCCK_K_NCLASS = 15
 };
 
 /* While enabled, every occk_far_K on the handle records a HIP event pair on

@@ -296,6 +296,10 @@ static int32_t check_far_K(const char* fn, Tree* t, const double* C, int64_t ldc
     set_error(f + ": jblock must be >= 0");
     return OCCK_EINVAL;
   }
+  if (o.lds_tree != 0 && o.lds_tree != 1) {
+    set_error(f + ": lds_tree must be 0 or 1");
+    return OCCK_EINVAL;
+  }
   if (o.one_stream != 0 && o.one_stream != 1) {
     set_error(f + ": one_stream must be 0 or 1");
     return OCCK_EINVAL;

@@ -184,6 +184,14 @@ struct DeviceState {
   // tiles with nt >= 4c, stored one after another; list c is
   // [*_nt_start[c], *_nt_start[c + 1]) and list 0 holds every tile
   std::vector<int32_t> omega_nt_start, l2p_nt_start;
+  // the whole tree of a column group in LDS on chains (tree_chain_kernel;
+  // Q = 9, op_sym 1): per-level stencil tables, levels lmin..depth (empty:
+  // the tree is not such a chain)
+  DevBuf<ChainLevel> chain;
+  int chain_nlev = 0;
+  int chain_nbelow = 0;   // boxes on the level above the leaves
+  DevBuf<double> ops_cls;   // operators per reflection class, compact (opclass_kernel)
+  int64_t ops_cls_off[4] = {0, 0, 0, 0};   // first element of each class
   size_t bytes = 0;
   // profiling: (class, start, end) event pairs recorded on the call's stream
   std::vector<hipEvent_t> ev_pool;

@@ -21,6 +21,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <functional>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <tuple>
@@ -53,6 +54,111 @@ void upload_tree(Tree* t) {
     throw;
   }
   t->dev = ds;
+}
+
+// One level of translations on the host: targets, CSR of sources, operators
+// (box slots as in the passes: upward Omega slots, downward Mloc rows).
+struct HostLevel {
+  std::vector<int32_t> tgt, ptr, src, op;
+};
+
+// Stencil tables of tree_chain_kernel when the tree is a chain in its
+// sense: the boxes of every level one unbroken row along x at equal y and z
+// (x = x0 + b for box b); every box above the leaves lists its children
+// present in increasing x, with one operator per child x parity; every box
+// below the first level lists its parent first, with one operator per x
+// parity; and every interaction list is the in-range part of one stencil per
+// level and x parity (the displacements of that parity's lists, in
+// increasing order, one operator each).  Leaves ds->chain_nlev at 0
+// otherwise.
+static void build_chain(const Tree* t, DeviceState* ds, const std::vector<HostLevel>& hup,
+                        const std::vector<HostLevel>& hdn, const std::vector<int32_t>& slot0) {
+  const int lmin = t->lmin, D = t->params.depth;
+  const int32_t nbox = ds->nbox;
+  const int nlev = D - lmin + 1;
+  std::vector<ChainLevel> lv(static_cast<size_t>(nlev));
+  for (int li = 0; li < nlev; ++li) {
+    const int lev = lmin + li;
+    const auto& bx = t->boxes[size_t(lev)];
+    ChainLevel& L = lv[size_t(li)];
+    L = ChainLevel{};
+    const HostLevel& h = hdn[size_t(li)];
+    L.n = int32_t(bx.size());
+    L.slot0 = slot0[size_t(lev)];
+    if (L.n == 0 || int32_t(h.tgt.size()) != L.n) return;
+    L.x0 = bx[0][0];
+    for (int32_t b = 0; b < L.n; ++b)
+      if (bx[size_t(b)][0] != L.x0 + b || bx[size_t(b)][1] != bx[0][1] || bx[size_t(b)][2] != bx[0][2]) return;
+    // the stencil of each x parity: every displacement of that parity's
+    // interaction lists, in increasing order, with its one operator
+    std::map<int32_t, int32_t> sten[2];
+    const int first = li > 0 ? 1 : 0;   // entry 0 is the parent's local expansion below the first level
+    for (int32_t b = 0; b < L.n; ++b) {
+      if (h.tgt[size_t(b)] != nbox + L.slot0 + b) return;
+      const int par = (L.x0 + b) & 1;
+      if (h.ptr[size_t(b) + 1] - h.ptr[size_t(b)] < first) return;
+      for (int32_t e = h.ptr[size_t(b)] + first; e < h.ptr[size_t(b) + 1]; ++e) {
+        const int32_t d = h.src[size_t(e)] - (L.slot0 + b);
+        auto it = sten[par].emplace(d, h.op[size_t(e)]).first;
+        if (it->second != h.op[size_t(e)]) return;
+      }
+    }
+    for (int par = 0; par < 2; ++par) {
+      L.dn_op[par] = -1;
+      if (sten[par].size() > size_t(kChainStencil)) return;
+      L.ne[par] = int32_t(sten[par].size());
+      int e = 0;
+      for (const auto& kv : sten[par]) {
+        L.d[par][e] = kv.first;
+        L.op[par][e] = kv.second;
+        ++e;
+      }
+    }
+    // every box: parent, then the in-range part of its parity's stencil
+    for (int32_t b = 0; b < L.n; ++b) {
+      const int par = (L.x0 + b) & 1;
+      int32_t e = h.ptr[size_t(b)];
+      if (li > 0) {
+        const ChainLevel& P = lv[size_t(li - 1)];
+        const int32_t pb = ((L.x0 + b) >> 1) - P.x0;
+        if (pb < 0 || pb >= P.n || h.src[size_t(e)] != nbox + P.slot0 + pb) return;
+        if (L.dn_op[par] < 0) L.dn_op[par] = h.op[size_t(e)];
+        if (h.op[size_t(e)] != L.dn_op[par]) return;
+        ++e;
+      }
+      for (int k = 0; k < L.ne[par]; ++k) {
+        const int32_t s = b + L.d[par][k];
+        if (s < 0 || s >= L.n) continue;
+        if (e >= h.ptr[size_t(b) + 1] || h.src[size_t(e)] != L.slot0 + s || h.op[size_t(e)] != L.op[par][k]) return;
+        ++e;
+      }
+      if (e != h.ptr[size_t(b) + 1]) return;
+    }
+  }
+  // upward: hup[k] holds level D - 1 - k as targets; children present in increasing x
+  for (int li = 0; li + 1 < nlev; ++li) {
+    const HostLevel& h = hup[size_t(D - 1 - (lmin + li))];
+    ChainLevel& L = lv[size_t(li)];
+    const ChainLevel& Cl = lv[size_t(li + 1)];
+    if (int32_t(h.tgt.size()) != L.n) return;
+    L.up_op[0] = L.up_op[1] = -1;
+    for (int32_t p = 0; p < L.n; ++p) {
+      if (h.tgt[size_t(p)] != L.slot0 + p) return;
+      int32_t e = h.ptr[size_t(p)];
+      for (int k = 0; k < 2; ++k) {
+        const int32_t ci = 2 * (L.x0 + p) + k - Cl.x0;
+        if (ci < 0 || ci >= Cl.n) continue;
+        if (e >= h.ptr[size_t(p) + 1] || h.src[size_t(e)] != Cl.slot0 + ci) return;
+        if (L.up_op[k] < 0) L.up_op[k] = h.op[size_t(e)];
+        if (h.op[size_t(e)] != L.up_op[k]) return;
+        ++e;
+      }
+      if (e != h.ptr[size_t(p) + 1]) return;
+    }
+  }
+  ds->chain.upload(lv);
+  ds->chain_nlev = nlev;
+  ds->chain_nbelow = nlev > 1 ? lv[size_t(nlev - 2)].n : 0;
 }
 
 static void upload_tree_into(Tree* t, DeviceState* ds) {
@@ -126,6 +232,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
   ds->nbox = nbox;
   ds->leaf_box.resize(nl);
   for (int b = 0; b < nl; ++b) ds->leaf_box[b] = slot0[D] + b;
+  std::vector<HostLevel> hup, hdn;   // host copies for the in-LDS tree programs
   // upward passes: targets at lev (parents), sources children at lev+1 (M2M)
   for (int lev = D - 1; lev >= lmin; --lev) {
     const auto& par = t->boxes[lev];
@@ -146,6 +253,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.ntgt = int(par.size());
     ps.nent = int(sb.size());
     ps.host_op = so;
+    hup.push_back({tb, sp, sb, so});
     ps.tgt_box.upload(tb);
     ps.src_ptr.upload(sp);
     ps.src_box.upload(sb);
@@ -234,6 +342,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ps.host_op = so;
     dn_ptr.push_back(sp);
     dn_box.push_back(sb);
+    hdn.push_back({tb, sp, sb, so});
     for (int32_t b = 0; b < ps.ntgt; ++b)
       for (int32_t e = sp[b]; e < sp[b + 1]; ++e) ps.host_tgt.push_back(b);
     ps.ent_tgt.upload(ps.host_tgt);
@@ -279,6 +388,16 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
     ds->dnw_nroots = int(t->boxes[lr].size());
     ds->dnw_nlv = D - lr + 1;
     ds->dnw_lroot = lr;
+  }
+  if (Q == 9 && ds->op_sym == 1) {
+    build_chain(t, ds, hup, hdn, slot0);
+    int64_t off = 0;
+    for (int cl = 0; cl < (ds->op_sym == 1 ? 4 : 2); ++cl) {
+      ds->ops_cls_off[cl] = off;
+      const int n = class_size(Q, ds->op_sym, cl);
+      off += int64_t(t->ops.size()) * n * n;
+    }
+    ds->ops_cls.alloc(size_t(off));
   }
   // reduction lists: function r -> rows of KB (leaf order, then local order)
   std::vector<std::vector<int32_t>> occ(t->nbasis);
@@ -680,6 +799,45 @@ void launch_walk(const Tree* t, const int32_t* pptr, const WalkStep* prog, int n
   HIP_OK(hipGetLastError());
 }
 
+// Whether tree_chain_kernel takes the translations of element type T: a
+// chain (build_chain), every class's LDS image of the tree within the
+// block's LDS, and the level above the leaves within the held items.
+template <class T>
+static bool tree_lds_fits(const Tree* t, const DeviceState* ds) {
+  if (ds->chain_nlev == 0 || t->Q != 9 || ds->op_sym != 1 || ds->leaf_box.empty()) return false;
+  if (ds->nbox > kTreeMaxBoxes) return false;
+  // a downward level above the leaves: at most kTreeRounds items per thread and parity
+  const int C = tree_cols(int(sizeof(T)));
+  return (ds->chain_nbelow + 1) / 2 * int64_t(C) <= int64_t(kTreeThreads) * kTreeRounds;
+}
+
+// One launch per reflection class: leaf Omega rows (+ load_shift) in, leaf
+// Mloc rows (+ store_shift) out.
+template <class T>
+static int launch_tree_lds(const Tree* t, DeviceState* ds, T* data, int64_t box_stride, const ColMap& cm,
+                           hipStream_t st, int64_t load_shift, int64_t store_shift) {
+  if (cm.nvalid <= 0) return 0;
+  const int nl = t->nleaf();
+  const int32_t leaf0 = ds->leaf_box[0];
+#define OCCK_TREE(CL)                                                                                              \
+  {                                                                                                                \
+    constexpr int C = tree_cols(int(sizeof(T)));                                                                  \
+    const int64_t ngroups = (cm.nvalid + C - 1) / C;                                                              \
+    const int64_t grid = ((ngroups + 7) / 8) * 8;                                                                 \
+    if (grid > 0x7fffffff) throw std::invalid_argument("translation grid too large; lower jblock");               \
+    hipLaunchKernelGGL((tree_chain_kernel<T, CL>), dim3(unsigned(grid)), dim3(kTreeThreads), 0, st, data,        \
+                       box_stride, cm, ds->chain.p, ds->chain_nlev, ds->ops_cls.p + ds->ops_cls_off[CL], leaf0,  \
+                       nl, ds->nbox, load_shift, store_shift, ngroups);                                          \
+  }
+  OCCK_TREE(0);
+  OCCK_TREE(1);
+  OCCK_TREE(2);
+  OCCK_TREE(3);
+#undef OCCK_TREE
+  HIP_OK(hipGetLastError());
+  return 4;
+}
+
 template void launch_translate<double>(const Tree*, const Pass&, double*, int64_t, const ColMap&, const double*,
                                        hipStream_t, const int8_t*, const double*);
 template void launch_translate<float>(const Tree*, const Pass&, float*, int64_t, const ColMap&, const float*,
@@ -942,7 +1100,7 @@ template <int MODE>
 static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T* Cg, int64_t ldcg, int i0, int i1,
                         int j0, int j1, int jb, int ni, bool prof, hipStream_t st, const void* sel,
                         bool stop_after_up = false, bool sym = false, const std::vector<int>* band = nullptr,
-                        bool two_streams = false) {
+                        bool two_streams = false, bool lds_tree = false) {
   using T = typename ModeT<MODE>::T;
   const int Q = t->Q;
   const int64_t ncol = int64_t(jb) * ni;
@@ -956,6 +1114,14 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
                                 : reinterpret_cast<const T*>(ds->opsf_perm.p);
   const int nj = j1 - j0;
   const int nblk = (nj + jb - 1) / jb;
+  // the whole tree of each column group in LDS, in place of the walks and level passes
+  const bool tree = lds_tree && !sel && !stop_after_up && tree_lds_fits<T>(t, ds);
+  if (tree) {   // its class-compact operators, from this call's FP64 operators
+    const int64_t n = int64_t(ds->ops_cls.n);
+    hipLaunchKernelGGL(opclass_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, ds->ops.p,
+                       int(t->ops.size()), 9, ds->op_sym, ds->ops_cls.p);
+    HIP_OK(hipGetLastError());
+  }
   const bool pipe = two_streams && sym && !sel && !stop_after_up && ds->ws_pipe && ds->dnw_nroots > 0 &&
                     ds->upw_nroots > 0 && nblk > 1;
   hipStream_t stg = st;   // the stream of Omega and the L2P
@@ -1033,6 +1199,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
 
   // upward passes on stream s
   auto upward = [&](const Batch& b, hipStream_t s) {
+    if (tree) return;   // part of the in-LDS tree kernel
     ProfScope ps(ds, prof, OCCK_K_UP, s, ds->upw_nroots > 0 ? 1 + ds->upw_lroot - t->lmin : int(ds->up.size()));
     // ds->up holds levels D-1 down to lmin; the walk covers those at or below its root level
     size_t k0 = 0;
@@ -1052,6 +1219,13 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
     if (sel) {
       ProfScope ps(ds, prof, OCCK_K_SELECT, s, 1 + int(ds->down.size()));
       learned_ranks<T>(t, ds, sel, data, box_stride, b.cm, s);
+    }
+    if (tree) {
+      wait_before_walk();
+      ProfScope ps(ds, prof, OCCK_K_DOWN, s, 4);
+      ProfScope ps_t(ds, prof, OCCK_K_TREE, s, 4);
+      launch_tree_lds<T>(t, ds, data, box_stride, b.cm, s, b.odd ? omega_shift : 0, b.odd ? mloc_shift : 0);
+      return;
     }
     // ds->down holds levels lmin..D; the walk covers those at or below its root level
     const bool walk = !sel && ds->dnw_nroots > 0;
@@ -1243,6 +1417,7 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       launch_to_float(C, ldc, ds->Cf.p, nocc, nbasis, nocc, st);
     }
     const bool two = opts->one_stream == 0;   // the L2P may overlap the next batch on a second stream
+    const bool lt = opts->lds_tree == 1;   // the in-LDS tree kernel on chains, when asked for
     std::vector<int> band;
     const std::vector<int>* bp = nullptr;
     if (opts->pair_thresh > 0.0) {   // occupied-pair screening (checked: symmetric ranges)
@@ -1258,13 +1433,13 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
       ds->band_jb = jb;
     }
     if (prec == OCCK_PREC_FP64)
-      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
+      run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two, lt);
     else if (prec == OCCK_PREC_FP32)
-      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
+      run_batches<kModeF32>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two, lt);
     else if (prec == OCCK_PREC_BF16X3)
-      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
+      run_batches<kModeBF16x3>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two, lt);
     else
-      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two);
+      run_batches<kModeBF16x6>(t, ds, ds->Cf.p, nocc, i0, i1, j0, j1, jb, ni, prof, st, sel, false, sym, bp, two, lt);
     {
       ProfScope ps(ds, prof, OCCK_K_REDUCE, st);
       hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
@@ -1392,7 +1567,8 @@ int32_t far_K_noalloc(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32
       hipLaunchKernelGGL(opgen_perm_kernel, dim3(unsigned(t->ops.size())), dim3(64), 0, st, ds->opparam.p,
                          ds->ops_perm.p, t->L, t->Q, ds->perm.p);
     HIP_OK(hipGetLastError());
-    run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, false, st, nullptr, false, sym);
+    run_batches<kModeF64>(t, ds, C, ldc, i0, i1, j0, j1, jb, ni, false, st, nullptr, false, sym, nullptr, false,
+                          opts->lds_tree == 1);
     hipLaunchKernelGGL(reduce_kernel, dim3(unsigned((ni + 255) / 256), unsigned(nbasis)), dim3(256), 0, st,
                        ds->KB.p, int64_t(ni), ds->occ_ptr.p, ds->occ_row.p, K, ldk, i0, opts->accumulate);
     HIP_OK(hipGetLastError());

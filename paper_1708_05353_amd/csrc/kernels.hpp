@@ -1226,6 +1226,229 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
   }
 }
 
+// --------------------------------------------------------------------------
+// The whole tree of a column group in LDS (M2M, M2L and L2L, Eqs. 11-13 and
+// 17a-c) on chains: trees split along x only whose every level is one
+// unbroken row of boxes, and whose every interaction list is the in-range
+// part of one displacement stencil per level and x parity.
+// Displacements on the x axis keep the four reflection classes of the real
+// components apart, so each class is a problem of its own.  One block per
+// (group of C carried columns, class CLS) reads the leaf multipoles of its
+// columns once, runs the upward levels and then the downward levels in LDS,
+// and writes the leaf local expansions once: per j batch HBM sees one read
+// and one write of the leaf rows, where the walks and level passes write and
+// read back every box of the tree.
+//
+// LDS holds the class's NK components of every box slot and column at
+// lds[(slot * NK + k) * C + c].  At each level all threads take the level's
+// (box, column) items, even boxes first and then odd ones, so that the
+// operators of a pass are uniform and come from scalar loads; a downward
+// level's local expansions replace its multipoles once all are formed (held
+// in registers across a barrier).  Each box takes its terms in the order of
+// the level-by-level passes (parent first, then the stencil in increasing
+// displacement; out-of-range stencil entries are skipped) with FP64
+// operators and accumulators.
+// --------------------------------------------------------------------------
+constexpr int kChainStencil = 8;   // stencil entries per parity
+struct ChainLevel {
+  int32_t n, slot0, x0, pad0;     // boxes of the level, first box slot, x index of the first box
+  int32_t up_op[2];               // M2M operators of the even-x and odd-x child (levels above the leaves)
+  int32_t dn_op[2];               // L2L operators of even-x and odd-x boxes (levels below the first)
+  int32_t ne[2];                  // stencil entries of even-x and odd-x boxes
+  int32_t d[2][kChainStencil];    // source minus target, increasing
+  int32_t op[2][kChainStencil];   // M2L operator of each entry
+  int32_t pad[6];
+};
+constexpr int kTreeThreads = 512;
+constexpr int kTreeMaxBoxes = 512;  // box slots in LDS
+constexpr int kTreeRounds = 4;      // (box, column) items per thread and parity on a downward level above the leaves
+
+__host__ __device__ constexpr int class_size(int Q, int sym, int cls) {
+  int n = 0;
+  for (int q = 0; q < Q; ++q) n += real_class(q, sym) == cls ? 1 : 0;
+  return n;
+}
+// the class's components in ascending q, 4 bits each
+__host__ __device__ constexpr uint64_t class_pack(int Q, int sym, int cls) {
+  uint64_t p = 0;
+  int k = 0;
+  for (int q = 0; q < Q; ++q)
+    if (real_class(q, sym) == cls) p |= uint64_t(q) << (4 * k++);
+  return p;
+}
+// columns per block: 64 bytes per component row of a box slot
+__host__ __device__ constexpr int tree_cols(int tbytes) { return 64 / tbytes; }
+
+template <class T, int CLS>
+__global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
+    T* __restrict__ data, int64_t box_stride, ColMap cm, const ChainLevel* __restrict__ lv, int nlev,
+    const double* __restrict__ opc, int32_t leaf0, int32_t nleaf, int32_t nbox, int64_t load_shift,
+    int64_t store_shift, int64_t ngroups) {
+  constexpr int Q = 9, SYM = 1;
+  constexpr int NK = class_size(Q, SYM, CLS);
+  constexpr uint64_t QP = class_pack(Q, SYM, CLS);
+  constexpr int C = tree_cols(int(sizeof(T)));
+  constexpr int NT = kTreeThreads;
+  static_assert(NK > 0 && NT % C == 0, "class layout");
+  __shared__ T lds[kTreeMaxBoxes * NK * C];
+  const int64_t per = (int64_t(gridDim.x) + 7) / 8;
+  const int64_t grp = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (grp >= ngroups) return;
+  const int tid = threadIdx.x;
+  const int c = tid % C;
+  const int64_t v = grp * C + c;
+  const bool ok = v < cm.nvalid;
+  const int64_t col = ok ? carried_col(cm, v) : 0;   // invalid columns read column 0, store nothing
+  const int64_t ncol = cm.ncol;
+  auto comp = [](int k) { return int((QP >> (4 * k)) & 15); };
+  // leaf multipoles of the class into LDS, rows r = (leaf, k), U loads in flight per thread
+  {
+    const gbl<const T>* base = as_global(static_cast<const T*>(data)) + col;
+    constexpr int RPP = NT / C;   // rows per pass
+    constexpr int U = 16;
+    const int nrow = nleaf * NK;
+    for (int r0 = tid / C; r0 < nrow; r0 += U * RPP) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * RPP;
+        if (r < nrow) {
+          const int b = r / NK, k = r - b * NK;
+          x[u] = base[(int64_t(leaf0 + b) + load_shift) * box_stride + int64_t(comp(k)) * ncol];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int r = r0 + u * RPP;
+        if (r < nrow) lds[(int(leaf0) * NK + r) * C + c] = x[u];
+      }
+    }
+  }
+  __syncthreads();
+  const cst<double>* A0 = as_const(opc);
+  // acc += w * T_op x(slot) over the class (T[i][k] at A[i * NK + k]); a
+  // term a lane does not take reads slot `alt` and adds exact zeros
+  auto term = [&](double (&acc)[NK], int op, int slot, bool take, int alt) {
+    const cst<double>* A = A0 + op * (NK * NK);
+    const int sl = take ? slot : alt;
+    double x[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) x[k] = take ? double(lds[(sl * NK + k) * C + c]) : 0.0;
+#pragma unroll
+    for (int i = 0; i < NK; ++i)
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[i] = fma(A[i * NK + k], x[k], acc[i]);
+  };
+  // upward levels: Omega(p) = sum over the children present (x = 2 x_p, 2 x_p + 1) of T Omega(child)
+  for (int li = nlev - 2; li >= 0; --li) {
+    const ChainLevel L = load_const(lv + li);
+    const ChainLevel Lc = load_const(lv + li + 1);
+    for (int it = tid; it < L.n * C; it += NT) {
+      const int p = it / C;
+      const int c0 = 2 * (L.x0 + p) - Lc.x0;   // index of the even-x child
+      double acc[NK];
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+      term(acc, L.up_op[0], Lc.slot0 + c0, c0 >= 0 && c0 < Lc.n, Lc.slot0);
+      term(acc, L.up_op[1], Lc.slot0 + c0 + 1, c0 + 1 >= 0 && c0 + 1 < Lc.n, Lc.slot0);
+#pragma unroll
+      for (int k = 0; k < NK; ++k) lds[((L.slot0 + p) * NK + k) * C + c] = T(acc[k]);
+    }
+    __syncthreads();
+  }
+  // downward levels: Mloc(b) = T_dn Mloc(parent) + sum over the stencil of T Omega(b + d);
+  // out-of-range stencil entries add exact zeros (the order of the real terms is kept)
+  for (int li = 0; li < nlev; ++li) {
+    const ChainLevel L = load_const(lv + li);
+    const int ps0 = li > 0 ? load_const(lv + li - 1).slot0 : 0, px0 = li > 0 ? load_const(lv + li - 1).x0 : 0;
+    auto item = [&](int par, int b, double (&acc)[NK]) {
+#pragma unroll
+      for (int k = 0; k < NK; ++k) acc[k] = 0.0;
+      if (li > 0) term(acc, L.dn_op[par], ps0 + ((L.x0 + b) >> 1) - px0, true, 0);
+#pragma unroll
+      for (int e = 0; e < kChainStencil; ++e) {
+        const int s = b + L.d[par][e];
+        term(acc, L.op[par][e], L.slot0 + s, e < L.ne[par] && s >= 0 && s < L.n, L.slot0);
+      }
+    };
+    if (li == nlev - 1) {   // leaves: the local expansions to HBM
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int b0 = (par - L.x0) & 1, cnt = (L.n - b0 + 1) / 2;
+        for (int it = tid; it < cnt * C; it += NT) {
+          const int b = b0 + 2 * (it / C);
+          double acc[NK];
+          item(par, b, acc);
+          if (ok) {
+            gbl<T>* Y = as_global(data) + (int64_t(nbox) + L.slot0 + b + store_shift) * box_stride + col;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) store_stream(Y + int64_t(comp(k)) * ncol, T(acc[k]));
+          }
+        }
+      }
+    } else {   // at most kTreeRounds items per thread and parity (checked on the host)
+      T hold[2][kTreeRounds][NK];
+      int hs[2][kTreeRounds];
+#pragma unroll
+      for (int par = 0; par < 2; ++par) {
+        const int b0 = (par - L.x0) & 1, cnt = (L.n - b0 + 1) / 2;
+#pragma unroll
+        for (int q = 0; q < kTreeRounds; ++q) {
+          const int it = tid + q * NT;
+          hs[par][q] = -1;
+          if (it < cnt * C) {
+            const int b = b0 + 2 * (it / C);
+            double acc[NK];
+            item(par, b, acc);
+            hs[par][q] = L.slot0 + b;
+#pragma unroll
+            for (int k = 0; k < NK; ++k) hold[par][q][k] = T(acc[k]);
+          }
+        }
+      }
+      __syncthreads();   // the level's multipoles are read no more
+#pragma unroll
+      for (int par = 0; par < 2; ++par)
+#pragma unroll
+        for (int q = 0; q < kTreeRounds; ++q)
+          if (hs[par][q] >= 0)
+#pragma unroll
+            for (int k = 0; k < NK; ++k) lds[(hs[par][q] * NK + k) * C + c] = hold[par][q][k];
+    }
+    __syncthreads();
+  }
+}
+
+// Operators of every reflection class in compact form for tree_chain_kernel:
+// class c of op o at out[off_c + (o * n_c + i) * n_c + k] = T[q_i][q_k]
+// (q_i the class's components in ascending order, off_c the sum of
+// nops * n_c'^2 over the classes before c).  One thread per element; Q <= 16
+// (one row tile of the fragment-ordered operator).
+static __global__ void opclass_kernel(const double* __restrict__ ops, int nops, int Q, int sym, double* __restrict__ out) {
+  const int KS = ksteps_of(Q);
+  const int ncls = sym == 1 ? 4 : sym == 2 ? 2 : 1;
+  int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int cl = 0; cl < ncls; ++cl) {
+    const int n = class_size(Q, sym, cl);
+    const int64_t sz = int64_t(nops) * n * n;
+    if (e < sz) {
+      const int o = int(e / (n * n)), r = int(e % (n * n));
+      const int i = r / n, k = r % n;
+      int qi = -1, qk = -1;
+      for (int q = 0, m = 0; q < Q; ++q)
+        if (real_class(q, sym) == cl) {
+          if (m == i) qi = q;
+          if (m == k) qk = q;
+          ++m;
+        }
+      out[e] = ops[int64_t(o) * KS * 64 + (qk >> 2) * 64 + qi + 16 * (qk & 3)];
+      return;
+    }
+    e -= sz;
+    out += sz;
+  }
+}
+
 // out[r*ldo + c] = float(in[r*ldi + c]) for r < rows, c < cols
 static __global__ void to_float_kernel(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
                                 int64_t rows, int64_t cols) {

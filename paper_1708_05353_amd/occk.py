@@ -58,7 +58,7 @@ class _JFlops(ct.Structure):
 class _Opts(ct.Structure):
     _fields_ = [("precision", ct.c_int32), ("rank_mode", ct.c_int32), ("selector", ct.c_void_p),
                 ("jblock", ct.c_int32), ("accumulate", ct.c_int32), ("pair_thresh", ct.c_double),
-                ("one_stream", ct.c_int32)]
+                ("one_stream", ct.c_int32), ("lds_tree", ct.c_int32)]
 
 
 EXPORTS = {
@@ -124,7 +124,7 @@ EXPORTS = {
 }
 
 KERNEL_CLASSES = ["opgen", "half", "omega", "up", "down", "l2p", "reduce", "convert", "select",
-                  "ht", "up_walk", "down_walk", "l2p_direct", "l2p_mirror"]
+                  "ht", "up_walk", "down_walk", "l2p_direct", "l2p_mirror", "tree"]
 NFEAT, NOUT, NPARAM = 24, 8, 6280
 
 _lib = None
@@ -301,12 +301,13 @@ class Tree:
 
 def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP64,
           jblock: int = 0, accumulate: bool = False, stream=None, selector=None, pair_thresh: float = 0.0,
-          one_stream: bool = False):
+          one_stream: bool = False, lds_tree: bool = False):
     """K[:, i0:i1] (+)= 2 sum_{j in [j0,j1)} (rj|ji)_ff on the GPU.
 
     C: torch.float64 CUDA tensor (nbasis, ldc) row-major; K: torch.float64 CUDA
     tensor (nbasis, ldk).  Asynchronous on ``stream`` (default: torch's current
-    stream)."""
+    stream).  lds_tree=True runs the translations of chain-like trees as the
+    in-LDS tree kernel (occk_far_opts.lds_tree)."""
     import torch
     nocc = int(C.shape[1])
     i0, i1 = (0, nocc) if i_range is None else i_range
@@ -318,7 +319,7 @@ def far_K(tree: Tree, C, K, i_range=None, j_range=None, precision: int = PREC_FP
         stream = torch.cuda.current_stream(C.device)
     opts = _Opts(int(precision), RANK_FIXED if selector is None else RANK_LEARNED,
                  None if selector is None else selector.handle.value, int(jblock), int(bool(accumulate)),
-                 float(pair_thresh), int(bool(one_stream)))
+                 float(pair_thresh), int(bool(one_stream)), int(bool(lds_tree)))
     _check(lib().occk_far_K(tree.handle, ct.c_void_p(C.data_ptr()), int(C.stride(0)), nocc, int(i0), int(i1),
                             int(j0), int(j1), ct.byref(opts), ct.c_void_p(K.data_ptr()), int(K.stride(0)),
                             ct.c_void_p(stream.cuda_stream)))

@@ -232,6 +232,8 @@ def test_far_K_validates_before_device_work():
     assert f(C, 20, 20, 0, 10, 0, 20, ct.byref(scr), K, 20, None) == occk.EINVAL
     assert "pair_thresh" in occk.lib().occk_last_error().decode()
     assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(occk._Opts(0, 0, None, 0, 0, 0.0, 2)), K, 20, None) == occk.EINVAL
+    assert f(C, 20, 20, 0, 20, 0, 20, ct.byref(occk._Opts(0, 0, None, 0, 0, 0.0, 0, 3)), K, 20, None) == occk.EINVAL
+    assert "lds_tree" in occk.lib().occk_last_error().decode()
 
 
 def test_batched_one_call_validates_before_device_work():
