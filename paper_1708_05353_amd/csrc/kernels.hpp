@@ -1326,7 +1326,8 @@ __global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
   }
   __syncthreads();
   const cst<double>* A0 = as_const(opc);
-  // acc += w * T_op x(slot) over the class (T[i][k] at A[i * NK + k]); a
+  const cst<ChainLevel>* LV = as_const(lv);   // uniform fields, read where used (scalar loads)
+  // acc += T_op x(slot) over the class (T[i][k] at A[i * NK + k]); a
   // term a lane does not take reads slot `alt` and adds exact zeros
   auto term = [&](double (&acc)[NK], int op, int slot, bool take, int alt) {
     const cst<double>* A = A0 + op * (NK * NK);
@@ -1341,46 +1342,49 @@ __global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
   };
   // upward levels: Omega(p) = sum over the children present (x = 2 x_p, 2 x_p + 1) of T Omega(child)
   for (int li = nlev - 2; li >= 0; --li) {
-    const ChainLevel L = load_const(lv + li);
-    const ChainLevel Lc = load_const(lv + li + 1);
-    for (int it = tid; it < L.n * C; it += NT) {
+    const cst<ChainLevel>& L = LV[li];
+    const cst<ChainLevel>& Lc = LV[li + 1];
+    const int n = L.n, s0 = L.slot0, x0 = L.x0, cn = Lc.n, cs0 = Lc.slot0, cx0 = Lc.x0;
+    for (int it = tid; it < n * C; it += NT) {
       const int p = it / C;
-      const int c0 = 2 * (L.x0 + p) - Lc.x0;   // index of the even-x child
+      const int c0 = 2 * (x0 + p) - cx0;   // index of the even-x child
       double acc[NK];
 #pragma unroll
       for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-      term(acc, L.up_op[0], Lc.slot0 + c0, c0 >= 0 && c0 < Lc.n, Lc.slot0);
-      term(acc, L.up_op[1], Lc.slot0 + c0 + 1, c0 + 1 >= 0 && c0 + 1 < Lc.n, Lc.slot0);
+      term(acc, L.up_op[0], cs0 + c0, c0 >= 0 && c0 < cn, cs0);
+      term(acc, L.up_op[1], cs0 + c0 + 1, c0 + 1 >= 0 && c0 + 1 < cn, cs0);
 #pragma unroll
-      for (int k = 0; k < NK; ++k) lds[((L.slot0 + p) * NK + k) * C + c] = T(acc[k]);
+      for (int k = 0; k < NK; ++k) lds[((s0 + p) * NK + k) * C + c] = T(acc[k]);
     }
     __syncthreads();
   }
   // downward levels: Mloc(b) = T_dn Mloc(parent) + sum over the stencil of T Omega(b + d);
   // out-of-range stencil entries add exact zeros (the order of the real terms is kept)
   for (int li = 0; li < nlev; ++li) {
-    const ChainLevel L = load_const(lv + li);
-    const int ps0 = li > 0 ? load_const(lv + li - 1).slot0 : 0, px0 = li > 0 ? load_const(lv + li - 1).x0 : 0;
+    const cst<ChainLevel>& L = LV[li];
+    const int n = L.n, s0 = L.slot0, x0 = L.x0;
+    const int ps0 = li > 0 ? int(LV[li - 1].slot0) : 0, px0 = li > 0 ? int(LV[li - 1].x0) : 0;
     auto item = [&](int par, int b, double (&acc)[NK]) {
 #pragma unroll
       for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-      if (li > 0) term(acc, L.dn_op[par], ps0 + ((L.x0 + b) >> 1) - px0, true, 0);
-#pragma unroll
-      for (int e = 0; e < kChainStencil; ++e) {
+      if (li > 0) term(acc, L.dn_op[par], ps0 + ((x0 + b) >> 1) - px0, true, 0);
+      const int ne = L.ne[par];
+#pragma unroll 1
+      for (int e = 0; e < ne; ++e) {
         const int s = b + L.d[par][e];
-        term(acc, L.op[par][e], L.slot0 + s, e < L.ne[par] && s >= 0 && s < L.n, L.slot0);
+        term(acc, L.op[par][e], s0 + s, s >= 0 && s < n, s0);
       }
     };
     if (li == nlev - 1) {   // leaves: the local expansions to HBM
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const int b0 = (par - L.x0) & 1, cnt = (L.n - b0 + 1) / 2;
+        const int b0 = (par - x0) & 1, cnt = (n - b0 + 1) / 2;
         for (int it = tid; it < cnt * C; it += NT) {
           const int b = b0 + 2 * (it / C);
           double acc[NK];
           item(par, b, acc);
           if (ok) {
-            gbl<T>* Y = as_global(data) + (int64_t(nbox) + L.slot0 + b + store_shift) * box_stride + col;
+            gbl<T>* Y = as_global(data) + (int64_t(nbox) + s0 + b + store_shift) * box_stride + col;
 #pragma unroll
             for (int k = 0; k < NK; ++k) store_stream(Y + int64_t(comp(k)) * ncol, T(acc[k]));
           }
@@ -1391,7 +1395,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
       int hs[2][kTreeRounds];
 #pragma unroll
       for (int par = 0; par < 2; ++par) {
-        const int b0 = (par - L.x0) & 1, cnt = (L.n - b0 + 1) / 2;
+        const int b0 = (par - x0) & 1, cnt = (n - b0 + 1) / 2;
 #pragma unroll
         for (int q = 0; q < kTreeRounds; ++q) {
           const int it = tid + q * NT;
@@ -1400,7 +1404,7 @@ __global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
             const int b = b0 + 2 * (it / C);
             double acc[NK];
             item(par, b, acc);
-            hs[par][q] = L.slot0 + b;
+            hs[par][q] = s0 + b;
 #pragma unroll
             for (int k = 0; k < NK; ++k) hold[par][q][k] = T(acc[k]);
           }
