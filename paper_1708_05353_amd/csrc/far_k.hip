@@ -806,9 +806,10 @@ template <class T>
 static bool tree_lds_fits(const Tree* t, const DeviceState* ds) {
   if (ds->chain_nlev == 0 || t->Q != 9 || ds->op_sym != 1 || ds->leaf_box.empty()) return false;
   if (ds->nbox > kTreeMaxBoxes) return false;
-  // a downward level above the leaves: at most kTreeRounds items per thread and parity
+  // a downward level above the leaves: the boxes of one x parity over half the
+  // threads, at most kTreeRounds items each
   const int C = tree_cols(int(sizeof(T)));
-  return (ds->chain_nbelow + 1) / 2 * int64_t(C) <= int64_t(kTreeThreads) * kTreeRounds;
+  return (ds->chain_nbelow + 1) / 2 * int64_t(C) <= int64_t(kTreeThreads / 2) * kTreeRounds;
 }
 
 // One launch per reflection class: leaf Omega rows (+ load_shift) in, leaf

@@ -1240,11 +1240,12 @@ __global__ __launch_bounds__(256) void down_walk_kernel(T* __restrict__ data, in
 // read back every box of the tree.
 //
 // LDS holds the class's NK components of every box slot and column at
-// lds[(slot * NK + k) * C + c].  At each level all threads take the level's
-// (box, column) items, even boxes first and then odd ones, so that the
-// operators of a pass are uniform and come from scalar loads; a downward
-// level's local expansions replace its multipoles once all are formed (held
-// in registers across a barrier).  Each box takes its terms in the order of
+// lds[(slot * NK + k) * C + c].  At each level the threads take the level's
+// (box, column) items, two at a time; on the downward levels one half of the
+// threads takes the boxes of even x and the other half those of odd x, so
+// that the operators of a wave are uniform and come from scalar loads.  A
+// downward level's local expansions replace its multipoles once all are
+// formed (held in registers across a barrier).  Each box takes its terms in the order of
 // the level-by-level passes (parent first, then the stencil in increasing
 // displacement; out-of-range stencil entries are skipped) with FP64
 // operators and accumulators.
@@ -1261,7 +1262,7 @@ struct ChainLevel {
 };
 constexpr int kTreeThreads = 512;
 constexpr int kTreeMaxBoxes = 512;  // box slots in LDS
-constexpr int kTreeRounds = 4;      // (box, column) items per thread and parity on a downward level above the leaves
+constexpr int kTreeRounds = 4;      // (box, column) items per thread on a downward level above the leaves (even)
 
 __host__ __device__ constexpr int class_size(int Q, int sym, int cls) {
   int n = 0;
@@ -1327,97 +1328,121 @@ __global__ __launch_bounds__(kTreeThreads) void tree_chain_kernel(
   __syncthreads();
   const cst<double>* A0 = as_const(opc);
   const cst<ChainLevel>* LV = as_const(lv);   // uniform fields, read where used (scalar loads)
-  // acc += T_op x(slot) over the class (T[i][k] at A[i * NK + k]); a
-  // term a lane does not take reads slot `alt` and adds exact zeros
-  auto term = [&](double (&acc)[NK], int op, int slot, bool take, int alt) {
+  // Two items (box, column) per thread go through the terms together: one
+  // operator read serves both, and their LDS reads and FMA chains overlap.
+  // acc_r += T_op x(slot_r) over the class (T[i][k] at A[i * NK + k]); an
+  // item that does not take the term reads slot `alt` and adds exact zeros.
+  auto term2 = [&](double (&a0)[NK], double (&a1)[NK], int op, int sl0, bool t0, int sl1, bool t1, int alt) {
     const cst<double>* A = A0 + op * (NK * NK);
-    const int sl = take ? slot : alt;
-    double x[NK];
+    const int u0 = t0 ? sl0 : alt, u1 = t1 ? sl1 : alt;
+    double x0[NK], x1[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) x[k] = take ? double(lds[(sl * NK + k) * C + c]) : 0.0;
+    for (int k = 0; k < NK; ++k) {
+      x0[k] = t0 ? double(lds[(u0 * NK + k) * C + c]) : 0.0;
+      x1[k] = t1 ? double(lds[(u1 * NK + k) * C + c]) : 0.0;
+    }
 #pragma unroll
     for (int i = 0; i < NK; ++i)
 #pragma unroll
-      for (int k = 0; k < NK; ++k) acc[i] = fma(A[i * NK + k], x[k], acc[i]);
+      for (int k = 0; k < NK; ++k) {
+        const double a = A[i * NK + k];
+        a0[i] = fma(a, x0[k], a0[i]);
+        a1[i] = fma(a, x1[k], a1[i]);
+      }
   };
   // upward levels: Omega(p) = sum over the children present (x = 2 x_p, 2 x_p + 1) of T Omega(child)
   for (int li = nlev - 2; li >= 0; --li) {
     const cst<ChainLevel>& L = LV[li];
     const cst<ChainLevel>& Lc = LV[li + 1];
     const int n = L.n, s0 = L.slot0, x0 = L.x0, cn = Lc.n, cs0 = Lc.slot0, cx0 = Lc.x0;
-    for (int it = tid; it < n * C; it += NT) {
-      const int p = it / C;
-      const int c0 = 2 * (x0 + p) - cx0;   // index of the even-x child
-      double acc[NK];
+    for (int it = tid; it < n * C; it += 2 * NT) {
+      const bool v1 = it + NT < n * C;
+      const int p0 = it / C, p1 = v1 ? (it + NT) / C : p0;
+      const int c0 = 2 * (x0 + p0) - cx0, c1 = 2 * (x0 + p1) - cx0;   // indices of the even-x children
+      double a0[NK], a1[NK];
 #pragma unroll
-      for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-      term(acc, L.up_op[0], cs0 + c0, c0 >= 0 && c0 < cn, cs0);
-      term(acc, L.up_op[1], cs0 + c0 + 1, c0 + 1 >= 0 && c0 + 1 < cn, cs0);
+      for (int k = 0; k < NK; ++k) a0[k] = a1[k] = 0.0;
+      term2(a0, a1, L.up_op[0], cs0 + c0, c0 >= 0 && c0 < cn, cs0 + c1, c1 >= 0 && c1 < cn, cs0);
+      term2(a0, a1, L.up_op[1], cs0 + c0 + 1, c0 + 1 >= 0 && c0 + 1 < cn, cs0 + c1 + 1, c1 + 1 >= 0 && c1 + 1 < cn,
+            cs0);
 #pragma unroll
-      for (int k = 0; k < NK; ++k) lds[((s0 + p) * NK + k) * C + c] = T(acc[k]);
+      for (int k = 0; k < NK; ++k) {
+        lds[((s0 + p0) * NK + k) * C + c] = T(a0[k]);
+        if (v1) lds[((s0 + p1) * NK + k) * C + c] = T(a1[k]);
+      }
     }
     __syncthreads();
   }
   // downward levels: Mloc(b) = T_dn Mloc(parent) + sum over the stencil of T Omega(b + d);
-  // out-of-range stencil entries add exact zeros (the order of the real terms is kept)
+  // out-of-range stencil entries add exact zeros (the order of the real terms is kept).
+  // The first half of the threads takes the boxes of even x, the second half
+  // those of odd x (each wave one parity: uniform operators).
+  constexpr int NH = NT / 2;
+  const int par = __builtin_amdgcn_readfirstlane(tid / NH), ht = tid % NH;
   for (int li = 0; li < nlev; ++li) {
     const cst<ChainLevel>& L = LV[li];
     const int n = L.n, s0 = L.slot0, x0 = L.x0;
     const int ps0 = li > 0 ? int(LV[li - 1].slot0) : 0, px0 = li > 0 ? int(LV[li - 1].x0) : 0;
-    auto item = [&](int par, int b, double (&acc)[NK]) {
+    const int b0 = (par - x0) & 1, cnt = (n - b0 + 1) / 2, nit = cnt * C;
+    const int ne = L.ne[par], dop = L.dn_op[par];
+    // the items it and it + NH of this parity; v1: the second one exists
+    auto items = [&](int it, bool v1, int& b0_, int& b1_, double (&a0)[NK], double (&a1)[NK]) {
+      b0_ = b0 + 2 * (it / C);
+      b1_ = v1 ? b0 + 2 * ((it + NH) / C) : b0_;
 #pragma unroll
-      for (int k = 0; k < NK; ++k) acc[k] = 0.0;
-      if (li > 0) term(acc, L.dn_op[par], ps0 + ((x0 + b) >> 1) - px0, true, 0);
-      const int ne = L.ne[par];
+      for (int k = 0; k < NK; ++k) a0[k] = a1[k] = 0.0;
+      if (li > 0)
+        term2(a0, a1, dop, ps0 + ((x0 + b0_) >> 1) - px0, true, ps0 + ((x0 + b1_) >> 1) - px0, true, 0);
 #pragma unroll 1
       for (int e = 0; e < ne; ++e) {
-        const int s = b + L.d[par][e];
-        term(acc, L.op[par][e], s0 + s, s >= 0 && s < n, s0);
+        const int d = L.d[par][e], op = L.op[par][e];
+        const int q0 = b0_ + d, q1 = b1_ + d;
+        term2(a0, a1, op, s0 + q0, q0 >= 0 && q0 < n, s0 + q1, q1 >= 0 && q1 < n, s0);
       }
     };
     if (li == nlev - 1) {   // leaves: the local expansions to HBM
+      for (int it = ht; it < nit; it += 2 * NH) {
+        const bool v1 = it + NH < nit;
+        int bb0, bb1;
+        double a0[NK], a1[NK];
+        items(it, v1, bb0, bb1, a0, a1);
+        if (ok) {
+          gbl<T>* Y0 = as_global(data) + (int64_t(nbox) + s0 + bb0 + store_shift) * box_stride + col;
+          gbl<T>* Y1 = as_global(data) + (int64_t(nbox) + s0 + bb1 + store_shift) * box_stride + col;
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        const int b0 = (par - x0) & 1, cnt = (n - b0 + 1) / 2;
-        for (int it = tid; it < cnt * C; it += NT) {
-          const int b = b0 + 2 * (it / C);
-          double acc[NK];
-          item(par, b, acc);
-          if (ok) {
-            gbl<T>* Y = as_global(data) + (int64_t(nbox) + s0 + b + store_shift) * box_stride + col;
-#pragma unroll
-            for (int k = 0; k < NK; ++k) store_stream(Y + int64_t(comp(k)) * ncol, T(acc[k]));
+          for (int k = 0; k < NK; ++k) {
+            store_stream(Y0 + int64_t(comp(k)) * ncol, T(a0[k]));
+            if (v1) store_stream(Y1 + int64_t(comp(k)) * ncol, T(a1[k]));
           }
         }
       }
-    } else {   // at most kTreeRounds items per thread and parity (checked on the host)
-      T hold[2][kTreeRounds][NK];
-      int hs[2][kTreeRounds];
+    } else {   // at most kTreeRounds items per thread (checked on the host), two at a time
+      T hold[kTreeRounds][NK];
+      int hs[kTreeRounds];
 #pragma unroll
-      for (int par = 0; par < 2; ++par) {
-        const int b0 = (par - x0) & 1, cnt = (n - b0 + 1) / 2;
+      for (int q = 0; q < kTreeRounds; q += 2) {
+        const int it = ht + q * NH;
+        hs[q] = hs[q + 1] = -1;
+        if (it < nit) {
+          const bool v1 = it + NH < nit;
+          int bb0, bb1;
+          double a0[NK], a1[NK];
+          items(it, v1, bb0, bb1, a0, a1);
+          hs[q] = s0 + bb0;
+          if (v1) hs[q + 1] = s0 + bb1;
 #pragma unroll
-        for (int q = 0; q < kTreeRounds; ++q) {
-          const int it = tid + q * NT;
-          hs[par][q] = -1;
-          if (it < cnt * C) {
-            const int b = b0 + 2 * (it / C);
-            double acc[NK];
-            item(par, b, acc);
-            hs[par][q] = s0 + b;
-#pragma unroll
-            for (int k = 0; k < NK; ++k) hold[par][q][k] = T(acc[k]);
+          for (int k = 0; k < NK; ++k) {
+            hold[q][k] = T(a0[k]);
+            hold[q + 1][k] = T(a1[k]);
           }
         }
       }
       __syncthreads();   // the level's multipoles are read no more
 #pragma unroll
-      for (int par = 0; par < 2; ++par)
+      for (int q = 0; q < kTreeRounds; ++q)
+        if (hs[q] >= 0)
 #pragma unroll
-        for (int q = 0; q < kTreeRounds; ++q)
-          if (hs[par][q] >= 0)
-#pragma unroll
-            for (int k = 0; k < NK; ++k) lds[(hs[par][q] * NK + k) * C + c] = hold[par][q][k];
+          for (int k = 0; k < NK; ++k) lds[(hs[q] * NK + k) * C + c] = hold[q][k];
     }
     __syncthreads();
   }
