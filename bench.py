@@ -12,8 +12,9 @@ overlapping the next batch's translations).  The kernels and the roofline
 object come from the same calls timed again in the one-stream schedule, where
 every kernel runs alone, with HIP events on the library's stream (the
 kernel with the largest time per call is the roofline's).  The "mixed"
-object times the FP32 path on the same inputs and gives its error against
-the FP64 result.  hbm_copy is the rate of a plain device copy on the box.
+object times the FP32, split-BF16x6 and split-BF16x3 paths on the same
+inputs, gives each one's error against the FP64 result, and heads with the
+fastest mode within the 1e-6 budget (BF16x3 is held to 5e-5).  hbm_copy is the rate of a plain device copy on the box.
 cpu_baseline times the FP64 oracle on a bounded j sample of the same
 workload and scales it linearly in the number of j columns.
 """
@@ -1067,29 +1068,37 @@ def main():
     }
     out["hbm_copy"] = copy_rate()   # the streaming rate the box delivers (read + write), for the HBM rooflines
     if args.precision == "fp64" and not args.no_mixed:
-        # the mixed path on the same inputs: FP32 contractions and translations,
+        # the mixed path on the same inputs: FP32 contractions and translations
+        # (FP32, or split-BF16 products on the MFMA with FP32 accumulation),
         # FP64 operators and K accumulation; error against this FP64 result
         K64 = K.clone()
         Km = torch.zeros_like(K)
-        mcall = lambda: occk.far_K(tree, Cd, Km, precision=occk.PREC_FP32, jblock=args.jblock, stream=stream,
-                                   one_stream=args.one_stream)
-        mcall()
-        for _ in range(args.warmup):
+        modes = [("fp32", occk.PREC_FP32, 1e-6), ("bf16x6", occk.PREC_BF16X6, 1e-6),
+                 ("bf16x3", occk.PREC_BF16X3, 5e-5)]
+        mixed = {}
+        for mname, mcode, bound in modes:
+            mcall = lambda: occk.far_K(tree, Cd, Km, precision=mcode, jblock=args.jblock, stream=stream,
+                                       one_stream=args.one_stream)
             mcall()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            mcall()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms_m = e0.elapsed_time(e1) / args.steps
-        err = float((Km - K64).abs().max() / K64.abs().max())
-        out["mixed"] = {"precision": "fp32", "ms_per_step": round(ms_m, 3),
-                        "value": round(fl["total"] / (ms_m * 1e-3) / 1e9, 1),
-                        "speedup_vs_fp64": round(ms / ms_m, 3), "rel_err_vs_fp64": err, "bound": 1e-6}
-        print(f"[bench] mixed fp32 {ms_m:.2f} ms/step, x{ms / ms_m:.2f}, rel err {err:.2e}", file=sys.stderr,
-              flush=True)
+            for _ in range(args.warmup):
+                mcall()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                mcall()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_m = e0.elapsed_time(e1) / args.steps
+            err = float((Km - K64).abs().max() / K64.abs().max())
+            mixed[mname] = {"ms_per_step": round(ms_m, 3), "value": round(fl["total"] / (ms_m * 1e-3) / 1e9, 1),
+                            "speedup_vs_fp64": round(ms / ms_m, 3), "rel_err_vs_fp64": err, "bound": bound}
+            print(f"[bench] mixed {mname} {ms_m:.2f} ms/step, x{ms / ms_m:.2f}, rel err {err:.2e}",
+                  file=sys.stderr, flush=True)
+        # the headline mixed figure: the fastest mode within the 1e-6 budget
+        ok = [m for m, _, b in modes if b <= 1e-6 and mixed[m]["rel_err_vs_fp64"] <= b]
+        best = min(ok, key=lambda m: mixed[m]["ms_per_step"]) if ok else "fp32"
+        out["mixed"] = dict(precision=best, **mixed[best], modes=mixed)
     if args.precision == "fp64" and not args.no_near:
         out["near_K"] = bench_near(wl, Cd, args, stream)
         print(f"[bench] near-field K {out['near_K']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)

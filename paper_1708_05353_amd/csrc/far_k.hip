@@ -1257,7 +1257,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       r.akoff = int32_t(b.jrel);
       r.klim = b.jbk;
     }
-    if (MODE <= kModeF32 && !ds->l2pw_nt_start.empty()) {   // the split-BF16 modes would need 256+ VGPRs
+    if (!ds->l2pw_nt_start.empty()) {
       r.tile0 = ds->l2pw_nt_start[size_t(b.ct0 / 4)];
       r.ntiles = ds->l2pw_nt_start[size_t(b.ct0 / 4) + 1] - r.tile0;
       if (sym)
@@ -1286,7 +1286,7 @@ static void run_batches(Tree* t, DeviceState* ds, const typename ModeT<MODE>::T*
       m.aptr = mshift;
       m.coff = b.jrel;
       m.mlim = b.jbk;
-      if (MODE <= kModeF32 && ds->n_l2ptw > 0) {   // the split-BF16 modes would need 256+ VGPRs
+      if (ds->n_l2ptw > 0) {
         m.ntiles = ds->n_l2ptw;
         hipLaunchKernelGGL((l2pt_wide_kernel<MODE>), dim3(gemm_grid(m.ntiles)), dim3(256), 0, s, ds->d_l2pt.p,
                            ds->t_l2ptw.p, Cg, ldcg, m);

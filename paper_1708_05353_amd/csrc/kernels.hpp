@@ -299,34 +299,48 @@ __device__ inline uint32_t bf16_rne_bits(float x) {   // bf16 bits (in the low h
   return u >> 16;
 }
 
+// The splits round to nearest even with the hardware's packed conversion
+// (two FP32 values to two bf16 per instruction); a bf16 value widens back to
+// FP32 exactly as its bits shifted into the high half.
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+__device__ inline f2 widen2(bf16x2 v) {
+  const uint32_t u = __builtin_bit_cast(uint32_t, v);
+  return f2{__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u)};
+}
+
 // x[e] -> hi[e] + lo[e] as bf16 vectors
 __device__ inline void split8(const float* x, bf16x8& hi, bf16x8& lo) {
-  s8v h, l;
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t hb = bf16_rne_bits(x[e]);
-    const float hf = __uint_as_float(hb << 16);
-    h[e] = short(hb);
-    l[e] = short(bf16_rne_bits(x[e] - hf));
+  bf16x2 h[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const f2 v{x[2 * e], x[2 * e + 1]};
+    h[e] = __builtin_convertvector(v, bf16x2);
+    l[e] = __builtin_convertvector(v - widen2(h[e]), bf16x2);
   }
-  hi = __builtin_bit_cast(bf16x8, h);
-  lo = __builtin_bit_cast(bf16x8, l);
+  hi = __builtin_shufflevector(__builtin_shufflevector(h[0], h[1], 0, 1, 2, 3),
+                               __builtin_shufflevector(h[2], h[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
+  lo = __builtin_shufflevector(__builtin_shufflevector(l[0], l[1], 0, 1, 2, 3),
+                               __builtin_shufflevector(l[2], l[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // x[e] -> hi[e] + mid[e] + lo[e] as bf16 vectors
 __device__ inline void split8x3(const float* x, bf16x8& hi, bf16x8& mid, bf16x8& lo) {
-  s8v h, m, l;
-  for (int e = 0; e < 8; ++e) {
-    const uint32_t hb = bf16_rne_bits(x[e]);
-    const float r1 = x[e] - __uint_as_float(hb << 16);
-    const uint32_t mb = bf16_rne_bits(r1);
-    const float r2 = r1 - __uint_as_float(mb << 16);
-    h[e] = short(hb);
-    m[e] = short(mb);
-    l[e] = short(bf16_rne_bits(r2));
+  bf16x2 h[4], m[4], l[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const f2 v{x[2 * e], x[2 * e + 1]};
+    h[e] = __builtin_convertvector(v, bf16x2);
+    const f2 r1 = v - widen2(h[e]);
+    m[e] = __builtin_convertvector(r1, bf16x2);
+    l[e] = __builtin_convertvector(r1 - widen2(m[e]), bf16x2);
   }
-  hi = __builtin_bit_cast(bf16x8, h);
-  mid = __builtin_bit_cast(bf16x8, m);
-  lo = __builtin_bit_cast(bf16x8, l);
+  hi = __builtin_shufflevector(__builtin_shufflevector(h[0], h[1], 0, 1, 2, 3),
+                               __builtin_shufflevector(h[2], h[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
+  mid = __builtin_shufflevector(__builtin_shufflevector(m[0], m[1], 0, 1, 2, 3),
+                                __builtin_shufflevector(m[2], m[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
+  lo = __builtin_shufflevector(__builtin_shufflevector(l[0], l[1], 0, 1, 2, 3),
+                               __builtin_shufflevector(l[2], l[3], 0, 1, 2, 3), 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 __device__ inline d4 mfma4(double a, double b, d4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -366,11 +380,28 @@ using GemmRows144 = GemmShape<1, 4, 9, 1>;  // 144 x 64: a whole leaf per tile
 
 // NB = 2: double-buffered operand tiles (one barrier per K tile); NB = 1:
 // single buffer (two barriers per K tile, half the LDS).
-template <int MODE, class S = GemmSquare, int NB = 1>
-struct GemmSmem {
+template <int MODE, class S, int NB>
+struct GemmSmemPlain {
   typename ModeT<MODE>::T A[NB][ModeT<MODE>::KT][S::BM + 1];
   typename ModeT<MODE>::T B[NB][ModeT<MODE>::KT][S::BN + 1];
 };
+// Split-BF16 modes: the operand tiles are split once, when they are stored,
+// and held as NP bf16 planes in the MFMA fragment layout: row m of A (column
+// n of B) holds its KT = 32 k as four 8-element chunks, one 16-byte fragment
+// each.  Chunk g of row m sits at position split_chunk(m, g): with 64-byte
+// rows, the 16-byte accesses of 8 (or 16) consecutive rows at one chunk then
+// fall on distinct banks of a 32 (or 64) bank LDS.
+constexpr bool mode_split(int mode) { return mode == kModeBF16x3 || mode == kModeBF16x6; }
+constexpr int mode_planes(int mode) { return mode == kModeBF16x6 ? 3 : 2; }
+__device__ inline int split_chunk(int m, int g) { return g ^ (((m >> 1) ^ (m >> 2)) & 3); }
+template <class S, int NB, int NP>
+struct GemmSmemSplit {
+  bf16x8 A[NB][NP][S::BM][4];
+  bf16x8 B[NB][NP][S::BN][4];
+};
+template <int MODE, class S = GemmSquare, int NB = 1>
+using GemmSmem = typename std::conditional<mode_split(MODE), GemmSmemSplit<S, NB, mode_planes(MODE)>,
+                                           GemmSmemPlain<MODE, S, NB>>::type;
 
 // Read in place of operand elements outside their matrix: the GEMM operand
 // loads take no branch and their values need no masking afterwards.
@@ -411,7 +442,16 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // ahead of the MFMAs
   static_assert(DEPTH == 1 || (DEPTH == 2 && NB == 2), "two-deep loads need two LDS buffers");
   constexpr int NR = DEPTH;
-  T ra[NR][EA], rb[NR][EB];
+  constexpr bool kSplit = mode_split(MODE);
+  T ra[NR][kSplit ? 1 : EA], rb[NR][kSplit ? 1 : EB];
+  // Split-BF16 modes move whole k chunks: unit c = tid + 256 p of the A tile
+  // is row m, chunk g (k = 8g .. 8g + 7), with m = c / KC, g = c % KC when A
+  // is k-contiguous and m = c % BM, g = c / BM otherwise, so that the lanes
+  // of a wave read adjacent memory; unit c of the B tile is column c % BN,
+  // chunk c / BN.  Units past the tile (c >= BM KC) are whole waves.
+  constexpr int KC = KT / 8;
+  constexpr int UA = kSplit ? (BM * KC + 255) / 256 : 1, UB = kSplit ? (BN * KC + 255) / 256 : 1;
+  float sa[kSplit ? NR : 1][UA][8], sb[kSplit ? NR : 1][UB][8];
   // Thread -> element maps of the operand tiles (element u of the thread):
   //   A k-contiguous: EA consecutive k of row am;
   //   A k-contiguous, KT not a multiple of EA (tiles of 48 rows, A_ROWS):
@@ -453,13 +493,17 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // ahead so that the operand loads never wait on the index loads.  A
   // wave's k rows are uniform (B_W map), so the indices are scalar loads.
   static_assert(!GATHER || B_W, "gathered B uses the 64-wide row map");
-  constexpr int NG = B_W ? EB : 1;   // k rows of B per thread
+  // Split modes: the 64 columns of a wave's B unit share chunk g = wave, so
+  // its 8 k rows are again uniform.
+  constexpr int NG = kSplit ? 8 : (B_W ? EB : 1);   // k rows of B per thread
+  static_assert(!GATHER || !kSplit || UB == 1, "gathered split B: one unit per thread");
   int grow[NG];
   const cst<int32_t>* gidx_c = as_const(d.gidx);
   auto fetch_rows = [&](int kt) {
 #pragma unroll
     for (int u = 0; u < NG; ++u) {
-      const int gk = __builtin_amdgcn_readfirstlane(kfirst + kt * KT + bk + u * ARW);
+      const int krow = kSplit ? 8 * wave + u : bk + u * ARW;
+      const int gk = __builtin_amdgcn_readfirstlane(kfirst + kt * KT + krow);
       grow[u] = gidx_c[gk < kend ? gk : kfirst];
     }
   };
@@ -470,11 +514,81 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   // no select after the load that could make the MFMAs of the current K
   // tile wait for the loads in flight.
   const gbl<const T>* zero = as_global(reinterpret_cast<const T*>(gemm_zero));
+  // Split modes: row (column) and chunk of each unit, and its operand offset
+  // at k = koff of segment 0.
+  int uam[UA], uag[UA], uac[UA], ubn[UB], ubg[UB], ubc[UB];   // uac, ubc: LDS chunk positions
+  int64_t uao[UA], ubo[UB];
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int p = 0; p < UA; ++p) {
+      const int c = tid + 256 * p;
+      const bool in = c < BM * KC;
+      uam[p] = !in ? 0 : A_KCONTIG ? c / KC : c % BM;
+      uag[p] = !in ? 0 : A_KCONTIG ? c % KC : c / BM;
+      uac[p] = split_chunk(uam[p], uag[p]);
+      uao[p] = int64_t(m0 + uam[p] + run.amoff) * sam + int64_t(kfirst + 8 * uag[p] + run.akoff) * sak;
+    }
+#pragma unroll
+    for (int p = 0; p < UB; ++p) {
+      const int c = tid + 256 * p;
+      const bool in = c < BN * KC;
+      ubn[p] = in ? c % BN : 0;
+      ubg[p] = in ? c / BN : 0;
+      ubc[p] = split_chunk(ubn[p], ubg[p]);
+      ubo[p] = int64_t(kfirst + 8 * ubg[p]) * ldb + (n0 + ubn[p]);
+    }
+  }
   int ld_step = 0;   // index of the next K tile to load; tiles past the last read as zero
   auto load = [&](int set) {
     const bool live = ld_step++ < nsteps;
     const int k0 = kfirst + kt_in_seg * KT;   // first k of this K tile
     const int64_t aoff = int64_t(seg_loaded) * sa_seg + int64_t(kt_in_seg) * KT * sak;
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int p = 0; p < UA; ++p) {
+        const bool row_ok = live && tid + 256 * p < BM * KC && m0 + uam[p] < M;
+        const int kc = k0 + 8 * uag[p];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = row_ok && kc + e < kend;
+          sa[set][p][e] = *(ok ? A0 + uao[p] + aoff + int64_t(e) * sak : zero);
+        }
+      }
+      const int64_t boffk = int64_t(seg_loaded) * sb_seg + int64_t(kt_in_seg) * KT * ldb;
+      if constexpr (GATHER) {
+        int64_t roff[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int64_t r = int64_t(grow[e]) * ldcu + boff;
+          const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(r));
+          const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(r) >> 32));
+          roff[e] = int64_t((uint64_t(hi) << 32) | lo);
+        }
+        const int gn = n0 + ubn[0], kc = k0 + 8 * ubg[0];
+        const bool col_ok = live & (gn < N) & (boff + gn < blim);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const bool ok = col_ok & (kc + e < kend);
+          sb[set][0][e] = *(ok ? cu + roff[e] + gn : zero);
+        }
+      } else {
+#pragma unroll
+        for (int p = 0; p < UB; ++p) {
+          const bool col_ok = live && tid + 256 * p < BN * KC && n0 + ubn[p] < N;
+          const int kc = k0 + 8 * ubg[p];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const bool ok = col_ok && kc + e < kend;
+            sb[set][p][e] = *(ok ? B0 + ubo[p] + boffk + int64_t(e) * ldb : zero);
+          }
+        }
+      }
+      if (++kt_in_seg == kpseg) {
+        kt_in_seg = 0;
+        ++seg_loaded;
+      }
+      if constexpr (GATHER) fetch_rows(kt_in_seg);
+    } else {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       int64_t off;
@@ -519,8 +633,29 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       ++seg_loaded;
     }
     if constexpr (GATHER) fetch_rows(kt_in_seg);
+    }
   };
   auto store = [&](int set, int buf) {
+    if constexpr (kSplit) {
+#pragma unroll
+      for (int p = 0; p < UA; ++p) {
+        if (tid + 256 * p >= BM * KC) continue;   // whole waves
+        if constexpr (MODE == kModeBF16x6)
+          split8x3(sa[set][p], sm.A[buf][0][uam[p]][uac[p]], sm.A[buf][1][uam[p]][uac[p]],
+                   sm.A[buf][2][uam[p]][uac[p]]);
+        else
+          split8(sa[set][p], sm.A[buf][0][uam[p]][uac[p]], sm.A[buf][1][uam[p]][uac[p]]);
+      }
+#pragma unroll
+      for (int p = 0; p < UB; ++p) {
+        if (tid + 256 * p >= BN * KC) continue;
+        if constexpr (MODE == kModeBF16x6)
+          split8x3(sb[set][p], sm.B[buf][0][ubn[p]][ubc[p]], sm.B[buf][1][ubn[p]][ubc[p]],
+                   sm.B[buf][2][ubn[p]][ubc[p]]);
+        else
+          split8(sb[set][p], sm.B[buf][0][ubn[p]][ubc[p]], sm.B[buf][1][ubn[p]][ubc[p]]);
+      }
+    } else {
     auto& Aw = sm.A[buf];
     auto& Bw = sm.B[buf];
 #pragma unroll
@@ -536,52 +671,37 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
       if (B_W) Bw[bk + u * ARW][bn] = rb[set][u];
       else Bw[bk][bn + u] = rb[set][u];
     }
+    }
   };
   auto compute = [&](int cur) {
-    auto& As = sm.A[cur];
-    auto& Bs = sm.B[cur];
-    if constexpr (MODE == kModeBF16x6) {
-      const int kb = 8 * (lane >> 4);
-      bf16x8 ah[TM], am_[TM], al[TM], bh[TN], bm[TN], bl[TN];
-      for (int i = 0; i < TM; ++i) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
-        split8x3(x, ah[i], am_[i], al[i]);
-      }
-      for (int j = 0; j < TN; ++j) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
-        split8x3(x, bh[j], bm[j], bl[j]);
-      }
+    if constexpr (kSplit) {
+      // one 16-byte LDS read per plane and fragment; planes 0, 1 (, 2) are
+      // hi, (mid,) lo
+      constexpr int NP = mode_planes(MODE);
+      const int fr = lane & 15, fg = lane >> 4;
+      bf16x8 a[NP][TM], b[NP][TN];
+      const int fc = split_chunk(fr, fg);   // rows wm + 16 i + fr: wm, 16 i are multiples of 16
+      for (int j = 0; j < TN; ++j)
+        for (int p = 0; p < NP; ++p) b[p][j] = sm.B[cur][p][wn + j * 16 + fr][fc];
+      for (int i = 0; i < TM; ++i)
+        for (int p = 0; p < NP; ++p) a[p][i] = sm.A[cur][p][wm + i * 16 + fr][fc];
       for (int i = 0; i < TM; ++i)
         for (int j = 0; j < TN; ++j) {   // smallest terms first
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am_[i], bm[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am_[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-        }
-    } else if constexpr (MODE == kModeBF16x3) {
-      const int kb = 8 * (lane >> 4);
-      bf16x8 ah[TM], al[TM], bh[TN], bl[TN];
-      for (int i = 0; i < TM; ++i) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = As[kb + e][wm + i * 16 + (lane & 15)];
-        split8(x, ah[i], al[i]);
-      }
-      for (int j = 0; j < TN; ++j) {
-        float x[8];
-        for (int e = 0; e < 8; ++e) x[e] = Bs[kb + e][wn + j * 16 + (lane & 15)];
-        split8(x, bh[j], bl[j]);
-      }
-      for (int i = 0; i < TM; ++i)
-        for (int j = 0; j < TN; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          if constexpr (MODE == kModeBF16x6) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          } else {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], acc[i][j], 0, 0, 0);
+          }
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], acc[i][j], 0, 0, 0);
         }
     } else {
+      auto& As = sm.A[cur];
+      auto& Bs = sm.B[cur];
 #pragma unroll
       for (int kk = 0; kk < KT; kk += 4) {
         const int kr = kk + (lane >> 4);
@@ -729,8 +849,8 @@ __device__ __forceinline__ void gemm_grouped(const GemmDesc* __restrict__ descs,
 // tiles), in l2pt the deeper loads cost more in L2 misses (the tiles of one
 // leaf drift apart) than they gain in latency, and the whole-leaf tiles
 // would drop to 2 waves per SIMD.
-OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48, 2, 1)
-OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
+OCCK_GEMM_KERNEL(half_kernel, true, true, typename ModeT<MODE>::T, GemmRows48, (MODE == kModeBF16x6 ? 1 : 2), 1)
+OCCK_GEMM_KERNEL(omega_kernel, false, true, typename ModeT<MODE>::T, GemmSquare, (MODE == kModeBF16x6 ? 1 : 2), 1)
 OCCK_GEMM_KERNEL(l2p_kernel, true, false, double, GemmRows48, 2, 2)
 OCCK_GEMM_KERNEL(l2pt_kernel, true, false, double, GemmCols48, 2, 1)
 OCCK_GEMM_KERNEL(l2pt_wide_kernel, true, false, double, GemmCols144, 2, 1)
@@ -739,7 +859,7 @@ OCCK_GEMM_KERNEL(l2p_wide_kernel, true, false, double, GemmRows144, 2, 1)
 // (formed once per call for every column) instead of forming it per batch:
 // A is HT^B_q[i][t] (t contiguous), Omega per (leaf, q) with rows j, and the
 // direct L2P over K segments q with k = j.
-OCCK_GEMM_KERNEL(omega_ht_kernel, true, true, typename ModeT<MODE>::T, GemmSquare, 2, 1)
+OCCK_GEMM_KERNEL(omega_ht_kernel, true, true, typename ModeT<MODE>::T, GemmSquare, (MODE == kModeBF16x6 ? 1 : 2), 1)
 OCCK_GEMM_KERNEL(l2p_ht_kernel, false, false, double, GemmRows48, 2, 2)
 OCCK_GEMM_KERNEL(l2p_ht_wide_kernel, false, false, double, GemmRows144, 2, 1)
 #undef OCCK_GEMM_KERNEL

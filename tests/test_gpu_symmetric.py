@@ -98,10 +98,12 @@ def test_symmetric_K_ij_is_symmetric(torch_cuda, water75):
     assert np.abs(Kij - Kij.T).max() <= 1e-10 * np.abs(Kij).max()
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6), (3, 1e-6), (2, 5e-5)],
+                         ids=["fp64", "fp32", "bf16x6", "bf16x3"])
 def test_symmetric_whole_leaf_mirrored_tiles(torch_cuda, prec, tol):
     """Alkane chain whose leaves hold at most 144 functions (mean 131): the
-    mirrored L2P runs in 64 x 144 tiles, one per leaf, with ragged leaves."""
+    direct and mirrored L2P run in 144 x 64 and 64 x 144 tiles, one per leaf,
+    with ragged leaves, in every precision."""
     wl = workloads.alkane_chain(n_carbon=100, depth=6)
     C = wl.orbitals()
     ref = oracle_far_K(Setup(wl.system, wl.params), C)
