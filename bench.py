@@ -701,7 +701,7 @@ def _classify_last_call(names, info):
             kind[i] = "half" if seen_half else "ht"
             seen_half = True
             continue
-        for key, c in (("opgen", "opgen"), ("reduce", "reduce"), ("omega_kernel", "omega"), ("omega_ht_kernel", "omega"),
+        for key, c in (("opgen", "opgen"), ("to_float", "convert"), ("reduce", "reduce"), ("omega_kernel", "omega"), ("omega_ht_kernel", "omega"),
                        ("l2pt_kernel", "l2p_mirror"), ("l2pt_wide_kernel", "l2p_mirror"),
                        ("l2p_kernel", "l2p_direct"), ("l2p_wide_kernel", "l2p_direct"),
                        ("l2p_ht_kernel", "l2p_direct"), ("l2p_ht_wide_kernel", "l2p_direct")):
@@ -805,10 +805,10 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, copy_mib, 
 
 SQ_COUNTERS = ["SQ_WAVE_CYCLES", "SQ_BUSY_CU_CYCLES", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY",
                "SQ_WAIT_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_VALU_MFMA_MOPS_F64",
-               "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VALU", "SQ_INSTS_SALU"]
+               "SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VALU", "SQ_INSTS_SALU"]
 
 
-def sq_summary(dirs, cmds):
+def sq_summary(dirs, cmds, precision="fp64"):
     """Per-kernel MFMA, wait-state and LDS counters of the last occk_far_K
     call recorded by rocprofv3 --pmc runs of 'bench.py --steps 1 --warmup 0
     --one-stream' (summed over the call's dispatches of each kernel class);
@@ -831,7 +831,8 @@ def sq_summary(dirs, cmds):
         t = tot.setdefault(cls, {c: 0.0 for c in SQ_COUNTERS})
         for c in SQ_COUNTERS:
             t[c] += per.get(c, {}).get(i, 0.0)
-    print("# MFMA, wait-state and LDS counters per kernel: alkane chain, L = 2, FP64 (one occk_far_K call, one stream)\n")
+    print(f"# MFMA, wait-state and LDS counters per kernel: alkane chain, L = 2, {precision.upper()} (one occk_far_K call, "
+          "one stream)\n")
     print("Commands (repository root, one MI355X, `export TMPDIR=/tmp`; two passes of at most 8 SQ counters):\n\n```")
     for c in cmds:
         print(c)
@@ -840,8 +841,8 @@ def sq_summary(dirs, cmds):
           "(4 SQ_BUSY_CU_CYCLES) (the MFMA counter summed over the 4 SIMDs of a CU); waits are fractions of "
           "SQ_WAVE_CYCLES; LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.\n")
     print("| kernel | MFMA busy | wait on dependencies (WAIT_INST_ANY) | wait any | LDS wait | LDS conflict | "
-          "VALU instr | SALU instr | VMEM reads | LDS instr | F64 MFMA ops |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|")
+          "VALU instr | SALU instr | VMEM reads | LDS instr | F64 MFMA ops | BF16 MFMA ops |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|")
     for cls in KERNELS:
         if cls not in tot:
             continue
@@ -851,7 +852,8 @@ def sq_summary(dirs, cmds):
         conf = t["SQ_LDS_BANK_CONFLICT"] / max(t["SQ_LDS_IDX_ACTIVE"], 1.0)
         print(f"| {cls} | {busy:.2f} | {t['SQ_WAIT_INST_ANY'] / wc:.2f} | {t['SQ_WAIT_ANY'] / wc:.2f} | "
               f"{t['SQ_WAIT_INST_LDS'] / wc:.3f} | {conf:.3f} | {t['SQ_INSTS_VALU']:.3g} | {t['SQ_INSTS_SALU']:.3g} | "
-              f"{t['SQ_INSTS_VMEM_RD']:.3g} | {t['SQ_INSTS_LDS']:.3g} | {t['SQ_INSTS_VALU_MFMA_MOPS_F64']:.3g} |")
+              f"{t['SQ_INSTS_VMEM_RD']:.3g} | {t['SQ_INSTS_LDS']:.3g} | {t['SQ_INSTS_VALU_MFMA_MOPS_F64']:.3g} | "
+              f"{t['SQ_INSTS_VALU_MFMA_MOPS_BF16']:.3g} |")
 
 
 def main():
@@ -897,7 +899,7 @@ def main():
         trace_summary(args.trace_summary)
         return
     if args.sq_summary:
-        sq_summary(args.sq_summary, args.pmc_commands)
+        sq_summary(args.sq_summary, args.pmc_commands, args.precision)
         return
     if args.workload == "batch16":
         bench_batch(args)
