@@ -240,9 +240,10 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
   }
 }
 
-// FP64 / FP32: at most 128 VGPRs (4 waves per SIMD), which the union of all
-// task paths fits without spills; the split-BF16 modes need more and keep the
-// compiler's own allocation.
+// FP64 / FP32 with one translation row tile (L <= 3): at most 128 VGPRs (4
+// waves per SIMD), which the union of all task paths fits without spills.
+// More row tiles (L >= 4), and the split-BF16 modes, keep the compiler's own
+// allocation, which is free of spills up to L = 8.
 template <int MODE, int MT, int QV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void batch_kernel_w4(
     const BTask* __restrict__ tasks, const int32_t* __restrict__ stage_ptr, int nstage, const BSys* __restrict__ sys,
@@ -404,7 +405,7 @@ static void prepare(BatchPlan& bp, hipStream_t st) {
 
 template <int MODE, int MT, int QV>
 static const void* kernel_of() {
-  if constexpr (MODE == kModeF64 || MODE == kModeF32)
+  if constexpr ((MODE == kModeF64 || MODE == kModeF32) && MT == 1)
     return reinterpret_cast<const void*>(batch_kernel_w4<MODE, MT, QV>);
   else
     return reinterpret_cast<const void*>(batch_kernel<MODE, MT, QV>);
@@ -448,7 +449,7 @@ static void check_kernel(BatchPlan& bp) {
   HIP_OK(hipFuncGetAttributes(&fa, kern));
   if (fa.localSizeBytes > 0)
     throw std::invalid_argument("batch: the persistent kernel for this lmax and precision spills registers; "
-                                "batched launches need a spill-free kernel (lmax <= 2 in every precision)");
+                                "batched launches need a spill-free kernel");
   int per_cu = 0;
   HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0));
   if (per_cu < 1) throw HipError("batch kernel cannot be resident");

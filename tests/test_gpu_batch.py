@@ -139,21 +139,46 @@ def test_plan_survives_standalone_call(systems):
     b.free()
 
 
-def test_spilling_persistent_kernel_is_refused():
-    """lmax = 4 needs a persistent kernel that spills registers; the plan is
-    refused at creation (before any launch) with an error."""
+@pytest.mark.parametrize("L,prec", [(4, 0), (4, 3), (6, 1), (6, 2), (8, 0), (8, 3)],
+                         ids=["L4-fp64", "L4-bf16x6", "L6-fp32", "L6-bf16x3", "L8-fp64", "L8-bf16x6"])
+def test_batched_high_rank_equals_standalone(L, prec):
+    """lmax 4..8 (2..6 MFMA row tiles): the persistent kernels are free of
+    register spills (the split-BF16 GEMM tiles hold fragments, not FP32
+    copies, and FP64/FP32 keep the compiler's allocation above one row
+    tile), so batched plans are accepted at every rank the exchange kernels
+    take.  Two uneven water clusters, several j batches; each system's K
+    matches the standalone occk_far_K of the same precision, which the other
+    tests pin on the oracle (FP64 to 1e-12, mixed modes to twice their
+    bound)."""
     import torch
     from paper_1708_05353_amd import occk
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    wl = workloads.water_cluster(6, 40, lmax=4, depth=3)
-    tr = occk.Tree(wl.system, wl.params)
-    with pytest.raises(occk.OcckError, match="spill"):
-        occk.Batch([tr], [wl.system.nocc], occk.PREC_FP64)
-    tr.free()
+    sysl = [workloads.water_cluster(n, s, lmax=L, depth=3) for n, s in [(6, 40), (9, 41)]]
+    trees = [occk.Tree(wl.system, wl.params) for wl in sysl]
+    Cs = [torch.from_numpy(wl.orbitals()).cuda() for wl in sysl]
+    Ks = [torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda") for wl, C in zip(sysl, Cs)]
+    b = occk.Batch(trees, [C.shape[1] for C in Cs], prec, jblock=16)
+    print(f"[batch] L{L} prec {prec}", flush=True)
+    b.run(Cs, Ks)
+    torch.cuda.synchronize()
+    b.free()
+    tol = 1e-12 if prec == 0 else 2 * {1: 1e-6, 2: 5e-5, 3: 1e-6}[prec]
+    for tr, C, K in zip(trees, Cs, Ks):
+        K1 = torch.zeros_like(K)
+        occk.far_K(tr, C, K1, precision=prec, jblock=16)
+        torch.cuda.synchronize()
+        assert rel(K.cpu().numpy(), K1.cpu().numpy()) <= tol
+    if L == 4 and prec == 0:   # and the oracle itself at the smallest of these ranks
+        wl = sysl[0]
+        ref = oracle_far_K(Setup(wl.system, wl.params), Cs[0].cpu().numpy())
+        assert rel(Ks[0].cpu().numpy(), ref) <= 1e-8
+    for t in trees:
+        t.free()
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6)], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("prec,tol", [(0, 1e-8), (1, 1e-6), (3, 1e-6), (2, 5e-5)],
+                         ids=["fp64", "fp32", "bf16x6", "bf16x3"])
 def test_batched_L3_mfma_translations(prec, tol):
     """lmax = 3 (Q = 16): the persistent kernel's MFMA translation tiles with
     the operator staged in its shared memory; three uneven systems, two j
