@@ -368,7 +368,8 @@ int32_t occk_workspace_info(occk_tree* tree, int32_t* jblock, int64_t* bytes);
  * included, the symmetric schedule over j batches) become tasks grouped by
  * stage; the blocks share the tasks of a stage and meet at a grid barrier
  * between stages.  trees: live handles with a far field and a common lmax;
- * the plan keeps pointers to them (free the plan first).  nocc[k]: occupied
+ * the plan keeps pointers to them (free the plan first); lmax up to 8, as for
+ * occk_far_K.  nocc[k]: occupied
  * count of system k.  opts: precision (any OCCK_PREC_*); rank_mode must be
  * FIXED; jblock: j batch width of every system (0: chosen per system as in
  * occk_far_K; capped at nocc); accumulate is ignored (K is overwritten).
