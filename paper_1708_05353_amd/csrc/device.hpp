@@ -259,7 +259,8 @@ void upload_tree(Tree* t);
 enum { kWsPlain = 0, kWsSym = 1, kWsSymHT = 2 };
 void setup_workspace(Tree* t, int jb, int ni, int prec, int sym_mode = kWsPlain, ScratchArena* arena = nullptr);
 // largest j batch width (<= 256) whose workspace fits min(cap/2, 32 GiB)
-int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym);
+int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym, int jmax = 256);
+bool walk_tree(const Tree* t);   // both tree walks apply (chain-like trees, Q <= 9)
 void ensure_mixed_operands(Tree* t, hipStream_t st);
 void launch_to_float(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
                      hipStream_t st);

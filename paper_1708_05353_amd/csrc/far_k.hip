@@ -44,6 +44,28 @@ static void free_state(DeviceState* ds);
 
 static void upload_tree_into(Tree* t, DeviceState* ds);
 
+
+// The walks pay off where a block's subtree is a long chain of cheap steps
+// (binary splits, short interaction lists: the chain-like trees); on 2-D
+// and 3-D trees, with up to 8 children and tens of interaction-list
+// sources per box, the level-by-level passes keep more waves busy and are
+// faster.  Both walks are used when the boxes above the leaves have at
+// most 2 children on average and the interaction lists at most 8 sources.
+bool walk_tree(const Tree* t) {
+  const int lmin = t->lmin, D = t->params.depth;
+  if (lmin < 0) return false;
+  int64_t n_above = 0, n_kids = 0, n_tgt = 0, n_src = 0;
+  for (int lev = lmin; lev < D; ++lev) {
+    n_above += int64_t(t->boxes[lev].size());
+    n_kids += int64_t(t->boxes[lev + 1].size());
+  }
+  for (int lev = lmin; lev <= D; ++lev) {
+    n_tgt += int64_t(t->boxes[lev].size());
+    n_src += int64_t(t->il_idx[lev].size());
+  }
+  return t->Q <= 9 && n_kids <= 2 * n_above && n_src <= 8 * n_tgt;
+}
+
 void upload_tree(Tree* t) {
   if (t->lmin < 0) throw std::invalid_argument("upload_tree: the tree has no far field");
   DeviceState* ds = new DeviceState();
@@ -271,22 +293,7 @@ static void upload_tree_into(Tree* t, DeviceState* ds) {
       kids[size_t(lev)][size_t(t->parent(lev + 1, c))].push_back({c, t->op_up[(lev + 1) * 8 + oct]});
     }
   }
-  // The walks pay off where a block's subtree is a long chain of cheap steps
-  // (binary splits, short interaction lists: the chain-like trees); on 2-D
-  // and 3-D trees, with up to 8 children and tens of interaction-list
-  // sources per box, the level-by-level passes keep more waves busy and are
-  // faster.  Both walks are used when the boxes above the leaves have at
-  // most 2 children on average and the interaction lists at most 8 sources.
-  int64_t n_above = 0, n_kids = 0, n_tgt = 0, n_src = 0;
-  for (int lev = lmin; lev < D; ++lev) {
-    n_above += int64_t(t->boxes[lev].size());
-    n_kids += int64_t(t->boxes[lev + 1].size());
-  }
-  for (int lev = lmin; lev <= D; ++lev) {
-    n_tgt += int64_t(t->boxes[lev].size());
-    n_src += int64_t(t->il_idx[lev].size());
-  }
-  const bool walks = Q <= 9 && n_kids <= 2 * n_above && n_src <= 8 * n_tgt;
+  const bool walks = walk_tree(t);
   // the upward walk: post-order program of every subtree below a box of
   // level lr = max(lmin, D - kUpWalkLevels); the levels above lr keep their
   // level-by-level passes, which read the walk's level-lr multipoles
@@ -905,7 +912,7 @@ static void free_state(DeviceState* ds) {
   delete ds;
 }
 
-int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
+int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym, int jmax) {
   const size_t cap = device_cap();
   const int Q = t->Q;
   int64_t sum_nb = 0;
@@ -913,7 +920,7 @@ int auto_jblock(const Tree* t, int nj, int ni, size_t es, bool sym) {
   int64_t nbox = 0;
   for (int lev = t->lmin; lev <= t->params.depth; ++lev) nbox += int64_t(t->boxes[lev].size());
   const size_t budget = std::min(cap / 2, size_t(32) << 30);
-  int jb = std::min(nj, 256);
+  int jb = std::min(nj, jmax);
   while (jb > 1) {
     if (workspace_need(sum_nb, Q, nbox, jb, ni, es, sym) <= budget) break;
     jb = (jb + 1) / 2;
@@ -1378,7 +1385,15 @@ int32_t far_K(Tree* t, const double* C, int64_t ldc, int32_t nocc, int32_t i0, i
     }
     const size_t es = mixed ? 4 : 8;
     const bool sym = i0 == j0 && i1 == j1;   // symmetric schedule when the i and j ranges coincide
-    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj) : auto_jblock(t, nj, ni, es, sym);
+    // Automatic j batches of at most 256, or 128 where the FP64 call runs the
+    // two-stream schedule (symmetric, fixed rank, both walks): twice the
+    // batches give the two streams more to overlap (alkane chain at L = 2:
+    // 91.6 against 94.0 ms per call; FP32 is slower with 128 and split-BF16
+    // the same, and one stream gains nothing).
+    const bool pipe_fp64 = !mixed && sym && !sel && opts->one_stream == 0 && opts->pair_thresh <= 0.0 &&
+                           opts->lds_tree != 1 && walk_tree(t);
+    const int jb = opts->jblock > 0 ? std::min<int>(opts->jblock, nj)
+                                    : auto_jblock(t, nj, ni, es, sym, pipe_fp64 ? 128 : 256);
     {
       // host-side check before any HIP call: leaf multipole blocks and the
       // workspace of this batch width must fit under the device-byte cap

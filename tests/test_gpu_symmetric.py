@@ -143,3 +143,30 @@ def test_two_streams_equal_one_stream(torch_cuda, prec):
     ref = oracle_far_K(Setup(wl.system, wl.params), C)
     assert rel(K2, ref) <= (1e-8 if prec == "fp64" else 1e-6)
     tr.free()
+
+
+def test_automatic_batch_width_follows_the_schedule(torch_cuda):
+    """Automatic j batches: at most 128 wide where the FP64 call runs the
+    two-stream schedule (chain-like tree, symmetric, fixed rank), at most 256
+    in one stream and in the mixed modes; the results agree with the oracle
+    either way."""
+    from paper_1708_05353_amd import occk
+    torch = torch_cuda
+    wl = workloads.alkane_chain(n_carbon=40, depth=5)
+    C = wl.orbitals()
+    n = C.shape[1]
+    assert n > 128
+    tr = occk.Tree(wl.system, wl.params)
+    Cd = torch.from_numpy(C).cuda()
+    ref = oracle_far_K(Setup(wl.system, wl.params), C)
+    print(f"[sym] automatic j batch width, n = {n}", flush=True)
+    K2 = _run(torch, tr, Cd, n, jblock=0, precision=occk.PREC_FP64)
+    assert tr.workspace_jblock() == 128
+    assert rel(K2, ref) <= 1e-8
+    K1 = _run(torch, tr, Cd, n, jblock=0, precision=occk.PREC_FP64, one_stream=True)
+    assert tr.workspace_jblock() == min(n, 256)
+    assert rel(K1, ref) <= 1e-8
+    Kf = _run(torch, tr, Cd, n, jblock=0, precision=occk.PREC_FP32)
+    assert tr.workspace_jblock() == min(n, 256)
+    assert rel(Kf, ref) <= 1e-6
+    tr.free()
