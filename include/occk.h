@@ -138,7 +138,10 @@ typedef struct occk_far_opts {
   int32_t precision;           /* OCCK_PREC_*                                  */
   int32_t rank_mode;           /* OCCK_RANK_*; LEARNED needs a live selector  */
   const occk_selector* selector;
-  int32_t jblock;              /* occupied j columns per batch, 0 = automatic */
+  int32_t jblock;              /* occupied j columns per batch, 0 = automatic:
+                                  the widest batch (<= 256; <= 128 where an FP64
+                                  call runs the two-stream schedule) whose
+                                  workspace fits the device-byte cap          */
   int32_t accumulate;          /* 0: K[:, i0:i1] = K^ff, 1: K[:, i0:i1] += K^ff */
   double pair_thresh;          /* occupied-pair screening for localised orbitals
                                   (Conclusion: localised orbitals and screening of
