@@ -240,12 +240,22 @@ __device__ __forceinline__ void batch_body(const BTask* __restrict__ tasks, cons
   }
 }
 
-// FP64 / FP32 with one translation row tile (L <= 3): at most 128 VGPRs (4
-// waves per SIMD), which the union of all task paths fits without spills.
-// More row tiles (L >= 4), and the split-BF16 modes, keep the compiler's own
-// allocation, which is free of spills up to L = 8.
+// One translation row tile (L <= 3): FP64 / FP32 at most 128 VGPRs (4 waves
+// per SIMD), the split-BF16 modes at most 168 (3 waves per SIMD; their GEMM
+// tiles hold bf16 fragments of three planes), which the union of all task
+// paths fits without spills.  More row tiles (L >= 4) keep the compiler's
+// own allocation, which is free of spills up to L = 8.
 template <int MODE, int MT, int QV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void batch_kernel_w4(
+    const BTask* __restrict__ tasks, const int32_t* __restrict__ stage_ptr, int nstage, const BSys* __restrict__ sys,
+    const BPass* __restrict__ passes, int gemm_group, int trans_group, uint64_t* __restrict__ stage_clk,
+    int* __restrict__ claim) {
+  __shared__ BatchSmem<MODE> sm;
+  batch_body<MODE, MT, QV>(tasks, stage_ptr, nstage, sys, passes, gemm_group, trans_group, stage_clk, claim, sm);
+}
+
+template <int MODE, int MT, int QV>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void batch_kernel_w3(
     const BTask* __restrict__ tasks, const int32_t* __restrict__ stage_ptr, int nstage, const BSys* __restrict__ sys,
     const BPass* __restrict__ passes, int gemm_group, int trans_group, uint64_t* __restrict__ stage_clk,
     int* __restrict__ claim) {
@@ -407,6 +417,8 @@ template <int MODE, int MT, int QV>
 static const void* kernel_of() {
   if constexpr ((MODE == kModeF64 || MODE == kModeF32) && MT == 1)
     return reinterpret_cast<const void*>(batch_kernel_w4<MODE, MT, QV>);
+  else if constexpr (MT == 1)
+    return reinterpret_cast<const void*>(batch_kernel_w3<MODE, MT, QV>);
   else
     return reinterpret_cast<const void*>(batch_kernel<MODE, MT, QV>);
 }
