@@ -606,17 +606,21 @@ def copy_rate(mb: int = 2048, reps: int = 10) -> dict:
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "alkane_L2_fp64_hbm_traffic.md")
 
 
+# the sources of the far-field K call (its kernels, their launches, the tree
+# and the ABI layer); the batch, selector, Coulomb and near-field sources
+# build other entry points
+FAR_K_SOURCES = ("abi.cpp", "device.hpp", "far_k.hip", "kernels.hpp", "occk_internal.hpp", "tree_build.cpp")
+
+
 def kernel_source_digest() -> str:
-    """sha256 over the library's device and host sources: counters taken
-    with other sources do not describe the current kernels."""
-    import glob
+    """sha256 over the sources of the far-field K call: counters taken with
+    other sources do not describe the current kernels."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1708_05353_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for name in FAR_K_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(ROOT, "paper_1708_05353_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
