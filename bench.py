@@ -407,7 +407,8 @@ def bench_batch(args):
 def bench_protein(args):
     """Learned ranks on the protein-shaped globule (644 sites, nbasis 6187,
     nocc 1261, 3-D depth 3, ws 2, L = 8), j sample [0, J) of all i: the plain
-    fixed-rank FP64 path (the judge) against the learned-rank path.
+    fixed-rank FP64 path (the judge) against the learned-rank path, and the
+    learned ranks with the split-BF16x6 contractions.
 
     The selector is trained on method-generated targets of two smaller
     training globules (seeds 1000, 1001) and its threshold calibrated on them
@@ -486,6 +487,13 @@ def bench_protein(args):
     hist = tree.rank_stats()
     work = float(sum(hist[p] * (p + 1) ** 4 for p in range(9)) / (hist.sum() * 9 ** 4))
     err = rel(Kl, Kf)
+    # the learned ranks with the split-BF16x6 contractions (FP32
+    # translations): the mixed and learned forms together, against the same
+    # fixed-rank FP64 result
+    Km = torch.zeros_like(Kf)
+    both = lambda: occk.far_K(tree, Cd, Km, j_range=(0, jn), selector=sel, precision=occk.PREC_BF16X6)
+    t_both = timeit(both)
+    err_both = rel(Km, Kf)
     fl = tree.flops(n, jn)["total"]
     out = {
         "metric": "far-field K_ri GFLOP/s (protein L=8, fixed rank; learned-rank path beside it)",
@@ -499,6 +507,8 @@ def bench_protein(args):
                     "rel_err_vs_fixed_L8": err, "m2l_work_fraction": round(work, 4),
                     "rank_histogram": [int(x) for x in hist], "log10_tau": chosen,
                     "train_and_calibrate_s": round(t_train, 1)},
+        "learned_bf16x6": {"ms_per_step": round(t_both, 3), "speedup_vs_fixed": round(t_fixed / t_both, 3),
+                           "rel_err_vs_fixed_L8": err_both, "bound": 1e-6, "within_bound": err_both <= 1e-6},
     }
     print(json.dumps(out), flush=True)
 

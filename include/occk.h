@@ -50,7 +50,10 @@ enum {
  *           Outside the 1e-6 target of the mixed path: its bound is 5e-5
  *           (normwise errors of 4e-6 to 9e-6 on the test systems)
  *   BF16X6  three-way split, six products (~2^-24 per product); translations
- *           on FP32 MFMA */
+ *           on FP32 MFMA
+ * The FP32 translations at L >= 3 accumulate a box's interaction list in FP32:
+ * on large 3-D trees at high rank (a 6187-function globule at L = 8) FP32 and
+ * BF16X6 reach ~5e-6 against FP64 instead of 1e-6. */
 enum { OCCK_PREC_FP64 = 0, OCCK_PREC_FP32 = 1, OCCK_PREC_BF16X3 = 2, OCCK_PREC_BF16X6 = 3 };
 enum { OCCK_RANK_FIXED = 0, OCCK_RANK_LEARNED = 1 };
 

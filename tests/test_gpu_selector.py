@@ -141,6 +141,38 @@ def test_ranked_translation_matches_oracle(occk, tiny, case, L, p):
     sel.free()
 
 
+@pytest.mark.parametrize("case,L,p,prec", [("chain", 4, 2, "fp32"), ("sheet", 3, 2, "bf16x6"),
+                                            ("water", 4, 3, "bf16x6"), ("water", 6, 4, "fp32")])
+def test_ranked_translation_mixed_precision(occk, tiny, case, L, p, prec):
+    """The ranked M2L with the mixed modes: FP32 translations (the ranks
+    truncate the operator rows and columns as in FP64), split-BF16 or FP32
+    contractions; K within the mixed path's 1e-6 of the oracle's
+    rank-truncated FMM."""
+    import torch
+    if case == "chain":
+        wl, C, _ = tiny
+        params = with_params(wl, lmax=L)
+    elif case == "sheet":
+        wl = workloads.graphene_flake(n=2, lmax=L, nocc=12, depth=3)
+        C, params = wl.orbitals(), wl.params
+    else:
+        wl = workloads.water_cluster(12, 42, lmax=L)
+        C, params = wl.orbitals(), wl.params
+    ref = oracle_far_K(Setup(wl.system, params), C, m2l_rank=p)
+    sel = _constant_rank_selector(occk, p)
+    tr = occk.Tree(wl.system, params)
+    code = {"fp32": occk.PREC_FP32, "bf16x6": occk.PREC_BF16X6}[prec]
+    K = torch.zeros((wl.system.nbasis, C.shape[1]), dtype=torch.float64, device="cuda")
+    print(f"[selector] ranked {case} L{L} p{p} {prec}", flush=True)
+    occk.far_K(tr, torch.from_numpy(C).cuda(), K, selector=sel, jblock=5, precision=code)
+    torch.cuda.synchronize()
+    hist = tr.rank_stats()
+    assert hist.sum() > 0 and hist[p] == hist.sum()
+    assert rel(K.cpu().numpy(), ref) <= 1e-6
+    tr.free()
+    sel.free()
+
+
 def test_collect_targets(occk):
     import torch
     wl = workloads.water_cluster(15, 43, lmax=6)
