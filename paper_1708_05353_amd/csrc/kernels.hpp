@@ -285,7 +285,6 @@ static __global__ __launch_bounds__(64) void opgen_perm_kernel(const OpParam* __
 enum { kModeF64 = 0, kModeF32 = 1, kModeBF16x3 = 2, kModeBF16x6 = 3 };
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s8v __attribute__((ext_vector_type(8)));
 
 template <int MODE> struct ModeT;
 template <> struct ModeT<kModeF64> { using T = double; using Acc = d4; static constexpr int KT = 16; };
