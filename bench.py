@@ -293,6 +293,14 @@ def bench_near(wl, Cd, args, stream):
             "first_call_s": round(t_first, 2)}
 
 
+def best_mixed_mode(mixed: dict, budget: float = 1e-6) -> str:
+    """The headline mixed mode: the fastest one whose stated bound is within
+    the mixed path's budget and whose measured error meets it (BF16x3, held
+    to 5e-5, never qualifies); FP32 when none does."""
+    ok = [m for m, r in mixed.items() if r["bound"] <= budget and r["rel_err_vs_fp64"] <= r["bound"]]
+    return min(ok, key=lambda m: mixed[m]["ms_per_step"]) if ok else "fp32"
+
+
 def cpu_model() -> str:
     """CPU model name of the host (lscpu, else /proc/cpuinfo)."""
     import subprocess
@@ -1117,9 +1125,7 @@ def main():
                             "speedup_vs_fp64": round(ms / ms_m, 3), "rel_err_vs_fp64": err, "bound": bound}
             print(f"[bench] mixed {mname} {ms_m:.2f} ms/step, x{ms / ms_m:.2f}, rel err {err:.2e}",
                   file=sys.stderr, flush=True)
-        # the headline mixed figure: the fastest mode within the 1e-6 budget
-        ok = [m for m, _, b in modes if b <= 1e-6 and mixed[m]["rel_err_vs_fp64"] <= b]
-        best = min(ok, key=lambda m: mixed[m]["ms_per_step"]) if ok else "fp32"
+        best = best_mixed_mode(mixed)
         out["mixed"] = dict(precision=best, **mixed[best], modes=mixed)
     if args.precision == "fp64" and not args.no_near:
         out["near_K"] = bench_near(wl, Cd, args, stream)

@@ -99,3 +99,16 @@ def test_kernel_costs_add_up_to_the_class_costs(il):
         assert add(a, b, 1) == c[cl][1], cl
     assert k["omega"] == c["omega"]
     assert k["ht"][0] == k["half"][0] == c["half"][0]
+
+
+def test_best_mixed_mode():
+    """The headline mixed mode is the fastest within the 1e-6 budget."""
+    import bench
+    m = {"fp32": {"ms_per_step": 55.0, "rel_err_vs_fp64": 1.9e-7, "bound": 1e-6},
+         "bf16x6": {"ms_per_step": 52.0, "rel_err_vs_fp64": 1.6e-7, "bound": 1e-6},
+         "bf16x3": {"ms_per_step": 47.0, "rel_err_vs_fp64": 7.8e-6, "bound": 5e-5}}
+    assert bench.best_mixed_mode(m) == "bf16x6"            # BF16x3 is faster but outside the budget
+    m["bf16x6"]["rel_err_vs_fp64"] = 2e-6                   # over its bound: not chosen
+    assert bench.best_mixed_mode(m) == "fp32"
+    m["fp32"]["rel_err_vs_fp64"] = 3e-6
+    assert bench.best_mixed_mode(m) == "fp32"               # none qualifies: FP32 is reported
