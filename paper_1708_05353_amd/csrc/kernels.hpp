@@ -428,9 +428,10 @@ __device__ void gemm_tile(const GemmDesc& d, int mt, int nt, const typename Mode
   for (int i = 0; i < TM; ++i)
     for (int j = 0; j < TN; ++j) acc[i][j] = Acc{};
   // FP32 accumulators feeding an FP64 output are flushed into FP64 registers
-  // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT terms.
+  // every FLUSH K tiles, so FP32 rounding accumulates over at most FLUSH*KT =
+  // 128 terms in every mixed mode.
   constexpr bool kFlush = std::is_same<OutT, double>::value && MODE != kModeF64;
-  constexpr int FLUSH = 8;
+  constexpr int FLUSH = 128 / KT;
   double acc64[kFlush ? TM : 1][kFlush ? TN : 1][kFlush ? 4 : 1];
   if constexpr (kFlush)
     for (int i = 0; i < TM; ++i)
